@@ -1,0 +1,301 @@
+/*
+ * rt.h -- C ABI of the MI355X formal-solution library.
+ *
+ * The library computes the formal solution of the radiative transfer
+ * equation (Osborne 2025, Eqs. Rte/RteRay/RteIntegral) along long
+ * characteristics through a sparse brick grid of emissivity eta and opacity
+ * chi, with variance-limited mipmapping (VLM, Sect. 2.2), hierarchical DDA
+ * traversal (HDDA, Sect. 2.3 and Alg. 1) and, for moving media, velocity
+ * interpolation (Sect. 3.1) or "Core and Voigt" (Sect. 3.2).  Each segment
+ * applies the piecewise-constant update I <- I exp(-tau) + S (1 - exp(-tau)),
+ * tau = chi dt ds0, S = eta / chi (accumulated front-to-back on the device,
+ * which equals the recurrence up to rounding).
+ *
+ * Conventions (all calls):
+ *   - Index space: a MIP-0 voxel has side 1; physical length = index length
+ *     x ds0.  Voxel (i,j,k) covers [i,i+1)x[j,j+1)x[k,k+1); voxel linear
+ *     index = i + nx*(j + ny*k).  2D scenes use n[2] = 1.
+ *   - A ray is x(t) = p - t w, t in [0, t_exit], from the probe p (a voxel
+ *     centre) upwind to the bounding box, where the boundary intensity I0
+ *     enters (Sect. 2.3, Eq. Ray: rays are clipped to the bounding box).  The
+ *     result is the intensity arriving at p travelling along w.
+ *   - Blocks ("bricks", Sect. 2.3) are B^D voxels, B a power of two; block
+ *     linear index = bx + nbx*(by + nby*bz).  Active blocks are stored in
+ *     Morton order (Sect. 2.3.1).
+ *   - "Probes" of the all-probes mode are the voxel centres of the active
+ *     blocks, numbered slot*B^D + local, local = x + B*(y + B*z) inside the
+ *     block, slot = rank of the block in Morton order among active blocks.
+ *   - Pointers named d_* are device pointers (HIP device memory) owned by
+ *     the caller; pointers named h_* are host pointers.  `stream` is a
+ *     hipStream_t passed as void*.  Every device-side call is asynchronous on
+ *     that stream unless documented as synchronising.
+ *   - Errors: every call returns rt_status; no C++ exception crosses the
+ *     ABI; rt_last_error() gives a thread-local message for the last failure.
+ *     Arguments are validated on the host before any device work.  Device
+ *     anomalies (traversal step cap exceeded) never abort a kernel: they are
+ *     counted and read with rt_scene_device_error().
+ */
+#ifndef RT_H
+#define RT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rt_status {
+    RT_OK = 0,
+    RT_E_ARG = 1,         /* invalid argument (shape, enum, null pointer, size) */
+    RT_E_UNSUPPORTED = 2, /* valid but not supported by this build */
+    RT_E_STATE = 3,       /* call order (e.g. trace before build) */
+    RT_E_HIP = 4,         /* a HIP runtime call failed */
+    RT_E_DEVICE = 5       /* a device-side anomaly was recorded */
+} rt_status;
+
+enum { RT_MAX_LINES = 4 };    /* lines evaluated per cell (Sect. 4.1.2: compile-time 4) */
+enum { RT_LAM_BATCH = 8 };    /* wavelengths per build/trace batch (Sect. 3.2.1, 4.1: 8) */
+enum { RT_MAX_LEVELS = 5 };   /* MIP levels 0..4 (B = 16 in 2D) */
+
+typedef enum rt_model {
+    RT_MODEL_STATIC = 0, /* eta, chi given per wavelength per voxel */
+    RT_MODEL_LINES = 1   /* line parameters + grey background + bulk velocity per voxel */
+} rt_model;
+
+typedef enum rt_profile {
+    RT_PROFILE_GAUSS = 0, /* peak-normalised Gaussian exp(-x^2), no wavelength scaling */
+    RT_PROFILE_VOIGT = 1  /* H(a,x)/(sqrt(pi) dlD) with Sect. 3.2.1 wavelength scalings */
+} rt_profile;
+
+typedef enum rt_emission {
+    RT_EMIS_STATIC = 0,    /* stored eta, chi per wavelength (lines model: evaluated at rest, u = 0) */
+    RT_EMIS_VELINTERP = 1, /* velocity-grid interpolation (Sect. 3.1), lines model only */
+    RT_EMIS_CAV = 2        /* Core and Voigt (Sect. 3.2): profile evaluated on the fly, lines model only */
+} rt_emission;
+
+typedef enum rt_avg {
+    RT_AVG_LOG = 0,   /* level value = exp(mean of ln(q ds0)) / ds0 (geometric mean) */
+    RT_AVG_LINEAR = 1 /* level value = arithmetic mean of the children */
+} rt_avg;
+
+typedef enum rt_dtype { RT_F32 = 0, RT_BF16 = 1, RT_F16 = 2 } rt_dtype;
+
+typedef enum rt_trace_mode {
+    RT_TRACE_LEVEL0 = 0, /* every active block at MIP 0 (SPARSE; DENSE if the scene is dense) */
+    RT_TRACE_VLM = 1     /* each block at its VLM level of the current batch */
+} rt_trace_mode;
+
+/*
+ * Scene description (host struct, copied by rt_scene_create).
+ *   dim        2 or 3.
+ *   n          voxels per axis, each a positive multiple of brick; n[2] = 1 in 2D.
+ *   brick      block side B: 8 or 16.
+ *   n_levels   MIP levels 0..n_levels-1, 1 <= n_levels <= log2(B) + 1 (<= RT_MAX_LEVELS).
+ *   model      rt_model.
+ *   emission   rt_emission the scene is built for (STATIC for the static model).
+ *   profile    rt_profile (lines model).
+ *   n_lines    1..RT_MAX_LINES (lines model).
+ *   n_v        velocity nodes per cell, >= 2 (velocity interpolation).
+ *   dense      nonzero: every block is active (the dense comparator); 0: blocks
+ *              whose inputs are all zero (or masked out) are empty.
+ *   n_lam      number of wavelengths of the scene.
+ *   ds0        physical side of a MIP-0 voxel (> 0).
+ *   h_lam      host [n_lam] wavelengths in nm (lines model; may be NULL for static).
+ *   h_lam0     host [n_lines] rest wavelengths in nm (lines model).
+ */
+typedef struct rt_scene_desc {
+    int32_t dim;
+    int32_t n[3];
+    int32_t brick;
+    int32_t n_levels;
+    int32_t model;
+    int32_t emission;
+    int32_t profile;
+    int32_t n_lines;
+    int32_t n_v;
+    int32_t dense;
+    int32_t n_lam;
+    int32_t reserved_;
+    double ds0;
+    const double* h_lam;
+    const double* h_lam0;
+} rt_scene_desc;
+
+/*
+ * Device inputs (caller-owned, float32, x fastest).  They must stay valid and
+ * unchanged for the lifetime of the scene: every rt_scene_build reads them.
+ *   static model:  d_eta, d_chi  [n_lam][nvox].
+ *   lines model:   d_eta_star, d_chi_star, d_damp, d_inv_dld  [n_lines][nvox]
+ *                  (eta*, chi* at lam0; Voigt damping at lam0; 1/Doppler width
+ *                  in 1/nm); d_eta_bg, d_chi_bg [nvox] (grey background);
+ *                  d_vel [dim][nvox] bulk velocity in km/s.
+ *   d_block_mask   optional uint8 [nblocks]; nonzero = active.  NULL: a block
+ *                  is active when any of its inputs is nonzero.
+ */
+typedef struct rt_scene_inputs {
+    const float* d_eta;
+    const float* d_chi;
+    const float* d_eta_star;
+    const float* d_chi_star;
+    const float* d_damp;
+    const float* d_inv_dld;
+    const float* d_eta_bg;
+    const float* d_chi_bg;
+    const float* d_vel;
+    const uint8_t* d_block_mask;
+} rt_scene_inputs;
+
+/*
+ * Build parameters of one wavelength batch (Sect. 2.2, 4.1).
+ *   iod_threshold  T: a level-m cell passes if IoD[ln(eta ds0)] <= T and
+ *                  IoD[ln(chi ds0)] <= T, IoD = |Var/Mean| over its 2^D children.
+ *   tau_thin       a cell also passes if chi_m 2^m ds0 < tau_thin.
+ *   max_level      cap on the selected level (-1: none).
+ *   avg_mode       rt_avg for the stored level values (the IoD always uses ln values).
+ *   storage        rt_dtype of the stored values (BF16/F16 round to nearest even).
+ */
+typedef struct rt_build_params {
+    double iod_threshold;
+    double tau_thin;
+    int32_t max_level;
+    int32_t avg_mode;
+    int32_t storage;
+    int32_t reserved_;
+} rt_build_params;
+
+/*
+ * Trace parameters.
+ *   mode       rt_trace_mode.
+ *   max_level  cap on the level sampled by the trace (-1: none).
+ *   I0         boundary intensity entering at the upwind end of every ray.
+ *   step_cap   maximum traversal steps per ray (0: sum of the grid sides x 2 + 16).
+ *              A ray that reaches it stops and is recorded as a device error.
+ *   d_stats    optional device uint64 [4], accumulated (not cleared):
+ *              [0] segments applied (non-empty cells), [1] rays,
+ *              [2] empty-block steps, [3] level changes.
+ *   level_dist distance-graded level cap (VLM mode): level m >= 1 is used only
+ *              in blocks the ray enters at path length t >= level_dist[m]
+ *              (index units; the probe's own block is entered at t = 0).
+ *              All zeros: no grading.  The paper's cascade caps [0,0,1,2,3,4]
+ *              over radiance intervals ending at 1.5 x 4^i voxels (Sect. 4.1)
+ *              correspond to level_dist = {0, 6, 24, 96, 384}.  Values are
+ *              compared exactly (use small dyadic numbers).
+ */
+typedef struct rt_trace_params {
+    int32_t mode;
+    int32_t max_level;
+    float I0;
+    int32_t step_cap;
+    unsigned long long* d_stats;
+    float level_dist[RT_MAX_LEVELS];
+    int32_t reserved_;
+} rt_trace_params;
+
+typedef struct rt_scene_info {
+    int64_t n_blocks;        /* total blocks */
+    int64_t n_active;        /* active blocks */
+    int64_t n_probes;        /* n_active * B^D */
+    int64_t cells_per_brick; /* sum over levels of (B/2^m)^D */
+    int64_t storage_bytes;   /* device bytes held by the scene */
+    int32_t batch_begin;     /* wavelength batch currently built, -1 if none */
+    int32_t batch_end;
+    int32_t n_state_words;   /* ceil(n_blocks / 21) */
+    int32_t reserved_;
+} rt_scene_info;
+
+typedef struct rt_device_err {
+    unsigned long long step_cap_hits; /* rays stopped at the step cap */
+    long long first_ray;              /* smallest ray id that hit it, -1 if none */
+} rt_device_err;
+
+typedef struct rt_scene rt_scene;
+
+/*
+ * rt_scene_create -- classify blocks, order the active ones in Morton order,
+ * assign storage slots (Sect. 2.3.1 offset table) and allocate the scene's
+ * device storage for one wavelength batch.  For the lines model it also
+ * builds the wavelength-independent level chains (velocity grid parameters,
+ * Core-and-Voigt line parameters).  Synchronises `stream` (the active-block
+ * count sizes the allocation).  On success *out owns device memory released
+ * by rt_scene_destroy.  Errors: RT_E_ARG (shape/enum/pointer), RT_E_HIP.
+ */
+rt_status rt_scene_create(const rt_scene_desc* desc, const rt_scene_inputs* inputs, void* stream, rt_scene** out);
+
+/*
+ * rt_scene_build -- for wavelengths [lam_begin, lam_end) (at most
+ * RT_LAM_BATCH): MIP-0 values of the batch, the mip chain of every active
+ * block (Sect. 2.1), the VLM level of every block (min over the batch of the
+ * per-wavelength levels, Sect. 2.2 / 4.1) and the packed 3-bit block states,
+ * 21 per 64-bit word (Sect. 2.3.1).  Asynchronous.  Errors: RT_E_ARG.
+ */
+rt_status rt_scene_build(rt_scene* scene, const rt_build_params* params, int32_t lam_begin, int32_t lam_end,
+                         void* stream);
+
+/*
+ * rt_trace -- long-characteristic formal solution for every (direction,
+ * probe) pair over the current batch (Sect. 2.3, Alg. 1 traversal; Eq.
+ * RteIntegral per segment).
+ *   d_dirs     device float [n_dir][dim], unit vectors (|w| - 1 within 1e-5).
+ *   d_probes   device int32 [n_probes] voxel linear indices, or NULL for all
+ *              probes (then n_probes must equal rt_scene_info.n_probes).
+ *   d_I        device float [n_dir][lam_end - lam_begin][n_probes]: intensity
+ *              arriving at each probe along each direction.
+ * Asynchronous.  Errors: RT_E_ARG, RT_E_STATE (no batch built).
+ */
+rt_status rt_trace(const rt_scene* scene, const rt_trace_params* params, const float* d_dirs, int32_t n_dir,
+                   const int32_t* d_probes, int64_t n_probes, float* d_I, void* stream);
+
+/* Scene facts (host only, no device work). */
+rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* h_info);
+
+/* Active blocks in Morton (storage) order: host int32 [n_active].  Synchronising. */
+rt_status rt_scene_active_blocks(const rt_scene* scene, int32_t* h_blocks);
+
+/* VLM level of every block for the current batch, -1 = empty: host int8 [n_blocks].  Synchronising. */
+rt_status rt_scene_levels(const rt_scene* scene, int8_t* h_levels);
+
+/* Packed block states (state = level + 1, 0 = empty; 3 bits, 21 per word): host uint64 [n_state_words].
+ * Synchronising. */
+rt_status rt_scene_states(const rt_scene* scene, uint64_t* h_words);
+
+/*
+ * Stored values of given cells for the current batch (parity checks).
+ *   h_cells  host int32 [n][4]: x, y, z (any voxel inside the cell) and level.
+ *   h_out    host float [n][RT_LAM_BATCH][2]: eta, chi per batch wavelength,
+ *            decoded to float32; static emission only.
+ * Synchronising.  Errors: RT_E_ARG (cell in an empty block, level out of range).
+ */
+rt_status rt_scene_cell_values(const rt_scene* scene, int32_t n, const int32_t* h_cells, float* h_out);
+
+/*
+ * Adapted-grid cells visited by one ray, using the trace kernel's own
+ * traversal code on one device lane (parity of the traversal).
+ *   probe_vox  voxel linear index of the probe;  h_dir host float [dim].
+ *   h_cells    host int32 [cap][4]: cell origin x, y, z (multiples of 2^level) and level.
+ *   h_t        host double [cap][2]: t at entry and exit of the cell.
+ *   h_count    number of cells written (<= cap; RT_E_ARG if cap is too small).
+ * Synchronising.
+ */
+rt_status rt_debug_visited(const rt_scene* scene, const rt_trace_params* params, int32_t probe_vox,
+                           const float* h_dir, int32_t cap, int32_t* h_cells, double* h_t, int32_t* h_count,
+                           void* stream);
+
+/* Device error counters accumulated by traces of this scene (synchronising); reset clears them. */
+rt_status rt_scene_device_error(const rt_scene* scene, rt_device_err* h_err);
+rt_status rt_scene_reset_device_error(rt_scene* scene, void* stream);
+
+/* Releases the scene's device memory and handle.  NULL is ignored. */
+void rt_scene_destroy(rt_scene* scene);
+
+/* Thread-local description of the last failure in this thread ("" if none). */
+const char* rt_last_error(void);
+
+/* Library version string. */
+const char* rt_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RT_H */

@@ -46,7 +46,7 @@ class OrcScene(ctypes.Structure):
         ("pad_", ctypes.c_int32), ("ds0", ctypes.c_double), ("I0", ctypes.c_double),
         ("st_eta", _P), ("st_chi", _P), ("lam", _P), ("lam0", _P), ("eta_star", _P),
         ("chi_star", _P), ("damp", _P), ("inv_dld", _P), ("eta_bg", _P), ("chi_bg", _P),
-        ("vel", _P),
+        ("vel", _P), ("level_dist", _P),
     ]
 
 
@@ -130,6 +130,17 @@ class Scene:
             s.n_lam = 0
         self.s = s
         self.level_total = int(lib().orc_level_total(self.dim, _ptr(np.array(self.n, np.int32)), s.n_levels))
+
+    def set_level_dist(self, level_dist):
+        """Distance-graded level cap: level m only in blocks the ray enters at
+        path length >= level_dist[m]; None disables the grading."""
+        if level_dist is None:
+            self.s.level_dist = None
+            return
+        ld = np.full(8, np.inf)  # levels beyond the given schedule are never allowed
+        ld[: len(level_dist)] = level_dist
+        self._keep["level_dist"] = ld
+        self.s.level_dist = _ptr(ld)
 
     def set_static_levels(self, st_eta, st_chi):
         """Level grids [n_lam][level_total] FP64 for the static march."""

@@ -43,16 +43,28 @@ def ray_cells_exact(dim, n, pv, w):
     return cells, tin, tout
 
 
-def adapted_cells_exact(dim, n, B, levels, pv, w):
-    """Adapted-grid cells (coarse coords, level, t_in, t_out) from the exact dense list."""
+def adapted_cells_exact(dim, n, B, levels, pv, w, level_dist=None):
+    """Adapted-grid cells (coarse coords, level, t_in, t_out) from the exact dense list.
+
+    level_dist: level m only in blocks entered at t >= level_dist[m] (exact compare)."""
     cells, tin, tout = ray_cells_exact(dim, n, pv, w)
     nb = [int(n[a]) // B for a in range(dim)] + [1] * (3 - dim)
     out = []
+    cur_blk, cur_cap = None, 127
     for c, a, b in zip(cells, tin, tout):
         blk = c[0] // B + nb[0] * (c[1] // B + nb[1] * (c[2] // B))
+        if blk != cur_blk:
+            cur_blk = blk
+            if level_dist is not None:
+                cur_cap = 0
+                for m in range(1, len(level_dist)):
+                    if not Fraction(level_dist[m]) <= a:
+                        break
+                    cur_cap = m
         L = int(levels[blk]) if levels is not None else 0
         if L < 0:
             continue
+        L = min(L, cur_cap)
         cc = [x & ~((1 << L) - 1) for x in c]
         if out and out[-1][0] == cc and out[-1][1] == L:
             out[-1][3] = b

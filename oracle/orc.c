@@ -79,6 +79,9 @@ typedef struct orc_scene {
     const float* eta_bg;    /* [nvox] */
     const float* chi_bg;    /* [nvox] */
     const float* vel;       /* [dim][nvox] km/s */
+    /* distance-graded level cap: level m only in blocks entered at path length
+     * >= level_dist[m] (m = 1 .. n_levels-1); NULL = no grading */
+    const double* level_dist;
 } orc_scene;
 
 static int64_t nvox_of(const orc_scene* s) { return (int64_t)s->n[0] * s->n[1] * s->n[2]; }
@@ -177,9 +180,28 @@ int orc_ray_cells(int32_t dim, const int32_t n[3], const int32_t pv[3], const fl
  * including empty blocks (the dense march).  Output cells are the level's
  * coarse coordinates (multiples of 2^level).  Returns count or -1.
  */
-int orc_ray_segments(const orc_scene* s, const int8_t* levels, const int32_t pv[3], const float w[3],
-                     int cap, int32_t* cell, int32_t* lvl, double* tin, double* tout,
-                     int32_t* scratch_cell, double* scratch_tin, double* scratch_tout, int scratch_cap)
+/*
+ * Distance-graded level cap (near field at full resolution): level_dist[m]
+ * (m = 1 .. n_levels-1, nullable) is the path length from the probe beyond
+ * which level m may be used.  A block's level is capped by the largest m with
+ * level_dist[m] <= t_entry, t_entry the path length at which the ray enters
+ * the block (0 for the probe's own block), following the per-cascade MIP caps
+ * of Sect. 4.1 (full resolution near the probe, coarser proxies further out).
+ */
+static int graded_cap(const orc_scene* s, const double* level_dist, double t_entry)
+{
+    int cap = 0;
+    if (!level_dist) return 127;
+    for (int m = 1; m < s->n_levels; ++m) {
+        if (!(level_dist[m] <= t_entry)) break;
+        cap = m;
+    }
+    return cap;
+}
+
+int orc_ray_segments_graded(const orc_scene* s, const int8_t* levels, const double* level_dist, const int32_t pv[3],
+                            const float w[3], int cap, int32_t* cell, int32_t* lvl, double* tin, double* tout,
+                            int32_t* scratch_cell, double* scratch_tin, double* scratch_tout, int scratch_cap)
 {
     int nd = orc_ray_cells(s->dim, s->n, pv, w, scratch_cap, scratch_cell, scratch_tin, scratch_tout);
     if (nd < 0) return -1;
@@ -187,13 +209,20 @@ int orc_ray_segments(const orc_scene* s, const int8_t* levels, const int32_t pv[
     int32_t nb[3] = {1, 1, 1};
     for (int a = 0; a < s->dim; ++a) nb[a] = s->n[a] / B;
     int cnt = 0;
+    int64_t cur_b = -1;
+    int cur_cap = 127;
     for (int i = 0; i < nd; ++i) {
         const int32_t* c = scratch_cell + 3 * i;
         int L = 0;
         if (levels) {
             int64_t b = c[0] / B + (int64_t)nb[0] * (c[1] / B + (int64_t)nb[1] * (c[2] / B));
+            if (b != cur_b) {
+                cur_b = b;
+                cur_cap = graded_cap(s, level_dist, scratch_tin[i]);
+            }
             L = levels[b];
             if (L < 0) continue;
+            if (L > cur_cap) L = cur_cap;
         }
         int32_t cc[3];
         for (int a = 0; a < 3; ++a) cc[a] = c[a] & ~((1 << L) - 1);
@@ -210,6 +239,14 @@ int orc_ray_segments(const orc_scene* s, const int8_t* levels, const int32_t pv[
         ++cnt;
     }
     return cnt;
+}
+
+int orc_ray_segments(const orc_scene* s, const int8_t* levels, const int32_t pv[3], const float w[3], int cap,
+                     int32_t* cell, int32_t* lvl, double* tin, double* tout, int32_t* scratch_cell,
+                     double* scratch_tin, double* scratch_tout, int scratch_cap)
+{
+    return orc_ray_segments_graded(s, levels, s->level_dist, pv, w, cap, cell, lvl, tin, tout, scratch_cell,
+                                   scratch_tin, scratch_tout, scratch_cap);
 }
 
 /* ------------------------------------------------------------------ */

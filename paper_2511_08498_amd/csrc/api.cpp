@@ -1,0 +1,480 @@
+// Host side of the C ABI (include/rt.h): argument validation, scene storage,
+// Morton ordering of blocks, and the launch sequence of build and trace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+using namespace rt;
+
+namespace {
+
+thread_local std::string g_err;
+
+rt_status fail(rt_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define RT_HIP(call)                                                                                  \
+    do {                                                                                              \
+        hipError_t e_ = (call);                                                                       \
+        if (e_ != hipSuccess) return fail(RT_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+int ilog2(int v)
+{
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+
+}  // namespace
+
+struct rt_scene {
+    rt_scene_desc desc;
+    Geo g;
+    Inputs in;
+    SceneBufs b;
+    int n_active = 0;
+    std::vector<double> lam;
+    std::vector<double> lam0;
+    std::vector<void*> allocs;
+    size_t bytes = 0;
+    int batch_begin = -1, batch_end = -1;
+    int storage = RT_F32;
+    int cav_rec = 0;
+
+    ~rt_scene()
+    {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    template <typename T>
+    rt_status alloc(T** p, size_t count)
+    {
+        size_t nbytes = std::max<size_t>(count * sizeof(T), 256);
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, nbytes);
+        if (e != hipSuccess) return fail(RT_E_HIP, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
+        allocs.push_back(q);
+        bytes += nbytes;
+        *p = (T*)q;
+        return RT_OK;
+    }
+};
+
+#define RT_TRY(call)                        \
+    do {                                    \
+        rt_status s_ = (call);              \
+        if (s_ != RT_OK) return s_;         \
+    } while (0)
+
+extern "C" {
+
+const char* rt_last_error(void) { return g_err.c_str(); }
+
+const char* rt_version(void) { return "rt 0.1 (gfx950)"; }
+
+rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, void* stream, rt_scene** out)
+{
+    g_err.clear();
+    if (!d || !inp || !out) return fail(RT_E_ARG, "null argument");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    if (d->dim != 2 && d->dim != 3) return fail(RT_E_ARG, "dim must be 2 or 3 (got %d)", d->dim);
+    if (d->brick != 8 && d->brick != 16) return fail(RT_E_ARG, "brick must be 8 or 16 (got %d)", d->brick);
+    const int log2B = ilog2(d->brick);
+    if (d->n_levels < 1 || d->n_levels > log2B + 1 || d->n_levels > RT_MAX_LEVELS)
+        return fail(RT_E_ARG, "n_levels must be in [1, log2(brick)+1] (got %d)", d->n_levels);
+    if (d->dim == 3 && d->brick == 16) return fail(RT_E_UNSUPPORTED, "3D scenes use 8^3 bricks");
+    for (int a = 0; a < 3; ++a) {
+        int na = d->n[a];
+        if (a < d->dim) {
+            if (na <= 0 || na % d->brick != 0 || na > 8192)
+                return fail(RT_E_ARG, "n[%d] = %d must be a positive multiple of brick, at most 8192", a, na);
+        } else if (na != 1) {
+            return fail(RT_E_ARG, "n[%d] must be 1 for a %dD scene", a, d->dim);
+        }
+    }
+    if (!(d->ds0 > 0.0)) return fail(RT_E_ARG, "ds0 must be positive");
+    if (d->n_lam < 1) return fail(RT_E_ARG, "n_lam must be >= 1");
+    if (d->model == RT_MODEL_STATIC) {
+        if (d->emission != RT_EMIS_STATIC) return fail(RT_E_ARG, "static model supports only RT_EMIS_STATIC");
+        if (!inp->d_eta || !inp->d_chi) return fail(RT_E_ARG, "static model needs d_eta and d_chi");
+    } else if (d->model == RT_MODEL_LINES) {
+        if (d->n_lines < 1 || d->n_lines > RT_MAX_LINES) return fail(RT_E_ARG, "n_lines must be in [1, %d]", RT_MAX_LINES);
+        if (d->profile != RT_PROFILE_GAUSS && d->profile != RT_PROFILE_VOIGT) return fail(RT_E_ARG, "bad profile");
+        if (d->emission < RT_EMIS_STATIC || d->emission > RT_EMIS_CAV) return fail(RT_E_ARG, "bad emission");
+        if (d->emission == RT_EMIS_VELINTERP && d->n_v < 2) return fail(RT_E_ARG, "n_v must be >= 2");
+        if (!d->h_lam || !d->h_lam0) return fail(RT_E_ARG, "lines model needs h_lam and h_lam0");
+        if (!inp->d_eta_star || !inp->d_chi_star || !inp->d_damp || !inp->d_inv_dld || !inp->d_eta_bg ||
+            !inp->d_chi_bg || !inp->d_vel)
+            return fail(RT_E_ARG, "lines model needs every line input");
+        for (int l = 0; l < d->n_lam; ++l)
+            if (!(d->h_lam[l] > 0.0)) return fail(RT_E_ARG, "wavelengths must be positive");
+        for (int l = 0; l < d->n_lines; ++l)
+            if (!(d->h_lam0[l] > 0.0)) return fail(RT_E_ARG, "rest wavelengths must be positive");
+    } else {
+        return fail(RT_E_ARG, "bad model %d", d->model);
+    }
+
+    rt_scene* sc = new (std::nothrow) rt_scene();
+    if (!sc) return fail(RT_E_ARG, "out of host memory");
+    sc->desc = *d;
+    Geo& g = sc->g;
+    std::memset(&g, 0, sizeof(g));
+    g.dim = d->dim;
+    g.B = d->brick;
+    g.log2B = log2B;
+    g.n_levels = d->n_levels;
+    g.nblocks = 1;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = d->n[a];
+        g.nb[a] = a < d->dim ? d->n[a] / d->brick : 1;
+        g.nblocks *= g.nb[a];
+    }
+    g.bvox = 1 << (d->dim * log2B);
+    int off = 0;
+    for (int m = 0; m <= RT_MAX_LEVELS; ++m) {
+        g.lvl_off[m] = off;
+        if (m < d->n_levels) off += 1 << (d->dim * (log2B - m));
+    }
+    g.cells = off;
+    g.n_state_words = (int)((g.nblocks + kStatesPerWord - 1) / kStatesPerWord);
+    if (d->model == RT_MODEL_LINES) {
+        sc->lam.assign(d->h_lam, d->h_lam + d->n_lam);
+        sc->lam0.assign(d->h_lam0, d->h_lam0 + d->n_lines);
+    }
+    Inputs& in = sc->in;
+    in.eta = inp->d_eta;
+    in.chi = inp->d_chi;
+    in.eta_star = inp->d_eta_star;
+    in.chi_star = inp->d_chi_star;
+    in.damp = inp->d_damp;
+    in.inv_dld = inp->d_inv_dld;
+    in.eta_bg = inp->d_eta_bg;
+    in.chi_bg = inp->d_chi_bg;
+    in.vel = inp->d_vel;
+    in.mask = inp->d_block_mask;
+    in.nvox = (long long)g.n[0] * g.n[1] * g.n[2];
+
+    // Morton order of all blocks (geometry only)
+    std::vector<std::pair<uint64_t, int32_t>> mo((size_t)g.nblocks);
+    for (long long b = 0; b < g.nblocks; ++b) {
+        uint32_t bc[3] = {(uint32_t)(b % g.nb[0]), (uint32_t)((b / g.nb[0]) % g.nb[1]),
+                          (uint32_t)(b / ((long long)g.nb[0] * g.nb[1]))};
+        uint64_t code = 0;
+        for (int bit = 0; bit < 21; ++bit)
+            for (int a = 0; a < g.dim; ++a) code |= (uint64_t)((bc[a] >> bit) & 1u) << (bit * g.dim + a);
+        mo[(size_t)b] = {code, (int32_t)b};
+    }
+    std::sort(mo.begin(), mo.end());
+    std::vector<int32_t> morton((size_t)g.nblocks);
+    for (size_t i = 0; i < mo.size(); ++i) morton[i] = mo[i].second;
+
+    SceneBufs& B = sc->b;
+    std::memset(&B, 0, sizeof(B));
+    auto cleanup = [&](rt_status st) {
+        delete sc;
+        return st;
+    };
+    rt_status st;
+    if ((st = sc->alloc(&B.morton, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.active, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.slot, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.active_list, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.n_active, 1)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.levels, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.states, (size_t)g.n_state_words)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.err, 2)) != RT_OK) return cleanup(st);
+    hipError_t e;
+    if ((e = hipMemcpyAsync(B.morton, morton.data(), morton.size() * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return cleanup(fail(RT_E_HIP, "upload: %s", hipGetErrorString(e)));
+    unsigned long long err0[2] = {0ull, ~0ull};
+    if ((e = hipMemcpyAsync(B.err, err0, sizeof(err0), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "upload: %s", hipGetErrorString(e)));
+    if ((e = launch_classify(g, in, d->model, d->n_lam, d->n_lines, d->dense, B.active, s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "classify: %s", hipGetErrorString(e)));
+    if ((e = launch_slots(g, B.morton, B.active, B.slot, B.active_list, B.n_active, s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "slots: %s", hipGetErrorString(e)));
+    if ((e = launch_fill_levels(g, B.levels, s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "levels: %s", hipGetErrorString(e)));
+    int32_t na = 0;
+    if ((e = hipMemcpyAsync(&na, B.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "readback: %s", hipGetErrorString(e)));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "synchronize: %s", hipGetErrorString(e)));
+    sc->n_active = na;
+    const size_t cells = (size_t)na * g.cells;
+    if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) {
+        if ((st = sc->alloc((float**)&B.vals, cells * kLam * 2)) != RT_OK) return cleanup(st);
+    }
+    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP) {
+        if ((st = sc->alloc(&B.vgrid, cells)) != RT_OK) return cleanup(st);
+        if ((st = sc->alloc(&B.vnodes, cells * (size_t)d->n_v * kLam * 2)) != RT_OK) return cleanup(st);
+        if ((e = launch_vgrid(g, in, B, na, s)) != hipSuccess)
+            return cleanup(fail(RT_E_HIP, "velocity grid: %s", hipGetErrorString(e)));
+    }
+    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
+        sc->cav_rec = cav_rec_floats(d->n_lines);
+        if ((st = sc->alloc(&B.cav, cells * (size_t)sc->cav_rec)) != RT_OK) return cleanup(st);
+        size_t shm = sizeof(double) * (size_t)(4 * d->n_lines + 2 + d->dim) * g.cells;
+        if (shm > 160 * 1024) return cleanup(fail(RT_E_UNSUPPORTED, "too many lines for the LDS chain"));
+        if ((e = launch_cav_chain(g, in, B, na, d->n_lines, d->ds0, RT_AVG_LOG, s)) != hipSuccess)
+            return cleanup(fail(RT_E_HIP, "core-and-voigt chain: %s", hipGetErrorString(e)));
+    }
+    *out = sc;
+    return RT_OK;
+}
+
+static LamBatch make_batch(const rt_scene* sc, int lam_begin, int lam_end)
+{
+    LamBatch lb;
+    std::memset(&lb, 0, sizeof(lb));
+    lb.nl = lam_end - lam_begin;
+    lb.n_lines = sc->desc.model == RT_MODEL_LINES ? sc->desc.n_lines : 0;
+    lb.profile = sc->desc.profile;
+    for (int l = 0; l < kLam; ++l) {
+        int il = lam_begin + std::min(l, lb.nl - 1);
+        lb.lam[l] = sc->lam.empty() ? 0.0 : sc->lam[(size_t)il];
+    }
+    for (int k = 0; k < kMaxLines; ++k) lb.lam0[k] = k < lb.n_lines ? sc->lam0[(size_t)k] : 1.0;
+    return lb;
+}
+
+rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_begin, int32_t lam_end, void* stream)
+{
+    g_err.clear();
+    if (!sc || !p) return fail(RT_E_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    const rt_scene_desc& d = sc->desc;
+    if (lam_begin < 0 || lam_end > d.n_lam || lam_end <= lam_begin || lam_end - lam_begin > kLam)
+        return fail(RT_E_ARG, "wavelength batch [%d, %d) invalid (n_lam %d, at most %d per batch)", lam_begin,
+                    lam_end, d.n_lam, kLam);
+    if (!(p->iod_threshold >= 0.0)) return fail(RT_E_ARG, "iod_threshold must be >= 0");
+    if (!(p->tau_thin >= 0.0)) return fail(RT_E_ARG, "tau_thin must be >= 0");
+    if (p->avg_mode != RT_AVG_LOG && p->avg_mode != RT_AVG_LINEAR) return fail(RT_E_ARG, "bad avg_mode");
+    if (p->storage < RT_F32 || p->storage > RT_F16) return fail(RT_E_ARG, "bad storage dtype");
+    const bool static_emis = d.model == RT_MODEL_STATIC || d.emission == RT_EMIS_STATIC;
+    if (!static_emis && p->storage != RT_F32)
+        return fail(RT_E_UNSUPPORTED, "reduced-precision storage is implemented for static emission");
+    if (d.emission == RT_EMIS_CAV && p->avg_mode != RT_AVG_LOG)
+        return fail(RT_E_UNSUPPORTED, "core-and-voigt chains are built in log mode");
+    LamBatch lb = make_batch(sc, lam_begin, lam_end);
+    const Geo& g = sc->g;
+    int cap = p->max_level < 0 ? -1 : p->max_level;
+    RT_HIP(launch_fill_levels(g, sc->b.levels, s));
+    int vrule = (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_CAV) ? 1 : 0;
+    RT_HIP(launch_build_static(g, sc->in, sc->b, sc->n_active, d.model, vrule, lb, lam_begin, d.ds0, p->iod_threshold,
+                               p->tau_thin, cap, p->avg_mode, p->storage, static_emis ? 1 : 0, s));
+    if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_VELINTERP)
+        RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, d.ds0, p->avg_mode, s));
+    RT_HIP(launch_pack_states(g, sc->b.levels, sc->b.states, s));
+    sc->batch_begin = lam_begin;
+    sc->batch_end = lam_end;
+    sc->storage = p->storage;
+    return RT_OK;
+}
+
+static TraceLaunch make_trace(const rt_scene* sc, const rt_trace_params* p)
+{
+    TraceLaunch t;
+    std::memset(&t, 0, sizeof(t));
+    const Geo& g = sc->g;
+    t.g = g;
+    t.states = sc->b.states;
+    t.slot = sc->b.slot;
+    t.vals = sc->b.vals;
+    t.vgrid = sc->b.vgrid;
+    t.vnodes = sc->b.vnodes;
+    t.cav = sc->b.cav;
+    t.mode = p->mode;
+    t.max_level = p->max_level < 0 ? 127 : p->max_level;
+    t.graded = 0;
+    for (int m = 0; m < kMaxLevels; ++m) {
+        t.level_dist[m] = m == 0 ? 0.f : p->level_dist[m];
+        if (m > 0 && p->level_dist[m] != 0.f) t.graded = 1;
+    }
+    int cap = 16;
+    for (int a = 0; a < g.dim; ++a) cap += 2 * g.n[a];
+    t.step_cap = p->step_cap > 0 ? p->step_cap : cap;
+    t.active_list = sc->b.active_list;
+    t.I0 = p->I0;
+    t.ds0 = (float)sc->desc.ds0;
+    t.emission = sc->desc.model == RT_MODEL_STATIC ? RT_EMIS_STATIC : sc->desc.emission;
+    t.storage = sc->storage;
+    t.n_v = sc->desc.n_v;
+    t.cav_rec = sc->cav_rec;
+    t.lb = make_batch(sc, sc->batch_begin, sc->batch_end);
+    t.stats = p->d_stats;
+    t.err = sc->b.err;
+    return t;
+}
+
+rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, int32_t n_dir,
+                   const int32_t* d_probes, int64_t n_probes, float* d_I, void* stream)
+{
+    g_err.clear();
+    if (!sc || !p || !d_dirs || !d_I) return fail(RT_E_ARG, "null argument");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace before rt_scene_build");
+    if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
+    if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
+    for (int m = 1; m < RT_MAX_LEVELS; ++m)
+        if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
+    const long long all = (long long)sc->n_active * sc->g.bvox;
+    if (!d_probes && n_probes != all)
+        return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
+    if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
+    if (n_probes == 0) return RT_OK;
+    if ((long long)n_dir * ((n_probes + 63) / 64) > (long long)0x7fffffff * 4)
+        return fail(RT_E_ARG, "launch too large");
+    TraceLaunch t = make_trace(sc, p);
+    t.dirs = d_dirs;
+    t.n_dir = n_dir;
+    t.probes = d_probes;
+    t.n_probes = n_probes;
+    t.I = d_I;
+    RT_HIP(launch_trace(t, (hipStream_t)stream));
+    return RT_OK;
+}
+
+rt_status rt_scene_get_info(const rt_scene* sc, rt_scene_info* h)
+{
+    if (!sc || !h) return fail(RT_E_ARG, "null argument");
+    h->n_blocks = sc->g.nblocks;
+    h->n_active = sc->n_active;
+    h->n_probes = (int64_t)sc->n_active * sc->g.bvox;
+    h->cells_per_brick = sc->g.cells;
+    h->storage_bytes = (int64_t)sc->bytes;
+    h->batch_begin = sc->batch_begin;
+    h->batch_end = sc->batch_end;
+    h->n_state_words = sc->g.n_state_words;
+    h->reserved_ = 0;
+    return RT_OK;
+}
+
+rt_status rt_scene_active_blocks(const rt_scene* sc, int32_t* h)
+{
+    if (!sc || !h) return fail(RT_E_ARG, "null argument");
+    if (sc->n_active == 0) return RT_OK;
+    RT_HIP(hipMemcpy(h, sc->b.active_list, sizeof(int32_t) * (size_t)sc->n_active, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+rt_status rt_scene_levels(const rt_scene* sc, int8_t* h)
+{
+    if (!sc || !h) return fail(RT_E_ARG, "null argument");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
+    RT_HIP(hipDeviceSynchronize());
+    RT_HIP(hipMemcpy(h, sc->b.levels, (size_t)sc->g.nblocks, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+rt_status rt_scene_states(const rt_scene* sc, uint64_t* h)
+{
+    if (!sc || !h) return fail(RT_E_ARG, "null argument");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
+    RT_HIP(hipDeviceSynchronize());
+    RT_HIP(hipMemcpy(h, sc->b.states, sizeof(uint64_t) * (size_t)sc->g.n_state_words, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+rt_status rt_scene_cell_values(const rt_scene* sc, int32_t n, const int32_t* h_cells, float* h_out)
+{
+    if (!sc || !h_cells || !h_out || n < 0) return fail(RT_E_ARG, "bad argument");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
+    if (!sc->b.vals) return fail(RT_E_UNSUPPORTED, "cell values exist for static emission only");
+    if (n == 0) return RT_OK;
+    for (int i = 0; i < n; ++i) {
+        const int32_t* c = h_cells + 4 * i;
+        for (int a = 0; a < 3; ++a)
+            if (c[a] < 0 || c[a] >= sc->g.n[a]) return fail(RT_E_ARG, "cell %d outside the grid", i);
+        if (c[3] < 0 || c[3] >= sc->g.n_levels) return fail(RT_E_ARG, "cell %d level out of range", i);
+    }
+    int32_t* dc = nullptr;
+    float* dout = nullptr;
+    RT_HIP(hipMalloc(&dc, sizeof(int32_t) * 4 * (size_t)n));
+    hipError_t e = hipMalloc(&dout, sizeof(float) * 2 * kLam * (size_t)n);
+    if (e != hipSuccess) {
+        (void)hipFree(dc);
+        return fail(RT_E_HIP, "hipMalloc: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(dc, h_cells, sizeof(int32_t) * 4 * (size_t)n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_read_cells(sc->g, sc->b, sc->storage, n, dc, dout, 0);
+    if (e == hipSuccess) e = hipMemcpy(h_out, dout, sizeof(float) * 2 * kLam * (size_t)n, hipMemcpyDeviceToHost);
+    (void)hipFree(dc);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(RT_E_HIP, "cell values: %s", hipGetErrorString(e));
+    return RT_OK;
+}
+
+rt_status rt_debug_visited(const rt_scene* sc, const rt_trace_params* p, int32_t probe_vox, const float* h_dir,
+                           int32_t cap, int32_t* h_cells, double* h_t, int32_t* h_count, void* stream)
+{
+    if (!sc || !p || !h_dir || !h_cells || !h_t || !h_count || cap < 1) return fail(RT_E_ARG, "bad argument");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
+    if (probe_vox < 0 || probe_vox >= sc->in.nvox) return fail(RT_E_ARG, "probe outside the grid");
+    hipStream_t s = (hipStream_t)stream;
+    TraceLaunch t = make_trace(sc, p);
+    int32_t* dc = nullptr;
+    double* dt = nullptr;
+    int32_t* dn = nullptr;
+    RT_HIP(hipMalloc(&dc, sizeof(int32_t) * 4 * (size_t)cap));
+    RT_HIP(hipMalloc(&dt, sizeof(double) * 2 * (size_t)cap));
+    RT_HIP(hipMalloc(&dn, sizeof(int32_t)));
+    float w[3] = {h_dir[0], sc->g.dim > 1 ? h_dir[1] : 0.f, sc->g.dim > 2 ? h_dir[2] : 0.f};
+    hipError_t e = launch_debug_visited(t, probe_vox, w[0], w[1], w[2], cap, dc, dt, dn, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    int32_t n = 0;
+    if (e == hipSuccess) e = hipMemcpy(&n, dn, sizeof(int32_t), hipMemcpyDeviceToHost);
+    int ncp = std::min(std::max(n, 0), cap);
+    if (e == hipSuccess && ncp > 0) e = hipMemcpy(h_cells, dc, sizeof(int32_t) * 4 * (size_t)ncp, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ncp > 0) e = hipMemcpy(h_t, dt, sizeof(double) * 2 * (size_t)ncp, hipMemcpyDeviceToHost);
+    (void)hipFree(dc);
+    (void)hipFree(dt);
+    (void)hipFree(dn);
+    if (e != hipSuccess) return fail(RT_E_HIP, "debug visited: %s", hipGetErrorString(e));
+    *h_count = n;
+    if (n < 0) return fail(RT_E_DEVICE, "step cap reached");
+    if (n > cap) return fail(RT_E_ARG, "cap %d too small for %d cells", cap, n);
+    return RT_OK;
+}
+
+rt_status rt_scene_device_error(const rt_scene* sc, rt_device_err* h)
+{
+    if (!sc || !h) return fail(RT_E_ARG, "null argument");
+    unsigned long long v[2];
+    RT_HIP(hipDeviceSynchronize());
+    RT_HIP(hipMemcpy(v, sc->b.err, sizeof(v), hipMemcpyDeviceToHost));
+    h->step_cap_hits = v[0];
+    h->first_ray = v[0] ? (long long)v[1] : -1;
+    return RT_OK;
+}
+
+rt_status rt_scene_reset_device_error(rt_scene* sc, void* stream)
+{
+    if (!sc) return fail(RT_E_ARG, "null argument");
+    unsigned long long err0[2] = {0ull, ~0ull};
+    RT_HIP(hipMemcpyAsync(sc->b.err, err0, sizeof(err0), hipMemcpyHostToDevice, (hipStream_t)stream));
+    RT_HIP(hipStreamSynchronize((hipStream_t)stream));
+    return RT_OK;
+}
+
+void rt_scene_destroy(rt_scene* sc) { delete sc; }
+
+}  // extern "C"

@@ -1,0 +1,357 @@
+// Scene construction kernels: block classification, Morton-ordered slots
+// (Sect. 2.3.1 offset table), the per-batch mip chain with the index of
+// dispersion and VLM level selection (Sect. 2.1-2.2), state packing.
+//
+// This translation unit is compiled with -ffp-contract=off: the level
+// statistics are FP64 sums in a fixed pairwise order (x pairs, then y, then z)
+// so that block levels are reproducible to the last bit.
+#include "common.h"
+#include "profile.h"
+
+namespace rt {
+
+// ------------------------------------------------------------------ classify
+__global__ void k_classify(Geo g, Inputs in, int model, int n_lam, int n_lines, int dense, uint8_t* active)
+{
+    const long long b = blockIdx.x;
+    int bc[3] = {(int)(b % g.nb[0]), (int)((b / g.nb[0]) % g.nb[1]), (int)(b / ((long long)g.nb[0] * g.nb[1]))};
+    int any = 0;
+    if (dense) {
+        any = 1;
+    } else if (in.mask) {
+        any = in.mask[b] != 0;
+    } else {
+        for (int i = threadIdx.x; i < g.bvox && !any; i += blockDim.x) {
+            int lx = i & (g.B - 1), ly = (i >> g.log2B) & (g.B - 1), lz = g.dim > 2 ? (i >> (2 * g.log2B)) : 0;
+            long long v = (long long)(bc[0] * g.B + lx) +
+                          (long long)g.n[0] * ((long long)(bc[1] * g.B + ly) + (long long)g.n[1] * (bc[2] * g.B + lz));
+            if (model == RT_MODEL_STATIC) {
+                for (int l = 0; l < n_lam; ++l)
+                    if (in.eta[(long long)l * in.nvox + v] != 0.f || in.chi[(long long)l * in.nvox + v] != 0.f) {
+                        any = 1;
+                        break;
+                    }
+            } else {
+                if (in.eta_bg[v] != 0.f || in.chi_bg[v] != 0.f) any = 1;
+                for (int l = 0; l < n_lines; ++l)
+                    if (in.eta_star[(long long)l * in.nvox + v] != 0.f || in.chi_star[(long long)l * in.nvox + v] != 0.f)
+                        any = 1;
+            }
+        }
+    }
+    any = __syncthreads_or(any);
+    if (threadIdx.x == 0) active[b] = (uint8_t)(any ? 1 : 0);
+}
+
+hipError_t launch_classify(const Geo& g, const Inputs& in, int model, int n_lam, int n_lines, int dense,
+                           uint8_t* active, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)g.nblocks), dim3(256), 0, s, g, in, model, n_lam, n_lines, dense,
+                       active);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------- slots
+// One workgroup walks the Morton order in chunks of 1024 blocks and assigns
+// each active block the next storage slot (exclusive prefix sum).
+__global__ void __launch_bounds__(1024) k_slots(long long nb, const int32_t* morton, const uint8_t* active,
+                                                int32_t* slot, int32_t* active_list, int32_t* n_active)
+{
+    __shared__ int wsum[16];
+    __shared__ int base_s;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (tid == 0) base_s = 0;
+    __syncthreads();
+    for (long long c0 = 0; c0 < nb; c0 += 1024) {
+        long long i = c0 + tid;
+        int b = i < nb ? morton[i] : -1;
+        int f = (b >= 0 && active[b]) ? 1 : 0;
+        // inclusive scan inside the wave
+        int x = f;
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        int off = 0;
+        for (int w = 0; w < wid; ++w) off += wsum[w];
+        int base = base_s;
+        int excl = base + off + x - f;
+        if (b >= 0) {
+            slot[b] = f ? excl : -1;
+            if (f) active_list[excl] = b;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int tot = 0;
+            for (int w = 0; w < 16; ++w) tot += wsum[w];
+            base_s = base + tot;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *n_active = base_s;
+}
+
+hipError_t launch_slots(const Geo& g, const int32_t* morton, const uint8_t* active, int32_t* slot,
+                        int32_t* active_list, int32_t* n_active, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_slots, dim3(1), dim3(1024), 0, s, g.nblocks, morton, active, slot, active_list, n_active);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_levels(long long nb, int8_t* levels)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nb) levels[i] = -1;
+}
+
+hipError_t launch_fill_levels(const Geo& g, int8_t* levels, hipStream_t s)
+{
+    unsigned blocks = (unsigned)((g.nblocks + 255) / 256);
+    hipLaunchKernelGGL(k_fill_levels, dim3(blocks), dim3(256), 0, s, g.nblocks, levels);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- mip chain
+// Level statistics of one level-m cell from its 2^D children at level m-1
+// (LDS, FP64): mean and population variance (two-pass) in the pairwise order.
+__device__ inline double pair4(double a, double b, double c, double d) { return (a + b) + (c + d); }
+
+template <int D>
+__device__ inline double tree_sum(const double* q)
+{
+    if (D == 2) return pair4(q[0], q[1], q[2], q[3]);
+    return pair4(q[0], q[1], q[2], q[3]) + pair4(q[4], q[5], q[6], q[7]);
+}
+
+struct Lvl0 {
+    double xe, xc, le, lc;  // ln(eta ds0), ln(chi ds0), eta, chi
+};
+
+// MIP-0 value of voxel v for batch wavelength l: given (static model), or
+// the line model with each line at projected velocity u = 0 (vrule 0: the rest
+// frame used by velocity interpolation, Sect. 3.1) or at the shift within
+// [-|v|, |v|] closest to the line core, u* = clamp(c (1 - lam/lam0)) (vrule 1:
+// Core and Voigt, Sect. 3.2).
+__device__ inline void mip0_value(const Inputs& in, int model, int vrule, int dim, const LamBatch& lb,
+                                  int lam_global, int l, long long v, float& e, float& c)
+{
+    if (model == RT_MODEL_STATIC) {
+        e = in.eta[(long long)lam_global * in.nvox + v];
+        c = in.chi[(long long)lam_global * in.nvox + v];
+    } else {
+        float ee = in.eta_bg[v], cc = in.chi_bg[v];
+        float sp = 0.f;
+        if (vrule == 1) {
+            float q = 0.f;
+            for (int a = 0; a < dim; ++a) {
+                float va = in.vel[(long long)a * in.nvox + v];
+                q = fmaf(va, va, q);
+            }
+            sp = sqrtf(q);
+        }
+        for (int k = 0; k < lb.n_lines; ++k) {
+            long long o = (long long)k * in.nvox + v;
+            float idl = in.inv_dld[o];
+            double dl = lb.lam[l] - lb.lam0[k];
+            float x;
+            if (vrule == 1) {
+                double us = kCkms * (1.0 - lb.lam[l] / lb.lam0[k]);
+                us = us > sp ? sp : (us < -sp ? -sp : us);
+                x = (float)(dl + lb.lam0[k] * us / kCkms) * idl;
+            } else {
+                x = (float)dl * idl;
+            }
+            float phi = line_shape(lb.profile, x, in.damp[o], lb.lam[l], lb.lam0[k], idl);
+            ee += in.eta_star[o] * phi;
+            cc += in.chi_star[o] * phi;
+        }
+        e = ee;
+        c = cc;
+    }
+}
+
+template <int D, typename T>
+__global__ void k_build_static(Geo g, Inputs in, SceneBufs bufs, int model, int vrule, LamBatch lb, int lam_begin,
+                               double ds0, double T_iod, double tau_thin, int cap, int avg_mode,
+                               int write_values)
+{
+    extern __shared__ double lds[];
+    __shared__ int pass_all[kMaxLevels];
+    const int slot = blockIdx.x;
+    const int blk = bufs.active_list[slot];
+    const int tid = threadIdx.x;
+    const int B = g.B, L = g.n_levels;
+    int bc[3] = {blk % g.nb[0], (blk / g.nb[0]) % g.nb[1], blk / (g.nb[0] * g.nb[1])};
+    int lx = tid & (B - 1), ly = (tid >> g.log2B) & (B - 1), lz = D > 2 ? (tid >> (2 * g.log2B)) : 0;
+    long long v = (long long)(bc[0] * B + lx) +
+                  (long long)g.n[0] * ((long long)(bc[1] * B + ly) + (long long)g.n[1] * (bc[2] * B + lz));
+    T* vals = (T*)bufs.vals;
+    const long long rec0 = (long long)slot * g.cells;
+    int Lmax = L - 1;
+    if (cap >= 0 && cap < Lmax) Lmax = cap;
+    int lv_batch = 127;
+    // LDS: level m occupies cells_m * 4 doubles starting at lvl_off[m] * 4.
+    for (int l = 0; l < lb.nl; ++l) {
+        float e, c;
+        mip0_value(in, model, vrule, D, lb, lam_begin + l, l, v, e, c);
+        if (write_values) {
+            T* r = vals + ((rec0 + tid) * kLam + l) * 2;
+            r[0] = Codec<T>::enc(e);
+            r[1] = Codec<T>::enc(c);
+        }
+        double qe = (double)e * ds0, qc = (double)c * ds0;
+        double* s0 = lds + 4 * tid;
+        s0[0] = log(qe > 1e-300 ? qe : 1e-300);
+        s0[1] = log(qc > 1e-300 ? qc : 1e-300);
+        s0[2] = (double)e;
+        s0[3] = (double)c;
+        if (tid < kMaxLevels) pass_all[tid] = 1;
+        __syncthreads();
+        for (int m = 1; m < L; ++m) {
+            const int side = B >> m, sidec = B >> (m - 1);
+            const int ncell = D == 2 ? side * side : side * side * side;
+            if (tid < ncell) {
+                int cx = tid % side, cy = (tid / side) % side, cz = D > 2 ? tid / (side * side) : 0;
+                const double* sc = lds + 4 * g.lvl_off[m - 1];
+                int idx[8];
+                int k = 0;
+                for (int dz = 0; dz < (D > 2 ? 2 : 1); ++dz)
+                    for (int dy = 0; dy < 2; ++dy)
+                        for (int dx = 0; dx < 2; ++dx)
+                            idx[k++] = (2 * cx + dx) + sidec * ((2 * cy + dy) + sidec * (2 * cz + dz));
+                constexpr int nch = 1 << D;
+                double q[8];
+                double st[4];  // mean_e, mean_c, lin_e, lin_c
+                double var[2];
+                for (int f = 0; f < 2; ++f) {
+                    for (int j = 0; j < nch; ++j) q[j] = sc[4 * idx[j] + f];
+                    double mean = tree_sum<D>(q) / nch;
+                    for (int j = 0; j < nch; ++j) {
+                        double d = sc[4 * idx[j] + f] - mean;
+                        q[j] = d * d;
+                    }
+                    var[f] = tree_sum<D>(q) / nch;
+                    st[f] = mean;
+                }
+                for (int f = 2; f < 4; ++f) {
+                    for (int j = 0; j < nch; ++j) q[j] = sc[4 * idx[j] + f];
+                    st[f] = tree_sum<D>(q) / nch;
+                }
+                double le, lc;
+                if (avg_mode == RT_AVG_LOG) {
+                    le = exp(st[0]) / ds0;
+                    lc = exp(st[1]) / ds0;
+                } else {
+                    le = st[2];
+                    lc = st[3];
+                }
+                double* so = lds + 4 * (g.lvl_off[m] + tid);
+                so[0] = st[0];
+                so[1] = st[1];
+                so[2] = le;
+                so[3] = lc;
+                double iod_e = var[0] == 0.0 ? 0.0 : (st[0] == 0.0 ? __builtin_inf() : fabs(var[0] / st[0]));
+                double iod_c = var[1] == 0.0 ? 0.0 : (st[1] == 0.0 ? __builtin_inf() : fabs(var[1] / st[1]));
+                int thin = lc * (double)(1 << m) * ds0 < tau_thin;
+                int pass = thin || (iod_e <= T_iod && iod_c <= T_iod);
+                if (!pass) pass_all[m] = 0;
+                if (write_values) {
+                    T* r = vals + ((rec0 + g.lvl_off[m] + tid) * kLam + l) * 2;
+                    r[0] = Codec<T>::enc((float)le);
+                    r[1] = Codec<T>::enc((float)lc);
+                }
+            }
+            __syncthreads();
+        }
+        int lv = 0;
+        for (int m = 1; m <= Lmax; ++m) {
+            if (!pass_all[m]) break;
+            lv = m;
+        }
+        lv_batch = lv < lv_batch ? lv : lv_batch;
+        __syncthreads();
+    }
+    if (tid == 0) bufs.levels[blk] = (int8_t)(lb.nl > 0 ? lv_batch : 0);
+}
+
+hipError_t launch_build_static(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int model,
+                               int vrule, const LamBatch& lb, int lam_begin, double ds0, double T, double tau_thin,
+                               int cap, int avg_mode, int storage, int write_values, hipStream_t s)
+{
+    if (n_active == 0) return hipSuccess;
+    size_t shm = sizeof(double) * 4 * (size_t)g.cells;
+    dim3 grid((unsigned)n_active), block((unsigned)g.bvox);
+#define RT_LAUNCH_BS(DD, TT)                                                                              \
+    hipLaunchKernelGGL((k_build_static<DD, TT>), grid, block, shm, s, g, in, b, model, vrule, lb, lam_begin, ds0, \
+                       T, tau_thin, cap, avg_mode, write_values)
+    if (g.dim == 2) {
+        if (storage == RT_F32) RT_LAUNCH_BS(2, float);
+        else if (storage == RT_BF16) RT_LAUNCH_BS(2, __hip_bfloat16);
+        else RT_LAUNCH_BS(2, __half);
+    } else {
+        if (storage == RT_F32) RT_LAUNCH_BS(3, float);
+        else if (storage == RT_BF16) RT_LAUNCH_BS(3, __hip_bfloat16);
+        else RT_LAUNCH_BS(3, __half);
+    }
+#undef RT_LAUNCH_BS
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ states
+__global__ void k_pack_states(long long nb, int nw, const int8_t* levels, uint64_t* states)
+{
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= nw) return;
+    uint64_t word = 0;
+    for (int j = 0; j < kStatesPerWord; ++j) {
+        long long b = (long long)w * kStatesPerWord + j;
+        if (b >= nb) break;
+        uint64_t st = (uint64_t)(levels[b] + 1) & 7ull;
+        word |= st << (3 * j);
+    }
+    states[w] = word;
+}
+
+hipError_t launch_pack_states(const Geo& g, const int8_t* levels, uint64_t* states, hipStream_t s)
+{
+    unsigned blocks = (unsigned)((g.n_state_words + 255) / 256);
+    hipLaunchKernelGGL(k_pack_states, dim3(blocks), dim3(256), 0, s, g.nblocks, g.n_state_words, levels, states);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- cell readback
+template <typename T>
+__global__ void k_read_cells(Geo g, SceneBufs bufs, int n, const int32_t* cells, float* out)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int x = cells[4 * i], y = cells[4 * i + 1], z = cells[4 * i + 2], m = cells[4 * i + 3];
+    int bx = x >> g.log2B, by = y >> g.log2B, bz = z >> g.log2B;
+    long long blk = bx + (long long)g.nb[0] * (by + (long long)g.nb[1] * bz);
+    int slot = bufs.slot[blk];
+    float* o = out + (long long)i * kLam * 2;
+    if (slot < 0) {
+        for (int j = 0; j < 2 * kLam; ++j) o[j] = __builtin_nanf("");
+        return;
+    }
+    int side = g.B >> m;
+    int cx = (x & (g.B - 1)) >> m, cy = (y & (g.B - 1)) >> m, cz = (z & (g.B - 1)) >> m;
+    int local = cx + side * (cy + side * cz);
+    const T* r = (const T*)bufs.vals + (((long long)slot * g.cells + g.lvl_off[m] + local) * kLam) * 2;
+    for (int j = 0; j < 2 * kLam; ++j) o[j] = Codec<T>::dec(r[j]);
+}
+
+hipError_t launch_read_cells(const Geo& g, const SceneBufs& b, int storage, int n, const int32_t* cells,
+                             float* out, hipStream_t s)
+{
+    unsigned blocks = (unsigned)((n + 127) / 128);
+    if (storage == RT_F32) hipLaunchKernelGGL(k_read_cells<float>, dim3(blocks), dim3(128), 0, s, g, b, n, cells, out);
+    else if (storage == RT_BF16)
+        hipLaunchKernelGGL(k_read_cells<__hip_bfloat16>, dim3(blocks), dim3(128), 0, s, g, b, n, cells, out);
+    else hipLaunchKernelGGL(k_read_cells<__half>, dim3(blocks), dim3(128), 0, s, g, b, n, cells, out);
+    return hipGetLastError();
+}
+
+}  // namespace rt

@@ -1,0 +1,160 @@
+// Internal structures shared by the host API and the HIP kernels of the
+// formal-solution library.  Not part of the C ABI (see include/rt.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+#include "../../include/rt.h"
+
+namespace rt {
+
+constexpr int kLam = RT_LAM_BATCH;   // wavelengths per batch, kept in registers by the march
+constexpr int kMaxLines = RT_MAX_LINES;
+constexpr int kMaxLevels = RT_MAX_LEVELS;
+constexpr int kStatesPerWord = 21;   // 3-bit block states per 64-bit word
+constexpr double kCkms = 299792.458; // speed of light, km/s
+
+// Grid geometry of a scene.
+struct Geo {
+    int dim;
+    int n[3];
+    int B;            // block side
+    int log2B;
+    int nb[3];        // blocks per axis (1 beyond dim)
+    int n_levels;
+    int bvox;         // B^dim voxels per block
+    int cells;        // cells per block over all levels
+    int lvl_off[kMaxLevels + 1];  // first cell of each level inside a block record
+    long long nblocks;
+    int n_state_words;
+    int pad_;
+};
+
+// Wavelength constants of one batch (line model).  Doubles: the kernels form
+// lam - lam0 in FP64 before narrowing, which keeps the profile argument accurate.
+struct LamBatch {
+    int nl;        // wavelengths in this batch (<= kLam)
+    int n_lines;
+    int profile;   // rt_profile
+    int pad_;
+    double lam[kLam];
+    double lam0[kMaxLines];
+};
+
+// Device buffers owned by a scene.
+struct SceneBufs {
+    int32_t* morton;        // [nblocks] block ids in Morton order (all blocks)
+    uint8_t* active;        // [nblocks]
+    int32_t* slot;          // [nblocks] storage slot, -1 empty
+    int32_t* active_list;   // [nblocks] first n_active: block ids in Morton order
+    int32_t* n_active;      // [1]
+    int8_t* levels;         // [nblocks] current batch
+    uint64_t* states;       // [n_state_words]
+    void* vals;             // [n_active][cells][kLam][2] static emission values (storage dtype)
+    float4* vgrid;          // [n_active][cells] velocity grid: V, vbar (velocity interpolation)
+    float* vnodes;          // [n_active][cells][n_v][kLam][2] node values (velocity interpolation)
+    float* cav;             // [n_active][cells][cav_rec] line parameters (Core and Voigt)
+    unsigned long long* err;  // [2]: step-cap hits, first ray id (min)
+};
+
+// Inputs (caller-owned device pointers).
+struct Inputs {
+    const float* eta;
+    const float* chi;
+    const float* eta_star;
+    const float* chi_star;
+    const float* damp;
+    const float* inv_dld;
+    const float* eta_bg;
+    const float* chi_bg;
+    const float* vel;
+    const uint8_t* mask;
+    long long nvox;
+};
+
+// Record of Core-and-Voigt parameters per cell: per line eta*, chi*, a, 1/dlD;
+// then eta_bg, chi_bg; then vbar[3]; padded to a multiple of 4 floats.
+__host__ __device__ inline int cav_rec_floats(int n_lines)
+{
+    int r = 4 * n_lines + 2 + 3;
+    return (r + 3) & ~3;
+}
+
+// ---------------------------------------------------------------- dtype codecs
+template <typename T>
+struct Codec;
+template <>
+struct Codec<float> {
+    __device__ static float dec(float v) { return v; }
+    __device__ static float enc(float v) { return v; }
+};
+template <>
+struct Codec<__hip_bfloat16> {
+    __device__ static float dec(__hip_bfloat16 v) { return __bfloat162float(v); }
+    __device__ static __hip_bfloat16 enc(float v) { return __float2bfloat16(v); }  // round to nearest even
+};
+template <>
+struct Codec<__half> {
+    __device__ static float dec(__half v) { return __half2float(v); }
+    __device__ static __half enc(float v) { return __float2half_rn(v); }
+};
+
+inline size_t dtype_bytes(int dt) { return dt == RT_F32 ? 4 : 2; }
+
+// ------------------------------------------------------------------ launchers
+// build.hip
+hipError_t launch_classify(const Geo& g, const Inputs& in, int model, int n_lam, int n_lines, int dense,
+                           uint8_t* active, hipStream_t s);
+hipError_t launch_slots(const Geo& g, const int32_t* morton, const uint8_t* active, int32_t* slot,
+                        int32_t* active_list, int32_t* n_active, hipStream_t s);
+hipError_t launch_fill_levels(const Geo& g, int8_t* levels, hipStream_t s);
+hipError_t launch_build_static(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int model,
+                               int vrule, const LamBatch& lb, int lam_begin, double ds0, double T, double tau_thin,
+                               int cap, int avg_mode, int storage, int write_values, hipStream_t s);
+hipError_t launch_pack_states(const Geo& g, const int8_t* levels, uint64_t* states, hipStream_t s);
+hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, hipStream_t s);
+hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
+                                  const LamBatch& lb, int n_v, double ds0, int avg_mode, hipStream_t s);
+hipError_t launch_cav_chain(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_lines,
+                            double ds0, int avg_mode, hipStream_t s);
+hipError_t launch_read_cells(const Geo& g, const SceneBufs& b, int storage, int n, const int32_t* cells,
+                             float* out, hipStream_t s);
+
+// march.hip
+struct TraceLaunch {
+    Geo g;
+    const uint64_t* states;
+    const int32_t* slot;
+    const void* vals;
+    const float4* vgrid;
+    const float* vnodes;
+    const float* cav;
+    const float* dirs;
+    int n_dir;
+    int mode;
+    int max_level;
+    int step_cap;
+    int graded;                      // nonzero when level_dist has a nonzero entry
+    float level_dist[kMaxLevels];    // distance-graded level cap
+    const int32_t* probes;   // nullable
+    const int32_t* active_list;
+    long long n_probes;
+    float* I;
+    float I0;
+    float ds0;
+    int emission;
+    int storage;
+    int n_v;
+    int cav_rec;
+    LamBatch lb;
+    unsigned long long* stats;
+    unsigned long long* err;
+};
+hipError_t launch_trace(const TraceLaunch& t, hipStream_t s);
+hipError_t launch_debug_visited(const TraceLaunch& t, int probe_vox, float wx, float wy, float wz, int cap,
+                                int32_t* cells, double* tt, int32_t* count, hipStream_t s);
+
+}  // namespace rt

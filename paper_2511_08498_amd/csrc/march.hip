@@ -1,0 +1,586 @@
+// Formal-solution march: hierarchical DDA over the adapted brick grid
+// (Sect. 2.3, Alg. 1) with the piecewise-constant update of Eq. RteIntegral
+// applied front-to-back for a batch of 8 wavelengths held in registers.
+//
+// Traversal decisions are exact.  The ray is x(t) = p - t w with p a voxel
+// centre, so 2 |p_a - k| is an odd integer for every integer plane k.  The
+// crossing time of axis a is d_a / |w_a| (d_a = |p_a - k_a|); "axis a before
+// axis b" is decided by comparing d_a |w_b| with d_b |w_a| in FP64, where both
+// products are exact (14-bit integer x 24-bit mantissa).  t itself is only
+// used for segment lengths.  Ties (the ray through a cell corner) step every
+// tied axis at once and emit no zero-length segment; at a change of MIP level
+// the non-crossing axes are re-located with the same exact predicate, and a
+// position exactly on a plane belongs to the cell the ray moves into.  This
+// replaces the two floating-point nudges of Sect. 2.3.1: t is recomputed
+// from integer plane indices every step, so it never drifts.
+//
+// Block states (3 bits, 21 per 64-bit word, Sect. 2.3.1) are staged in LDS
+// for the whole grid; the storage slot of a block is read once per block
+// visit and kept in a register (the "cached block index" of Sect. 2.3.1).
+#include "common.h"
+#include "profile.h"
+
+namespace rt {
+
+__device__ __forceinline__ int block_level(const uint64_t* sts, long long b, int mode, int maxl)
+{
+    int w = (int)(b / kStatesPerWord);
+    int sh = 3 * (int)(b - (long long)w * kStatesPerWord);
+    int s = (int)((sts[w] >> sh) & 7ull);
+    if (s == 0) return -1;
+    int l = mode == RT_TRACE_LEVEL0 ? 0 : s - 1;
+    return l < maxl ? l : maxl;
+}
+
+// Fine cell (multiple of nvs inside [c0, c0 + vs)) containing x_a(t*) with
+// t* = d2s / (2 |w_s|); on a plane, the cell the ray moves into.
+__device__ __noinline__ int fine_cell(int p2a, double wa, double aws, int d2s, int c0, int vs, int nvs, int sta)
+{
+    const double rhs = (double)d2s * wa;  // exact
+    double xa = 0.5 * (double)p2a - ((double)d2s * 0.5 / aws) * wa;
+    int j = ((int)floor(xa)) & ~(nvs - 1);
+    if (j < c0) j = c0;
+    if (j > c0 + vs - nvs) j = c0 + vs - nvs;
+    // x_a(t*) >= j  <=>  (p2a - 2 j) |w_s| >= d2s w_a   (exact products)
+    while (j + nvs <= c0 + vs - nvs && (double)(p2a - 2 * (j + nvs)) * aws >= rhs) j += nvs;
+    while (j > c0 && !((double)(p2a - 2 * j) * aws >= rhs)) j -= nvs;
+    if (sta < 0 && j > c0 && (double)(p2a - 2 * j) * aws == rhs) j -= nvs;
+    return j;
+}
+
+struct Counters {
+    unsigned segs, empty, lvlchg;
+};
+
+// Distance-graded cap at a block entered at t = d2 / (2 |w_s|): the largest m
+// with level_dist[1..m] <= t, decided exactly as d2/2 >= level_dist[m] |w_s|.
+__device__ __forceinline__ int graded_cap(const float* ld, int nlev, int d2, double aws)
+{
+    int cap = 0;
+    for (int m = 1; m < nlev; ++m) {
+        if (!((double)d2 * 0.5 >= (double)ld[m] * aws)) break;
+        cap = m;
+    }
+    return cap;
+}
+
+// Traverses the adapted grid from voxel centre pv upwind along -w.  Calls
+// vis.seg(c, level, block, t0, t1) for every non-empty cell in order of
+// increasing t.  Returns 0 when the ray left the grid, 1 at the step cap.
+// With `graded`, a block's level is also capped by the path length at which
+// the ray enters it (ld: level_dist).
+template <int D, class Vis>
+__device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode, int maxl, int graded,
+                                    const float* ld, const int* pv, const float* wf, int step_cap, Vis& vis,
+                                    Counters& cnt)
+{
+    int p2[3], st[3], c[3], k[3], bc[3];
+    double aw[3], iw[3], ws[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        p2[a] = 1;
+        st[a] = 0;
+        c[a] = 0;
+        k[a] = 0;
+        bc[a] = 0;
+        aw[a] = 0.0;
+        iw[a] = 0.0;
+        ws[a] = 0.0;
+    }
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        p2[a] = 2 * pv[a] + 1;
+        ws[a] = (double)wf[a];
+        aw[a] = fabs(ws[a]);
+        iw[a] = aw[a] > 0.0 ? 1.0 / aw[a] : 0.0;
+        st[a] = wf[a] > 0.f ? -1 : (wf[a] < 0.f ? 1 : 0);
+        bc[a] = pv[a] >> g.log2B;
+    }
+    long long blk = bc[0] + (long long)g.nb[0] * (bc[1] + (long long)g.nb[1] * bc[2]);
+    int cap0 = maxl;
+    if (graded) {
+        int c0 = 0;
+        for (int m = 1; m < g.n_levels; ++m) {
+            if (!(ld[m] <= 0.f)) break;
+            c0 = m;
+        }
+        cap0 = c0 < maxl ? c0 : maxl;
+    }
+    int lvl = block_level(sts, blk, mode, cap0);
+    int vs = lvl < 0 ? g.B : (1 << lvl);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        c[a] = pv[a] & ~(vs - 1);
+        k[a] = c[a] + (st[a] > 0 ? vs : 0);
+    }
+    double t = 0.0;
+    for (int step = 0; step < step_cap; ++step) {
+        int s0 = -1, d2s0 = 0;
+        unsigned tie = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (st[a] == 0) continue;
+            int d2 = abs(p2[a] - 2 * k[a]);
+            if (s0 < 0) {
+                s0 = a;
+                d2s0 = d2;
+                tie = 1u << a;
+            } else {
+                double lhs = (double)d2 * aw[s0];
+                double rhs = (double)d2s0 * aw[a];
+                if (lhs < rhs) {
+                    s0 = a;
+                    d2s0 = d2;
+                    tie = 1u << a;
+                } else if (lhs == rhs) {
+                    tie |= 1u << a;
+                }
+            }
+        }
+        const double tn = (double)d2s0 * 0.5 * iw[s0];
+        if (lvl >= 0) {
+            vis.seg(c, lvl, blk, t, tn);
+            ++cnt.segs;
+        } else {
+            ++cnt.empty;
+        }
+        t = tn;
+        int kc[3] = {0, 0, 0};
+        bool out = false, bchg = false;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (!((tie >> a) & 1u)) continue;
+            kc[a] = k[a];
+            c[a] += st[a] * vs;
+            k[a] += st[a] * vs;
+            if (c[a] < 0 || c[a] >= g.n[a]) out = true;
+            int nbc = c[a] >> g.log2B;
+            if (nbc != bc[a]) {
+                bchg = true;
+                bc[a] = nbc;
+            }
+        }
+        if (out) return 0;
+        if (bchg) {
+            blk = bc[0] + (long long)g.nb[0] * (bc[1] + (long long)g.nb[1] * bc[2]);
+            int capb = maxl;
+            if (graded) {
+                int cg = graded_cap(ld, g.n_levels, d2s0, aw[s0]);
+                capb = cg < maxl ? cg : maxl;
+            }
+            int nl = block_level(sts, blk, mode, capb);
+            if (nl != lvl) {
+                ++cnt.lvlchg;
+                int nvs = nl < 0 ? g.B : (1 << nl);
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    if ((tie >> a) & 1u) c[a] = (st[a] > 0 ? kc[a] : kc[a] - 1) & ~(nvs - 1);
+                    else if (st[a] == 0) c[a] = pv[a] & ~(nvs - 1);
+                    else if (nvs >= vs) c[a] &= ~(nvs - 1);
+                    else c[a] = fine_cell(p2[a], ws[a], aw[s0], d2s0, c[a], vs, nvs, st[a]);
+                    k[a] = c[a] + (st[a] > 0 ? nvs : 0);
+                }
+                lvl = nl;
+                vs = nvs;
+            }
+        }
+    }
+    return 1;
+}
+
+// ------------------------------------------------------------ RTE update
+// One segment, one wavelength, front to back:
+//   I += T (eta dt) g(tau),  T *= exp(-tau),  g(tau) = (1 - exp(-tau)) / tau,
+// which is S (1 - exp(-tau)) with S = eta/chi and stays finite at chi = 0.
+// g uses its Taylor series below tau = 1/16 (no cancellation in 1 - exp).
+__device__ __forceinline__ void rte_step(float& I, float& Tr, float eta, float chi, float dt)
+{
+    float tau = chi * dt;
+    float e = __expf(-tau);
+    float gp = fmaf(tau, fmaf(tau, fmaf(tau, fmaf(tau, fmaf(tau, -1.0f / 720.0f, 1.0f / 120.0f), -1.0f / 24.0f),
+                                        1.0f / 6.0f), -0.5f), 1.0f);
+    float gd = (1.0f - e) * __builtin_amdgcn_rcpf(tau);
+    float gg = tau < 0.0625f ? gp : gd;
+    I = fmaf(Tr * (eta * dt), gg, I);
+    Tr *= e;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rec(const T* r, float* e, float* c);
+
+template <>
+__device__ __forceinline__ void load_rec<float>(const float* r, float* e, float* c)
+{
+    const float4* r4 = (const float4*)r;
+#pragma unroll
+    for (int q = 0; q < kLam / 2; ++q) {
+        float4 v = r4[q];
+        e[2 * q] = v.x;
+        c[2 * q] = v.y;
+        e[2 * q + 1] = v.z;
+        c[2 * q + 1] = v.w;
+    }
+}
+
+__device__ __forceinline__ float bf16_lo(unsigned u) { return __uint_as_float(u << 16); }
+__device__ __forceinline__ float bf16_hi(unsigned u) { return __uint_as_float(u & 0xffff0000u); }
+
+template <>
+__device__ __forceinline__ void load_rec<__hip_bfloat16>(const __hip_bfloat16* r, float* e, float* c)
+{
+    const uint4* r4 = (const uint4*)r;
+#pragma unroll
+    for (int q = 0; q < kLam / 4; ++q) {
+        uint4 v = r4[q];
+        unsigned u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            e[4 * q + j] = bf16_lo(u[j]);
+            c[4 * q + j] = bf16_hi(u[j]);
+        }
+    }
+}
+
+template <>
+__device__ __forceinline__ void load_rec<__half>(const __half* r, float* e, float* c)
+{
+    const uint4* r4 = (const uint4*)r;
+#pragma unroll
+    for (int q = 0; q < kLam / 4; ++q) {
+        uint4 v = r4[q];
+        unsigned u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            __half2 h = *reinterpret_cast<__half2*>(&u[j]);
+            float2 f = __half22float2(h);
+            e[4 * q + j] = f.x;
+            c[4 * q + j] = f.y;
+        }
+    }
+}
+
+__device__ __forceinline__ int local_index(const Geo& g, const int* c, int lvl, int D)
+{
+    int sl = g.log2B - lvl;
+    int lx = (c[0] & (g.B - 1)) >> lvl, ly = (c[1] & (g.B - 1)) >> lvl;
+    int li = lx + (ly << sl);
+    if (D > 2) li += ((c[2] & (g.B - 1)) >> lvl) << (2 * sl);
+    return li;
+}
+
+// ------------------------------------------------------------- visitors
+template <int D, typename T>
+struct VisStatic {
+    const TraceLaunch* tl;
+    long long cur_blk;
+    long long base;
+    float dsf;
+    float I[kLam], Tr[kLam];
+    __device__ void init(const TraceLaunch* t, const float*)
+    {
+        tl = t;
+        cur_blk = -1;
+        base = 0;
+        dsf = t->ds0;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            I[l] = 0.f;
+            Tr[l] = 1.f;
+        }
+    }
+    __device__ __forceinline__ void seg(const int* c, int lvl, long long blk, double t0, double t1)
+    {
+        if (blk != cur_blk) {
+            cur_blk = blk;
+            base = (long long)tl->slot[blk] * tl->g.cells;
+        }
+        const T* r = (const T*)tl->vals + (base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D)) * (kLam * 2);
+        float e[kLam], x[kLam];
+        load_rec<T>(r, e, x);
+        float dt = (float)(t1 - t0) * dsf;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) rte_step(I[l], Tr[l], e[l], x[l], dt);
+    }
+};
+
+template <int D>
+struct VisVelinterp {
+    const TraceLaunch* tl;
+    long long cur_blk;
+    long long base;
+    float dsf;
+    float w[3];
+    float I[kLam], Tr[kLam];
+    __device__ void init(const TraceLaunch* t, const float* wf)
+    {
+        tl = t;
+        cur_blk = -1;
+        base = 0;
+        dsf = t->ds0;
+        w[0] = wf[0];
+        w[1] = wf[1];
+        w[2] = D > 2 ? wf[2] : 0.f;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            I[l] = 0.f;
+            Tr[l] = 1.f;
+        }
+    }
+    __device__ __forceinline__ void seg(const int* c, int lvl, long long blk, double t0, double t1)
+    {
+        if (blk != cur_blk) {
+            cur_blk = blk;
+            base = (long long)tl->slot[blk] * tl->g.cells;
+        }
+        long long cell = base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D);
+        float4 vg = tl->vgrid[cell];  // V, vbar
+        float u = vg.y * w[0] + vg.z * w[1] + (D > 2 ? vg.w * w[2] : 0.f);
+        const int nv = tl->n_v;
+        int kn = 0;
+        float wt = 0.f;
+        if (vg.x > 0.f) {
+            float f = (u + vg.x) / (2.0f * vg.x) * (float)(nv - 1);
+            kn = (int)floorf(f);
+            kn = kn < 0 ? 0 : (kn > nv - 2 ? nv - 2 : kn);
+            wt = f - (float)kn;
+        }
+        const float* r0 = tl->vnodes + (cell * nv + kn) * (kLam * 2);
+        float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
+        load_rec<float>(r0, e0, x0);
+        load_rec<float>(r0 + kLam * 2, e1, x1);
+        float dt = (float)(t1 - t0) * dsf;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            float ee = fmaf(wt, e1[l] - e0[l], e0[l]);
+            float xx = fmaf(wt, x1[l] - x0[l], x0[l]);
+            rte_step(I[l], Tr[l], ee, xx, dt);
+        }
+    }
+};
+
+template <int D>
+struct VisCav {
+    const TraceLaunch* tl;
+    long long cur_blk;
+    long long base;
+    float dsf;
+    float w[3];
+    float dl[kLam][kMaxLines];  // lam - lam0
+    float k0[kMaxLines];        // lam0 / c
+    float rr[kLam][kMaxLines];  // lam / lam0
+    float I[kLam], Tr[kLam];
+    __device__ void init(const TraceLaunch* t, const float* wf)
+    {
+        tl = t;
+        cur_blk = -1;
+        base = 0;
+        dsf = t->ds0;
+        w[0] = wf[0];
+        w[1] = wf[1];
+        w[2] = D > 2 ? wf[2] : 0.f;
+#pragma unroll
+        for (int k = 0; k < kMaxLines; ++k) {
+            k0[k] = (float)(t->lb.lam0[k] / kCkms);
+#pragma unroll
+            for (int l = 0; l < kLam; ++l) {
+                dl[l][k] = (float)(t->lb.lam[l] - t->lb.lam0[k]);
+                rr[l][k] = (float)(t->lb.lam[l] / t->lb.lam0[k]);
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            I[l] = 0.f;
+            Tr[l] = 1.f;
+        }
+    }
+    __device__ __forceinline__ void seg(const int* c, int lvl, long long blk, double t0, double t1)
+    {
+        if (blk != cur_blk) {
+            cur_blk = blk;
+            base = (long long)tl->slot[blk] * tl->g.cells;
+        }
+        long long cell = base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D);
+        const float4* r = (const float4*)(tl->cav + cell * tl->cav_rec);
+        const int nln = tl->lb.n_lines;
+        float ls[kMaxLines][4];
+#pragma unroll
+        for (int k = 0; k < kMaxLines; ++k) {
+            if (k < nln) {
+                float4 q = r[k];
+                ls[k][0] = q.x;
+                ls[k][1] = q.y;
+                ls[k][2] = q.z;
+                ls[k][3] = q.w;
+            }
+        }
+        float4 bgv = r[nln];  // eta_bg, chi_bg, vx, vy
+        float vz = 0.f;
+        if (D > 2) vz = ((const float*)r)[4 * nln + 4];
+        float u = bgv.z * w[0] + bgv.w * w[1] + vz * w[2];
+        float dt = (float)(t1 - t0) * dsf;
+        const bool voigt = tl->lb.profile == RT_PROFILE_VOIGT;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            float ee = bgv.x, xx = bgv.y;
+#pragma unroll
+            for (int k = 0; k < kMaxLines; ++k) {
+                if (k < nln) {
+                    float x = fmaf(k0[k], u, dl[l][k]) * ls[k][3];
+                    float phi;
+                    if (!voigt) {
+                        phi = __expf(-x * x);
+                    } else {
+                        float r2 = rr[l][k];
+                        phi = voigt_h(ls[k][2] * r2 * r2, x) * ls[k][3] * (0.56418958354775628f / r2);
+                    }
+                    ee = fmaf(ls[k][0], phi, ee);
+                    xx = fmaf(ls[k][1], phi, xx);
+                }
+            }
+            rte_step(I[l], Tr[l], ee, xx, dt);
+        }
+    }
+};
+
+// ------------------------------------------------------------ trace kernel
+template <int D, class Vis>
+__global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
+{
+    extern __shared__ uint64_t sts[];
+    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
+    __syncthreads();
+    // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; give
+    // each XCD a contiguous range of (direction, probe tile) work.
+    const unsigned G = gridDim.x, wg = blockIdx.x;
+    const unsigned q = G / 8u, r = G % 8u, xcd = wg % 8u, i = wg / 8u;
+    const unsigned lwg = xcd < r ? xcd * (q + 1u) + i : r * (q + 1u) + (xcd - r) * q + i;
+    const long long tiles = (t.n_probes + 63) / 64;
+    const long long wave = (long long)lwg * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const long long dir = wave / tiles;
+    const long long probe = (wave - dir * tiles) * 64 + lane;
+    if (dir >= t.n_dir || probe >= t.n_probes) return;
+
+    int pv[3] = {0, 0, 0};
+    if (t.probes) {
+        long long v = t.probes[probe];
+        pv[0] = (int)(v % t.g.n[0]);
+        pv[1] = (int)((v / t.g.n[0]) % t.g.n[1]);
+        pv[2] = (int)(v / ((long long)t.g.n[0] * t.g.n[1]));
+    } else {
+        long long slot = probe >> (D * t.g.log2B);
+        int local = (int)(probe & (t.g.bvox - 1));
+        int blk = t.active_list[slot];
+        int bcx = blk % t.g.nb[0], bcy = (blk / t.g.nb[0]) % t.g.nb[1], bcz = blk / (t.g.nb[0] * t.g.nb[1]);
+        pv[0] = bcx * t.g.B + (local & (t.g.B - 1));
+        pv[1] = bcy * t.g.B + ((local >> t.g.log2B) & (t.g.B - 1));
+        if (D > 2) pv[2] = bcz * t.g.B + (local >> (2 * t.g.log2B));
+    }
+    float wf[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < D; ++a) wf[a] = t.dirs[dir * D + a];
+
+    Vis vis;
+    vis.init(&t, wf);
+    Counters cnt = {0, 0, 0};
+    int capped = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+    const int nl = t.lb.nl;
+#pragma unroll
+    for (int l = 0; l < kLam; ++l) {
+        if (l < nl) t.I[((long long)dir * nl + l) * t.n_probes + probe] = fmaf(vis.Tr[l], t.I0, vis.I[l]);
+    }
+    if (t.stats) {
+        atomicAdd(&t.stats[0], (unsigned long long)cnt.segs);
+        atomicAdd(&t.stats[1], 1ull);
+        atomicAdd(&t.stats[2], (unsigned long long)cnt.empty);
+        atomicAdd(&t.stats[3], (unsigned long long)cnt.lvlchg);
+    }
+    if (capped) {
+        atomicAdd(&t.err[0], 1ull);
+        atomicMin(&t.err[1], (unsigned long long)(dir * t.n_probes + probe));
+    }
+}
+
+template <int D, class Vis>
+static hipError_t launch_one(const TraceLaunch& t, hipStream_t s)
+{
+    long long tiles = (t.n_probes + 63) / 64;
+    long long waves = tiles * t.n_dir;
+    long long wgs = (waves + 3) / 4;
+    if (wgs <= 0) return hipSuccess;
+    size_t shm = sizeof(uint64_t) * (size_t)t.g.n_state_words;
+    hipLaunchKernelGGL((k_trace<D, Vis>), dim3((unsigned)wgs), dim3(256), shm, s, t);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)
+{
+    if (t.emission == RT_EMIS_STATIC) {
+        if (t.g.dim == 2) {
+            if (t.storage == RT_F32) return launch_one<2, VisStatic<2, float>>(t, s);
+            if (t.storage == RT_BF16) return launch_one<2, VisStatic<2, __hip_bfloat16>>(t, s);
+            return launch_one<2, VisStatic<2, __half>>(t, s);
+        }
+        if (t.storage == RT_F32) return launch_one<3, VisStatic<3, float>>(t, s);
+        if (t.storage == RT_BF16) return launch_one<3, VisStatic<3, __hip_bfloat16>>(t, s);
+        return launch_one<3, VisStatic<3, __half>>(t, s);
+    }
+    if (t.emission == RT_EMIS_VELINTERP) {
+        if (t.g.dim == 2) return launch_one<2, VisVelinterp<2>>(t, s);
+        return launch_one<3, VisVelinterp<3>>(t, s);
+    }
+    if (t.g.dim == 2) return launch_one<2, VisCav<2>>(t, s);
+    return launch_one<3, VisCav<3>>(t, s);
+}
+
+// --------------------------------------------------- debug: visited cells
+struct VisRecord {
+    int32_t* cells;
+    double* tt;
+    int cap;
+    int n;
+    __device__ void seg(const int* c, int lvl, long long, double t0, double t1)
+    {
+        if (n < cap) {
+            cells[4 * n] = c[0];
+            cells[4 * n + 1] = c[1];
+            cells[4 * n + 2] = c[2];
+            cells[4 * n + 3] = lvl;
+            tt[2 * n] = t0;
+            tt[2 * n + 1] = t1;
+        }
+        ++n;
+    }
+};
+
+template <int D>
+__global__ void k_debug_visited(TraceLaunch t, int probe_vox, float wx, float wy, float wz, int cap,
+                                int32_t* cells, double* tt, int32_t* count)
+{
+    extern __shared__ uint64_t sts[];
+    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    int pv[3] = {(int)(probe_vox % t.g.n[0]), (int)((probe_vox / t.g.n[0]) % t.g.n[1]),
+                 (int)(probe_vox / (t.g.n[0] * t.g.n[1]))};
+    float wf[3] = {wx, wy, wz};
+    VisRecord vis{cells, tt, cap, 0};
+    Counters cnt = {0, 0, 0};
+    int capped = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+    *count = capped ? -1 : vis.n;
+}
+
+hipError_t launch_debug_visited(const TraceLaunch& t, int probe_vox, float wx, float wy, float wz, int cap,
+                                int32_t* cells, double* tt, int32_t* count, hipStream_t s)
+{
+    size_t shm = sizeof(uint64_t) * (size_t)t.g.n_state_words;
+    if (t.g.dim == 2)
+        hipLaunchKernelGGL(k_debug_visited<2>, dim3(1), dim3(64), shm, s, t, probe_vox, wx, wy, wz, cap, cells, tt,
+                           count);
+    else
+        hipLaunchKernelGGL(k_debug_visited<3>, dim3(1), dim3(64), shm, s, t, probe_vox, wx, wy, wz, cap, cells, tt,
+                           count);
+    return hipGetLastError();
+}
+
+}  // namespace rt

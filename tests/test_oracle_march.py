@@ -185,6 +185,32 @@ def test_adapted_cells_match_exact(orc, case):
                 assert to[i] == pytest.approx(float(b), rel=1e-14, abs=1e-14)
 
 
+@pytest.mark.parametrize("sched", [(0, 6, 24, 96, 384), (0, 2, 8, 32), (0, 0, 5, 5)])
+def test_graded_cap_matches_exact(orc, sched):
+    """Distance-graded cap: a block's level is capped by the path length at which the ray enters it."""
+    rng = np.random.default_rng(11)
+    n, B = (64, 64), 16
+    lv = rng.integers(-1, 5, size=16).astype(np.int8)
+    sc = static_scene(n, B, np.zeros((1,) + n), np.zeros((1,) + n), n_levels=5)
+    s = orc.Scene(sc)
+    s.set_level_dist(sched)
+    for w in _rand_dirs(rng, 2, 10):
+        for _ in range(5):
+            pv = (int(rng.integers(0, 64)), int(rng.integers(0, 64)))
+            cells, lvl, ti, to = orc.ray_segments(s, lv, pv, w)
+            ex = adapted_cells_exact(2, n, B, lv, pv, w, level_dist=sched)
+            assert len(ex) == len(cells)
+            for i, (cc, L, a, b) in enumerate(ex):
+                assert list(cells[i]) == cc and lvl[i] == L
+    # the probe's own block is never coarsened when level_dist[1] > 0
+    if sched[1] > 0:
+        for _ in range(50):
+            pv = (int(rng.integers(0, 64)), int(rng.integers(0, 64)))
+            cells, lvl, ti, to = orc.ray_segments(s, lv, pv, np.array([0.6, 0.8], np.float32))
+            if len(lvl) and ti[0] == 0.0:
+                assert lvl[0] == 0
+
+
 def test_single_resolution_is_aw87(orc):
     """All levels 0 and no empty blocks: the adapted list is the dense list (Sect. 2.3)."""
     rng = np.random.default_rng(5)
