@@ -70,6 +70,10 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--compare-batches", type=int, default=4)
     ap.add_argument("--sample-seconds", type=float, default=15.0)
+    ap.add_argument("--batches", type=int, default=0,
+                    help="profiling only: trace the first N wavelength batches per step (0 = all)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="profiling only: first run a device-to-device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus %d requested); the path shards by "
@@ -90,6 +94,17 @@ def main():
     log("scene generated in %.1fs" % (time.time() - t_gen))
     n_lam = sc["lam"].size
     nb_lam = n_lam // 8
+    if args.batches:
+        nb_lam = min(nb_lam, args.batches)
+        n_lam = 8 * nb_lam
+    if args.copy_probe_mb:
+        src = torch.ones(args.copy_probe_mb * 2 ** 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB read + %d MiB written per copy, 3 copies" % (args.copy_probe_mb, args.copy_probe_mb))
+        del src, dst
     dirs = torch.from_numpy(sc["dirs"]).to(dev)
     n_dir = dirs.shape[0]
     level_dist = None if args.no_grading else rt.CASCADE_LEVEL_DIST
@@ -217,9 +232,10 @@ def main():
             return k, d, ref, int(nseg.sum()), time.perf_counter() - ta
 
         lam_all = list(range(n_lam))
-        _, _, _, ns_cal, dt_cal = oracle_run(64, lam_all)
+        # calibrate on 512 pairs, then size the sample to about --sample-seconds of CPU time
+        _, _, _, ns_cal, dt_cal = oracle_run(512, lam_all)
         rate = ns_cal * n_lam / max(dt_cal, 1e-3)
-        npairs = int(min(2 ** 15, max(256, 64 * args.sample_seconds / max(dt_cal, 1e-3))))
+        npairs = int(min(probes.size, max(512, 512 * args.sample_seconds / max(dt_cal, 1e-3))))
         k, d, ref, nseg, dt = oracle_run(npairs, lam_all)
         cpu_rate = nseg * n_lam / dt
         out["cpu_baseline"] = {"value": cpu_rate / 1e9, "unit": "Gsegments/s", "cores": nthreads, "kind": "oracle",

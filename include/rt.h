@@ -281,6 +281,173 @@ rt_status rt_debug_visited(const rt_scene* scene, const rt_trace_params* params,
                            const float* h_dir, int32_t cap, int32_t* h_cells, double* h_t, int32_t* h_count,
                            void* stream);
 
+/*
+ * ---------------------------------------------------------------- batching
+ * Many scenes of uneven size traced in one persistent launch with a
+ * work-stealing queue (the batched form of the formal solution; each job is
+ * exactly rt_trace over all probes of its scene's current batch).
+ *
+ * A job traces one scene (static emission) for n_dir directions over all of
+ * its probes.  d_I is device float [n_dir][nl][n_probes] (nl = wavelengths of
+ * the scene's current batch, n_probes = rt_scene_info.n_probes); params as
+ * for rt_trace (d_stats is ignored).
+ */
+typedef struct rt_batch_job {
+    const rt_scene* scene;
+    const float* d_dirs;
+    int32_t n_dir;
+    int32_t reserved_;
+    float* d_I;
+    rt_trace_params params;
+} rt_batch_job;
+
+/*
+ * Launch shape of the persistent kernel (0 selects the default):
+ *   wg_waves       waves per workgroup: 1, 2, 4 (default) or 8;
+ *   wgs_per_cu     resident workgroups per compute unit (default 2);
+ *   tiles_per_pop  64-probe tiles claimed per atomic pop (default 1);
+ *   order          0 (default): costliest job first (cost ~ n_dir x n_probes x
+ *                  sum of grid sides); 1: the given job order;
+ *   d_claims       optional device uint32 [total tiles], incremented once per
+ *                  processed tile (lets tests check that every tile is taken
+ *                  exactly once).
+ */
+typedef struct rt_batch_params {
+    int32_t wg_waves;
+    int32_t wgs_per_cu;
+    int32_t tiles_per_pop;
+    int32_t order;
+    unsigned int* d_claims;
+} rt_batch_params;
+
+typedef struct rt_batch rt_batch;
+
+/* Validates the jobs, uploads the job table (synchronises `stream`) and sizes
+ * the queue.  The scenes must have a built batch; their storage is read at
+ * every rt_batch_run, so rebuilding a scene for another batch of the same
+ * size is picked up by the next run.  Errors: RT_E_ARG, RT_E_STATE, RT_E_UNSUPPORTED
+ * (non-static emission), RT_E_HIP. */
+rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_batch_params* params, void* stream,
+                          rt_batch** out);
+
+/* Runs the batch: a queue-reset kernel and the persistent kernel.  Kernels
+ * only (no allocation, copy or memset), so it can be captured in a graph. */
+rt_status rt_batch_run(const rt_batch* batch, void* stream);
+
+/* Total 64-probe tiles of the batch (the queue length). */
+rt_status rt_batch_tiles(const rt_batch* batch, int64_t* h_tiles);
+
+/* Step-cap hits of the batch's runs (synchronising). */
+rt_status rt_batch_device_error(const rt_batch* batch, rt_device_err* h_err);
+
+void rt_batch_destroy(rt_batch* batch);
+
+/*
+ * Autotuner: times every launch shape of a small candidate grid (waves per
+ * workgroup x workgroups per CU x tiles per pop) on the given jobs, `reps`
+ * runs each after one warm-up, and returns the fastest in *h_best with its
+ * mean time in *h_best_ms.  Synchronising; writes the jobs' outputs.
+ */
+rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t reps, void* stream,
+                            rt_batch_params* h_best, float* h_best_ms);
+
+/*
+ * Graph capture of work issued on `stream` (e.g. builds + rt_batch_run for a
+ * sequence of wavelength batches), replayed with rt_graph_launch.
+ */
+typedef struct rt_graph rt_graph;
+rt_status rt_graph_begin(void* stream);
+rt_status rt_graph_end(void* stream, rt_graph** out);
+rt_status rt_graph_launch(const rt_graph* graph, void* stream);
+void rt_graph_destroy(rt_graph* graph);
+
+/*
+ * ------------------------------------------------- neural radiance cache
+ * Truncated march: every ray is marched to path length t_trunc (index units);
+ * the part beyond is the far field, to be supplied by a learned cache (the
+ * neural radiance cache form of the formal solution).  Outputs, for rays
+ * (dir, probe) and batch wavelengths l:
+ *   d_I_near [n_dir][nl][n_probes]  near-field intensity (for rays that need no
+ *                                   query, the complete intensity incl. I0)
+ *   d_T_near [n_dir][nl][n_probes]  transmittance to the truncation point (0 when
+ *                                   no query is needed)
+ *   d_I_far  [n_dir][nl][n_probes]  gen != 0 only: exact far-field intensity
+ *                                   arriving at the truncation point (incl. I0)
+ *   d_feat   [n_dir][n_probes][4]   truncation point x, y, z (index space; z = 0.5
+ *                                   in 2D) and 1 if the ray needs a query
+ *   d_fstat  [n_dir][nl][n_probes][4] level statistics of the cell there: mean
+ *                                   and variance of ln(chi ds0), of ln(eta ds0)
+ * The complete intensity is I = I_near + T_near I_far.  The truncation point
+ * is t_trunc, moved to the entry of the next non-empty cell when t_trunc lies
+ * in empty space (the far field is the same).  Rays that leave the grid
+ * before it need no query.  In inference mode (gen = 0) a ray whose
+ * truncation block is flagged in d_fallback (uint8 [n_blocks], nullable)
+ * keeps marching to the boundary and needs no query.  Asynchronous.
+ */
+rt_status rt_trace_truncated(const rt_scene* scene, const rt_trace_params* params, float t_trunc, int32_t gen,
+                             const uint8_t* d_fallback, const float* d_dirs, int32_t n_dir, const int32_t* d_probes,
+                             int64_t n_probes, float* d_I_near, float* d_T_near, float* d_I_far, float* d_feat,
+                             float* d_fstat, void* stream);
+
+/*
+ * The cache: an MLP 256 -> 4 x 64 (SiLU) -> 1 on BF16 matrix cores with FP32
+ * accumulation, FP32 master weights and Adam.  Input: 16 log-spaced
+ * frequencies from 1 to freq_max cycles per domain (sin, cos) of the
+ * normalised truncation point, the direction and the wavelength offset within
+ * the scene's wavelength range, plus the 4 level statistics; output
+ * ln(I_far) / 10.
+ *   max_batch  largest training batch (multiple of 256, at most 2^19); sizes the workspace.
+ *   freq_max   highest frequency (grid side / 2 in the default set-up).
+ *   seed       weight initialisation (uniform +-1/sqrt(fan_in)) and batch sampling.
+ * Training rows are 12 floats: x/n_x, y/n_y, z/n_z, w_x, w_y, w_z, wavelength
+ * offset, mean ln chi / 10, ln(1 + var ln chi), (mean ln eta - mean ln chi) / 10,
+ * ln(1 + var ln eta), weight (0 ignores the row); target ln(I_far) / 10.
+ */
+typedef struct rt_nrc_desc {
+    int32_t max_batch;
+    float freq_max;
+    uint64_t seed;
+} rt_nrc_desc;
+
+typedef struct rt_nrc rt_nrc;
+
+rt_status rt_nrc_num_params(int32_t* h_n);
+rt_status rt_nrc_create(const rt_nrc_desc* desc, void* stream, rt_nrc** out);
+void rt_nrc_destroy(rt_nrc* nrc);
+/* FP32 master weights, host float [num_params] (checkpoint / restore). */
+rt_status rt_nrc_get_weights(const rt_nrc* nrc, float* h_w);
+rt_status rt_nrc_set_weights(rt_nrc* nrc, const float* h_w, void* stream);
+/* Packs generation-mode outputs of one batch into training rows starting at row0
+ * (rows ordered (dir, lam, probe)); d_raw [.][12], d_target [.]. */
+rt_status rt_nrc_pack(const rt_scene* scene, const float* d_dirs, int32_t n_dir, int64_t n_probes,
+                      const float* d_feat, const float* d_fstat, const float* d_I_far, float* d_raw, float* d_target,
+                      int64_t row0, void* stream);
+/* `steps` Adam steps (lr, beta 0.9 / 0.999) on batches of `batch` rows sampled
+ * from the n rows (mean squared error on the target). */
+rt_status rt_nrc_train(rt_nrc* nrc, const float* d_raw, const float* d_target, int64_t n, int32_t steps, int32_t batch,
+                       float lr, void* stream);
+/* Mean loss of the last training batch (synchronising). */
+rt_status rt_nrc_loss(const rt_nrc* nrc, float* h_loss);
+/* Gradients of the mean squared error over the first n rows (n multiple of 256,
+ * <= max_batch) into d_grad [num_params]; for checking the backward pass. */
+rt_status rt_nrc_gradients(rt_nrc* nrc, const float* d_raw, const float* d_target, int64_t n, float* d_grad,
+                           void* stream);
+/* Network outputs for n training-form rows into d_y [n]. */
+rt_status rt_nrc_predict(const rt_nrc* nrc, const float* d_raw, int64_t n, float* d_y, void* stream);
+/* I = I_near + T_near exp(10 y) for every query of a truncated trace of the
+ * scene's current batch (rays needing no query copy I_near). */
+rt_status rt_nrc_compose(const rt_nrc* nrc, const rt_scene* scene, const float* d_dirs, int32_t n_dir,
+                         int64_t n_probes, const float* d_feat, const float* d_fstat, const float* d_I_near,
+                         const float* d_T_near, float* d_I, void* stream);
+/* Held-out check on a generation-mode trace: composed prediction into d_I_pred,
+ * relative error against I_near + T_near I_far into d_err (nullable), and
+ * d_fallback[block of the truncation point] = 1 wherever it exceeds thresh
+ * (the map is not cleared first). */
+rt_status rt_nrc_validate(const rt_nrc* nrc, const rt_scene* scene, const float* d_dirs, int32_t n_dir,
+                          int64_t n_probes, const float* d_feat, const float* d_fstat, const float* d_I_near,
+                          const float* d_T_near, const float* d_I_far, float thresh, float* d_I_pred,
+                          uint8_t* d_fallback, float* d_err, void* stream);
+
 /* Device error counters accumulated by traces of this scene (synchronising); reset clears them. */
 rt_status rt_scene_device_error(const rt_scene* scene, rt_device_err* h_err);
 rt_status rt_scene_reset_device_error(rt_scene* scene, void* stream);

@@ -30,8 +30,13 @@ EXPORTS = (
     "rt_scene_create", "rt_scene_build", "rt_trace", "rt_scene_get_info", "rt_scene_active_blocks",
     "rt_scene_levels", "rt_scene_states", "rt_scene_cell_values", "rt_debug_visited",
     "rt_scene_device_error", "rt_scene_reset_device_error", "rt_scene_destroy", "rt_last_error",
-    "rt_version",
+    "rt_version", "rt_batch_create", "rt_batch_run", "rt_batch_tiles", "rt_batch_device_error",
+    "rt_batch_destroy", "rt_batch_autotune", "rt_graph_begin", "rt_graph_end", "rt_graph_launch",
+    "rt_graph_destroy", "rt_trace_truncated", "rt_nrc_num_params", "rt_nrc_create", "rt_nrc_destroy",
+    "rt_nrc_get_weights", "rt_nrc_set_weights", "rt_nrc_pack", "rt_nrc_train", "rt_nrc_loss", "rt_nrc_gradients",
+    "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate",
 )
+_VOID = ("rt_scene_destroy", "rt_last_error", "rt_version", "rt_batch_destroy", "rt_graph_destroy", "rt_nrc_destroy")
 
 _P = ctypes.c_void_p
 
@@ -76,6 +81,20 @@ class RtDeviceErr(ctypes.Structure):
     _fields_ = [("step_cap_hits", ctypes.c_ulonglong), ("first_ray", ctypes.c_longlong)]
 
 
+class RtBatchJob(ctypes.Structure):
+    _fields_ = [("scene", _P), ("d_dirs", _P), ("n_dir", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("d_I", _P), ("params", RtTraceParams)]
+
+
+class RtNrcDesc(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("freq_max", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
+class RtBatchParams(ctypes.Structure):
+    _fields_ = [("wg_waves", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("tiles_per_pop", ctypes.c_int32),
+                ("order", ctypes.c_int32), ("d_claims", _P)]
+
+
 _LIB = None
 
 
@@ -107,10 +126,36 @@ def lib():
     L.rt_scene_reset_device_error.argtypes = [_P, _P]
     L.rt_scene_destroy.argtypes = [_P]
     L.rt_scene_destroy.restype = None
+    L.rt_batch_create.argtypes = [_P, i32, _P, _P, ctypes.POINTER(_P)]
+    L.rt_batch_run.argtypes = [_P, _P]
+    L.rt_batch_tiles.argtypes = [_P, _P]
+    L.rt_batch_device_error.argtypes = [_P, _P]
+    L.rt_batch_destroy.argtypes = [_P]
+    L.rt_batch_destroy.restype = None
+    L.rt_batch_autotune.argtypes = [_P, i32, i32, _P, _P, _P]
+    L.rt_graph_begin.argtypes = [_P]
+    L.rt_graph_end.argtypes = [_P, ctypes.POINTER(_P)]
+    L.rt_graph_launch.argtypes = [_P, _P]
+    L.rt_graph_destroy.argtypes = [_P]
+    L.rt_graph_destroy.restype = None
+    L.rt_trace_truncated.argtypes = [_P, _P, ctypes.c_float, i32, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P, _P]
+    L.rt_nrc_num_params.argtypes = [_P]
+    L.rt_nrc_create.argtypes = [_P, _P, ctypes.POINTER(_P)]
+    L.rt_nrc_destroy.argtypes = [_P]
+    L.rt_nrc_destroy.restype = None
+    L.rt_nrc_get_weights.argtypes = [_P, _P]
+    L.rt_nrc_set_weights.argtypes = [_P, _P, _P]
+    L.rt_nrc_pack.argtypes = [_P, _P, i32, i64, _P, _P, _P, _P, _P, i64, _P]
+    L.rt_nrc_train.argtypes = [_P, _P, _P, i64, i32, i32, ctypes.c_float, _P]
+    L.rt_nrc_loss.argtypes = [_P, _P]
+    L.rt_nrc_gradients.argtypes = [_P, _P, _P, i64, _P, _P]
+    L.rt_nrc_predict.argtypes = [_P, _P, i64, _P, _P]
+    L.rt_nrc_compose.argtypes = [_P, _P, _P, i32, i64, _P, _P, _P, _P, _P, _P]
+    L.rt_nrc_validate.argtypes = [_P, _P, _P, i32, i64, _P, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P]
     L.rt_last_error.restype = ctypes.c_char_p
     L.rt_version.restype = ctypes.c_char_p
     for name in EXPORTS:
-        if name not in ("rt_scene_destroy", "rt_last_error", "rt_version"):
+        if name not in _VOID:
             getattr(L, name).restype = ctypes.c_int
     _LIB = L
     return L
@@ -274,6 +319,39 @@ class Scene:
         self._last = (td, tp)
         return out
 
+    def trace_truncated(self, dirs, t_trunc, gen=True, fallback=None, probes=None, mode="vlm", I0=0.0,
+                        max_level=-1, step_cap=0, level_dist=None, stream=None):
+        """Truncated trace (rt_trace_truncated).  Returns a dict of device tensors:
+        I_near, T_near, I_far (generation mode only) [n_dir][batch][n_probes],
+        feat [n_dir][n_probes][4] (truncation point x, y, z, query flag) and
+        fstat [n_dir][batch][n_probes][4] (level statistics there)."""
+        torch = self.torch
+        td = dirs if isinstance(dirs, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(dirs, np.float32))
+        td = td.to(device=self.device, dtype=torch.float32).contiguous()
+        if probes is None:
+            n_probes, tp = self.info["n_probes"], None
+        else:
+            tp = probes if isinstance(probes, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(probes, np.int32))
+            tp = tp.to(device=self.device, dtype=torch.int32).contiguous()
+            n_probes = tp.numel()
+        nd, nl = int(td.shape[0]), self.batch[1] - self.batch[0]
+        f32 = dict(dtype=torch.float32, device=self.device)
+        out = dict(I_near=torch.empty((nd, nl, n_probes), **f32), T_near=torch.empty((nd, nl, n_probes), **f32),
+                   I_far=torch.empty((nd, nl, n_probes), **f32) if gen else None,
+                   feat=torch.empty((nd, n_probes, 4), **f32), fstat=torch.empty((nd, nl, n_probes, 4), **f32))
+        fb = None
+        if fallback is not None:
+            fb = fallback.to(device=self.device, dtype=torch.uint8).contiguous()
+        p = self._tparams(mode, max_level, I0, step_cap, None, level_dist)
+        _check(lib().rt_trace_truncated(self.h, ctypes.byref(p), float(t_trunc), 1 if gen else 0,
+                                        fb.data_ptr() if fb is not None else None, td.data_ptr(), nd,
+                                        tp.data_ptr() if tp is not None else None, int(n_probes),
+                                        out["I_near"].data_ptr(), out["T_near"].data_ptr(),
+                                        out["I_far"].data_ptr() if gen else None, out["feat"].data_ptr(),
+                                        out["fstat"].data_ptr(), _stream(stream)))
+        out["dirs"], out["n_probes"], out["probes"] = td, n_probes, tp
+        return out
+
     def active_blocks(self):
         out = np.zeros(self.info["n_active"], np.int32)
         _check(lib().rt_scene_active_blocks(self.h, _np_ptr(out)))
@@ -333,3 +411,192 @@ class Scene:
 
 def version():
     return lib().rt_version().decode()
+
+
+# --------------------------------------------------------------------- batching
+def _batch_jobs(jobs):
+    """jobs: list of dicts {scene, dirs (device tensor), out (device tensor), trace kwargs...}."""
+    arr = (RtBatchJob * len(jobs))()
+    keep = []
+    for i, j in enumerate(jobs):
+        sc = j["scene"]
+        d = j["dirs"].contiguous()
+        o = j["out"]
+        keep += [d, o]
+        arr[i].scene = sc.h
+        arr[i].d_dirs = d.data_ptr()
+        arr[i].n_dir = int(d.shape[0])
+        arr[i].d_I = o.data_ptr()
+        arr[i].params = sc._tparams(j.get("mode", "vlm"), j.get("max_level", -1), j.get("I0", 0.0),
+                                    j.get("step_cap", 0), None, j.get("level_dist"))
+    return arr, keep
+
+
+class Batch:
+    """Many scenes traced in one persistent launch (rt_batch_*)."""
+
+    def __init__(self, jobs, wg_waves=0, wgs_per_cu=0, tiles_per_pop=0, order=0, claims=None, stream=None):
+        self._arr, self._keep = _batch_jobs(jobs)
+        p = RtBatchParams()
+        p.wg_waves, p.wgs_per_cu, p.tiles_per_pop, p.order = int(wg_waves), int(wgs_per_cu), int(tiles_per_pop), int(order)
+        p.d_claims = claims.data_ptr() if claims is not None else None
+        self._claims = claims
+        h = _P()
+        _check(lib().rt_batch_create(self._arr, len(jobs), ctypes.byref(p), _stream(stream), ctypes.byref(h)))
+        self.h = h
+
+    def run(self, stream=None):
+        _check(lib().rt_batch_run(self.h, _stream(stream)))
+
+    def tiles(self):
+        v = ctypes.c_int64(0)
+        _check(lib().rt_batch_tiles(self.h, ctypes.byref(v)))
+        return v.value
+
+    def device_error(self):
+        e = RtDeviceErr()
+        _check(lib().rt_batch_device_error(self.h, ctypes.byref(e)))
+        return int(e.step_cap_hits), int(e.first_ray)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.rt_batch_destroy(h)
+            self.h = None
+
+
+def batch_autotune(jobs, reps=3, stream=None):
+    """Fastest launch shape of the persistent kernel for these jobs: (params dict, ms per run)."""
+    arr, keep = _batch_jobs(jobs)
+    best = RtBatchParams()
+    ms = ctypes.c_float(0)
+    _check(lib().rt_batch_autotune(arr, len(jobs), int(reps), _stream(stream), ctypes.byref(best), ctypes.byref(ms)))
+    del keep
+    return {"wg_waves": best.wg_waves, "wgs_per_cu": best.wgs_per_cu, "tiles_per_pop": best.tiles_per_pop}, ms.value
+
+
+class Graph:
+    """Captures the work issued on a (non-default) stream and replays it (rt_graph_*)."""
+
+    def __init__(self, stream):
+        self.stream = stream
+        self.h = None
+
+    def __enter__(self):
+        _check(lib().rt_graph_begin(_stream(self.stream)))
+        return self
+
+    def __exit__(self, exc_type, exc, tb):
+        h = _P()
+        st = lib().rt_graph_end(_stream(self.stream), ctypes.byref(h))
+        if exc_type is None:
+            _check(st)
+            self.h = h
+        return False
+
+    def replay(self):
+        _check(lib().rt_graph_launch(self.h, _stream(self.stream)))
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.rt_graph_destroy(h)
+            self.h = None
+
+
+# ------------------------------------------------------------ radiance cache
+RAW = 12  # training row: pos 3, dir 3, wavelength offset, 4 level statistics, weight
+
+
+def nrc_num_params():
+    n = ctypes.c_int32(0)
+    _check(lib().rt_nrc_num_params(ctypes.byref(n)))
+    return n.value
+
+
+class Nrc:
+    """The neural radiance cache (rt_nrc_*): training rows are float32 [n][12]."""
+
+    def __init__(self, max_batch=65536, freq_max=64.0, seed=0, stream=None):
+        import torch
+        self.torch = torch
+        d = RtNrcDesc()
+        d.max_batch, d.freq_max, d.seed = int(max_batch), float(freq_max), int(seed)
+        self.desc = d
+        h = _P()
+        _check(lib().rt_nrc_create(ctypes.byref(d), _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.n_params = nrc_num_params()
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.rt_nrc_destroy(h)
+            self.h = None
+
+    def get_weights(self):
+        w = np.zeros(self.n_params, np.float32)
+        _check(lib().rt_nrc_get_weights(self.h, _np_ptr(w)))
+        return w
+
+    def set_weights(self, w, stream=None):
+        w = np.ascontiguousarray(w, np.float32)
+        assert w.size == self.n_params
+        _check(lib().rt_nrc_set_weights(self.h, _np_ptr(w), _stream(stream)))
+
+    def _dev(self, a, dt=None):
+        torch = self.torch
+        t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+        return t.to(device="cuda", dtype=dt or torch.float32).contiguous()
+
+    def train(self, raw, target, steps, batch, lr=1e-3, stream=None):
+        r, t = self._dev(raw), self._dev(target)
+        assert r.shape[-1] == RAW and t.numel() == r.shape[0]
+        _check(lib().rt_nrc_train(self.h, r.data_ptr(), t.data_ptr(), int(r.shape[0]), int(steps), int(batch),
+                                  float(lr), _stream(stream)))
+
+    def loss(self):
+        v = ctypes.c_float(0)
+        _check(lib().rt_nrc_loss(self.h, ctypes.byref(v)))
+        return v.value
+
+    def gradients(self, raw, target, stream=None):
+        r, t = self._dev(raw), self._dev(target)
+        g = self.torch.zeros(self.n_params, dtype=self.torch.float32, device="cuda")
+        _check(lib().rt_nrc_gradients(self.h, r.data_ptr(), t.data_ptr(), int(r.shape[0]), g.data_ptr(),
+                                      _stream(stream)))
+        return g
+
+    def predict(self, raw, stream=None):
+        r = self._dev(raw)
+        y = self.torch.empty(r.shape[0], dtype=self.torch.float32, device="cuda")
+        _check(lib().rt_nrc_predict(self.h, r.data_ptr(), int(r.shape[0]), y.data_ptr(), _stream(stream)))
+        return y
+
+    def pack(self, scene, tr, raw, target, row0, stream=None):
+        """Training rows from a generation-mode truncated trace `tr` (Scene.trace_truncated output)."""
+        _check(lib().rt_nrc_pack(scene.h, tr["dirs"].data_ptr(), int(tr["dirs"].shape[0]), int(tr["n_probes"]),
+                                 tr["feat"].data_ptr(), tr["fstat"].data_ptr(), tr["I_far"].data_ptr(),
+                                 raw.data_ptr(), target.data_ptr(), int(row0), _stream(stream)))
+
+    def compose(self, scene, tr, out=None, stream=None):
+        """I = I_near + T_near exp(10 y) over a truncated trace."""
+        if out is None:
+            out = self.torch.empty_like(tr["I_near"])
+        _check(lib().rt_nrc_compose(self.h, scene.h, tr["dirs"].data_ptr(), int(tr["dirs"].shape[0]),
+                                    int(tr["n_probes"]), tr["feat"].data_ptr(), tr["fstat"].data_ptr(),
+                                    tr["I_near"].data_ptr(), tr["T_near"].data_ptr(), out.data_ptr(),
+                                    _stream(stream)))
+        return out
+
+    def validate(self, scene, tr, thresh, fallback, stream=None):
+        """Held-out check of a generation-mode trace: (prediction, relative error); flags
+        fallback[block] for blocks whose queries exceed thresh."""
+        pred = self.torch.empty_like(tr["I_near"])
+        err = self.torch.empty_like(tr["I_near"])
+        _check(lib().rt_nrc_validate(self.h, scene.h, tr["dirs"].data_ptr(), int(tr["dirs"].shape[0]),
+                                     int(tr["n_probes"]), tr["feat"].data_ptr(), tr["fstat"].data_ptr(),
+                                     tr["I_near"].data_ptr(), tr["T_near"].data_ptr(), tr["I_far"].data_ptr(),
+                                     float(thresh), pred.data_ptr(), fallback.data_ptr(), err.data_ptr(),
+                                     _stream(stream)))
+        return pred, err

@@ -27,6 +27,7 @@ UNITS = [
     ("build.hip", ["-ffp-contract=off"]),
     ("build_lines.hip", ["-ffp-contract=off"]),
     ("march.hip", []),
+    ("nrc.hip", []),
     ("api.cpp", []),
 ]
 

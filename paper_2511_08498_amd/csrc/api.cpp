@@ -11,7 +11,7 @@
 #include <string>
 #include <vector>
 
-#include "common.h"
+#include "scene_impl.h"
 
 using namespace rt;
 
@@ -45,37 +45,16 @@ int ilog2(int v)
 
 }  // namespace
 
-struct rt_scene {
-    rt_scene_desc desc;
-    Geo g;
-    Inputs in;
-    SceneBufs b;
-    int n_active = 0;
-    std::vector<double> lam;
-    std::vector<double> lam0;
-    std::vector<void*> allocs;
-    size_t bytes = 0;
-    int batch_begin = -1, batch_end = -1;
-    int storage = RT_F32;
-    int cav_rec = 0;
-
-    ~rt_scene()
-    {
-        for (void* p : allocs) (void)hipFree(p);
-    }
-    template <typename T>
-    rt_status alloc(T** p, size_t count)
-    {
-        size_t nbytes = std::max<size_t>(count * sizeof(T), 256);
-        void* q = nullptr;
-        hipError_t e = hipMalloc(&q, nbytes);
-        if (e != hipSuccess) return fail(RT_E_HIP, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
-        allocs.push_back(q);
-        bytes += nbytes;
-        *p = (T*)q;
-        return RT_OK;
-    }
-};
+rt_status rt::set_error(rt_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
 
 #define RT_TRY(call)                        \
     do {                                    \
@@ -155,6 +134,7 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     }
     g.cells = off;
     g.n_state_words = (int)((g.nblocks + kStatesPerWord - 1) / kStatesPerWord);
+    g.feat_level = std::min(2, d->n_levels - 1);
     if (d->model == RT_MODEL_LINES) {
         sc->lam.assign(d->h_lam, d->h_lam + d->n_lam);
         sc->lam0.assign(d->h_lam0, d->h_lam0 + d->n_lines);
@@ -221,13 +201,20 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
         return cleanup(fail(RT_E_HIP, "synchronize: %s", hipGetErrorString(e)));
     sc->n_active = na;
     const size_t cells = (size_t)na * g.cells;
+    {
+        size_t fcells = (size_t)na << (d->dim * (log2B - g.feat_level));
+        if ((st = sc->alloc(&B.fstats, fcells * kLam)) != RT_OK) return cleanup(st);
+    }
     if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) {
         if ((st = sc->alloc((float**)&B.vals, cells * kLam * 2)) != RT_OK) return cleanup(st);
     }
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP) {
+        if (cells * (size_t)d->n_v * kLam * 2 >= (size_t)1 << 31)
+            return cleanup(fail(RT_E_UNSUPPORTED, "velocity-node storage exceeds 2^31 floats"));
         if ((st = sc->alloc(&B.vgrid, cells)) != RT_OK) return cleanup(st);
+        if ((st = sc->alloc(&B.vmax, cells)) != RT_OK) return cleanup(st);
         if ((st = sc->alloc(&B.vnodes, cells * (size_t)d->n_v * kLam * 2)) != RT_OK) return cleanup(st);
-        if ((e = launch_vgrid(g, in, B, na, s)) != hipSuccess)
+        if ((e = launch_vgrid(g, in, B, na, d->n_v, s)) != hipSuccess)
             return cleanup(fail(RT_E_HIP, "velocity grid: %s", hipGetErrorString(e)));
     }
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
@@ -291,7 +278,9 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     return RT_OK;
 }
 
-static TraceLaunch make_trace(const rt_scene* sc, const rt_trace_params* p)
+}  // extern "C"
+
+TraceLaunch rt::make_trace(const rt_scene* sc, const rt_trace_params* p)
 {
     TraceLaunch t;
     std::memset(&t, 0, sizeof(t));
@@ -323,8 +312,11 @@ static TraceLaunch make_trace(const rt_scene* sc, const rt_trace_params* p)
     t.lb = make_batch(sc, sc->batch_begin, sc->batch_end);
     t.stats = p->d_stats;
     t.err = sc->b.err;
+    t.fstats = sc->b.fstats;
     return t;
 }
+
+extern "C" {
 
 rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, int32_t n_dir,
                    const int32_t* d_probes, int64_t n_probes, float* d_I, void* stream)
@@ -349,6 +341,39 @@ rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_
     t.probes = d_probes;
     t.n_probes = n_probes;
     t.I = d_I;
+    RT_HIP(launch_trace(t, (hipStream_t)stream));
+    return RT_OK;
+}
+
+rt_status rt_trace_truncated(const rt_scene* sc, const rt_trace_params* p, float t_trunc, int32_t gen,
+                             const uint8_t* d_fallback, const float* d_dirs, int32_t n_dir, const int32_t* d_probes,
+                             int64_t n_probes, float* d_I_near, float* d_T_near, float* d_I_far, float* d_feat,
+                             float* d_fstat, void* stream)
+{
+    g_err.clear();
+    if (!sc || !p || !d_dirs || !d_I_near || !d_T_near || !d_feat || !d_fstat) return fail(RT_E_ARG, "null argument");
+    if (gen && !d_I_far) return fail(RT_E_ARG, "generation mode needs d_I_far");
+    if (!(t_trunc > 0.f)) return fail(RT_E_ARG, "t_trunc must be positive");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace_truncated before rt_scene_build");
+    if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
+    if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
+    const long long all = (long long)sc->n_active * sc->g.bvox;
+    if (!d_probes && n_probes != all) return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld", all);
+    if (n_probes <= 0) return n_probes == 0 ? RT_OK : fail(RT_E_ARG, "n_probes must be >= 0");
+    TraceLaunch t = make_trace(sc, p);
+    t.dirs = d_dirs;
+    t.n_dir = n_dir;
+    t.probes = d_probes;
+    t.n_probes = n_probes;
+    t.trunc = 1;
+    t.gen = gen ? 1 : 0;
+    t.t_trunc = (double)t_trunc;
+    t.fallback = gen ? nullptr : d_fallback;
+    t.I_near = d_I_near;
+    t.T_near = d_T_near;
+    t.I_far = d_I_far;
+    t.feat = (float4*)d_feat;
+    t.fstat_out = (float4*)d_fstat;
     RT_HIP(launch_trace(t, (hipStream_t)stream));
     return RT_OK;
 }
@@ -476,5 +501,248 @@ rt_status rt_scene_reset_device_error(rt_scene* sc, void* stream)
 }
 
 void rt_scene_destroy(rt_scene* sc) { delete sc; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batching
+struct rt_batch {
+    std::vector<BatchJob> jobs;
+    BatchJob* d_jobs = nullptr;
+    unsigned* counter = nullptr;
+    unsigned long long* err = nullptr;
+    unsigned* claims = nullptr;
+    unsigned total_tiles = 0;
+    int wg_waves = 4, n_wgs = 0, tiles_per_pop = 1;
+    ~rt_batch()
+    {
+        if (d_jobs) (void)hipFree(d_jobs);
+        if (counter) (void)hipFree(counter);
+        if (err) (void)hipFree(err);
+    }
+};
+
+struct rt_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static int device_cus()
+{
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) return 256;
+    return cus;
+}
+
+extern "C" {
+
+rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_batch_params* p, void* stream,
+                          rt_batch** out)
+{
+    g_err.clear();
+    if (!jobs || !out || n_jobs < 1) return fail(RT_E_ARG, "need at least one job");
+    *out = nullptr;
+    rt_batch_params bp = p ? *p : rt_batch_params{0, 0, 0, 0, nullptr};
+    int wg_waves = bp.wg_waves ? bp.wg_waves : 4;
+    int wgs_per_cu = bp.wgs_per_cu ? bp.wgs_per_cu : 2;
+    int tpp = bp.tiles_per_pop ? bp.tiles_per_pop : 1;
+    if (wg_waves != 1 && wg_waves != 2 && wg_waves != 4 && wg_waves != 8) return fail(RT_E_ARG, "wg_waves must be 1, 2, 4 or 8");
+    if (wgs_per_cu < 1 || wgs_per_cu > 16) return fail(RT_E_ARG, "wgs_per_cu must be in [1, 16]");
+    if (tpp < 1 || tpp > 64) return fail(RT_E_ARG, "tiles_per_pop must be in [1, 64]");
+    std::vector<BatchJob> bj((size_t)n_jobs);
+    std::vector<double> cost((size_t)n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        const rt_batch_job& J = jobs[j];
+        const rt_scene* sc = J.scene;
+        if (!sc || !J.d_dirs || !J.d_I) return fail(RT_E_ARG, "job %d: null scene, directions or output", j);
+        if (sc->batch_begin < 0) return fail(RT_E_STATE, "job %d: scene has no built batch", j);
+        if (!(sc->desc.model == RT_MODEL_STATIC || sc->desc.emission == RT_EMIS_STATIC))
+            return fail(RT_E_UNSUPPORTED, "job %d: batched trace supports static emission", j);
+        if (J.n_dir < 1) return fail(RT_E_ARG, "job %d: n_dir must be >= 1", j);
+        const rt_trace_params& tp = J.params;
+        if (tp.mode != RT_TRACE_LEVEL0 && tp.mode != RT_TRACE_VLM) return fail(RT_E_ARG, "job %d: bad mode", j);
+        TraceLaunch t = make_trace(sc, &tp);
+        BatchJob& b = bj[(size_t)j];
+        std::memset(&b, 0, sizeof(b));
+        b.g = t.g;
+        b.states = t.states;
+        b.slot = t.slot;
+        b.vals = t.vals;
+        b.active_list = t.active_list;
+        b.dirs = J.d_dirs;
+        b.I = J.d_I;
+        b.n_probes = (long long)sc->n_active * sc->g.bvox;
+        b.tiles = (int)((b.n_probes + 63) / 64);
+        b.n_dir = J.n_dir;
+        b.nl = sc->batch_end - sc->batch_begin;
+        b.mode = t.mode;
+        b.max_level = t.max_level;
+        b.graded = t.graded;
+        b.step_cap = t.step_cap;
+        b.storage = t.storage;
+        b.I0 = t.I0;
+        b.ds0 = t.ds0;
+        for (int m = 0; m < kMaxLevels; ++m) b.level_dist[m] = t.level_dist[m];
+        double diam = 0;
+        for (int a = 0; a < sc->g.dim; ++a) diam += sc->g.n[a];
+        cost[(size_t)j] = (double)J.n_dir * (double)b.n_probes * diam;
+    }
+    std::vector<int> order((size_t)n_jobs);
+    for (int j = 0; j < n_jobs; ++j) order[(size_t)j] = j;
+    if (bp.order == 0)
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[(size_t)a] > cost[(size_t)b]; });
+    rt_batch* bt = new (std::nothrow) rt_batch();
+    if (!bt) return fail(RT_E_ARG, "out of host memory");
+    unsigned long long tile = 0;
+    for (int j : order) {
+        BatchJob b = bj[(size_t)j];
+        b.tile0 = (unsigned)tile;
+        tile += (unsigned long long)b.tiles * b.n_dir;
+        bt->jobs.push_back(b);
+    }
+    if (tile >= (1ull << 31)) {
+        delete bt;
+        return fail(RT_E_ARG, "too many tiles in one batch (%llu)", tile);
+    }
+    bt->total_tiles = (unsigned)tile;
+    bt->wg_waves = wg_waves;
+    bt->tiles_per_pop = tpp;
+    bt->n_wgs = device_cus() * wgs_per_cu;
+    bt->claims = bp.d_claims;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&bt->d_jobs, sizeof(BatchJob) * bt->jobs.size());
+    if (e == hipSuccess) e = hipMalloc(&bt->counter, 256);
+    if (e == hipSuccess) e = hipMalloc(&bt->err, 256);
+    unsigned long long err0[2] = {0ull, ~0ull};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(bt->d_jobs, bt->jobs.data(), sizeof(BatchJob) * bt->jobs.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(bt->err, err0, sizeof(err0), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete bt;
+        return fail(RT_E_HIP, "batch setup: %s", hipGetErrorString(e));
+    }
+    *out = bt;
+    return RT_OK;
+}
+
+rt_status rt_batch_run(const rt_batch* bt, void* stream)
+{
+    if (!bt) return fail(RT_E_ARG, "null batch");
+    RT_HIP(launch_batched(bt->d_jobs, (int)bt->jobs.size(), bt->total_tiles, bt->wg_waves, bt->n_wgs,
+                          bt->tiles_per_pop, bt->counter, bt->claims, bt->err, (hipStream_t)stream));
+    return RT_OK;
+}
+
+rt_status rt_batch_tiles(const rt_batch* bt, int64_t* h)
+{
+    if (!bt || !h) return fail(RT_E_ARG, "null argument");
+    *h = bt->total_tiles;
+    return RT_OK;
+}
+
+rt_status rt_batch_device_error(const rt_batch* bt, rt_device_err* h)
+{
+    if (!bt || !h) return fail(RT_E_ARG, "null argument");
+    unsigned long long v[2];
+    RT_HIP(hipDeviceSynchronize());
+    RT_HIP(hipMemcpy(v, bt->err, sizeof(v), hipMemcpyDeviceToHost));
+    h->step_cap_hits = v[0];
+    h->first_ray = v[0] ? (long long)v[1] : -1;
+    return RT_OK;
+}
+
+void rt_batch_destroy(rt_batch* bt) { delete bt; }
+
+rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t reps, void* stream,
+                            rt_batch_params* best, float* best_ms)
+{
+    if (!jobs || !best || !best_ms || reps < 1) return fail(RT_E_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    const int waves[] = {2, 4, 8};
+    const int per_cu[] = {1, 2, 4};
+    const int pops[] = {1, 4};
+    hipEvent_t e0, e1;
+    RT_HIP(hipEventCreate(&e0));
+    RT_HIP(hipEventCreate(&e1));
+    float best_t = 3.0e38f;
+    rt_batch_params bestp = {4, 2, 1, 0, nullptr};
+    rt_status st = RT_OK;
+    for (int w : waves)
+        for (int c : per_cu)
+            for (int q : pops) {
+                rt_batch_params p = {w, c, q, 0, nullptr};
+                rt_batch* bt = nullptr;
+                if ((st = rt_batch_create(jobs, n_jobs, &p, stream, &bt)) != RT_OK) goto done;
+                if ((st = rt_batch_run(bt, stream)) != RT_OK) {
+                    rt_batch_destroy(bt);
+                    goto done;
+                }
+                {
+                    hipError_t e = hipEventRecord(e0, s);
+                    for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                        if (rt_batch_run(bt, stream) != RT_OK) e = hipErrorUnknown;
+                    }
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    rt_batch_destroy(bt);
+                    if (e != hipSuccess) {
+                        st = fail(RT_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+                        goto done;
+                    }
+                    ms /= (float)reps;
+                    if (ms < best_t) {
+                        best_t = ms;
+                        bestp = p;
+                    }
+                }
+            }
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RT_OK) return st;
+    *best = bestp;
+    *best_ms = best_t;
+    return RT_OK;
+}
+
+rt_status rt_graph_begin(void* stream)
+{
+    RT_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeRelaxed));
+    return RT_OK;
+}
+
+rt_status rt_graph_end(void* stream, rt_graph** out)
+{
+    if (!out) return fail(RT_E_ARG, "null argument");
+    rt_graph* g = new (std::nothrow) rt_graph();
+    if (!g) return fail(RT_E_ARG, "out of host memory");
+    hipError_t e = hipStreamEndCapture((hipStream_t)stream, &g->graph);
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return fail(RT_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return RT_OK;
+}
+
+rt_status rt_graph_launch(const rt_graph* g, void* stream)
+{
+    if (!g) return fail(RT_E_ARG, "null graph");
+    RT_HIP(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return RT_OK;
+}
+
+void rt_graph_destroy(rt_graph* g)
+{
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
 
 }  // extern "C"

@@ -207,6 +207,9 @@ __global__ void k_build_static(Geo g, Inputs in, SceneBufs bufs, int model, int 
         s0[1] = log(qc > 1e-300 ? qc : 1e-300);
         s0[2] = (double)e;
         s0[3] = (double)c;
+        if (bufs.fstats && g.feat_level == 0)
+            bufs.fstats[((long long)slot * g.bvox + tid) * kLam + l] =
+                make_float4((float)s0[1], 0.f, (float)s0[0], 0.f);
         if (tid < kMaxLevels) pass_all[tid] = 1;
         __syncthreads();
         for (int m = 1; m < L; ++m) {
@@ -257,6 +260,9 @@ __global__ void k_build_static(Geo g, Inputs in, SceneBufs bufs, int model, int 
                 int thin = lc * (double)(1 << m) * ds0 < tau_thin;
                 int pass = thin || (iod_e <= T_iod && iod_c <= T_iod);
                 if (!pass) pass_all[m] = 0;
+                if (bufs.fstats && m == g.feat_level)
+                    bufs.fstats[((long long)slot * ncell + tid) * kLam + l] =
+                        make_float4((float)st[1], (float)var[1], (float)st[0], (float)var[0]);
                 if (write_values) {
                     T* r = vals + ((rec0 + g.lvl_off[m] + tid) * kLam + l) * 2;
                     r[0] = Codec<T>::enc((float)le);

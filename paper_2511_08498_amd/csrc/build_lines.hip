@@ -9,8 +9,9 @@
 //  * Core and Voigt (Sect. 3.2): eta*, chi* and the background averaged in
 //    the stored-value mode, damping, 1/Doppler width and velocity linearly.
 //
-// Averages over a cell's voxels follow the fixed pairwise order of the level
-// statistics (x pairs, then y, then z, level by level).
+// The V / vbar and Core-and-Voigt chains average children level by level in
+// the fixed pairwise order of the level statistics (x pairs, then y, then z).
+// Velocity-node values are FP32 sums over the cell's voxels (values only).
 #include "common.h"
 #include "profile.h"
 
@@ -42,8 +43,14 @@ __device__ __forceinline__ F tsum(const F* q)
 }
 
 // ------------------------------------------------------ velocity grid (V, vbar)
+__device__ __forceinline__ float4 vgrid_rec(double V, const double* vb, int n_v)
+{
+    float s = V > 0.0 ? (float)(0.5 * (double)(n_v - 1) / V) : 0.f;
+    return make_float4(s, (float)vb[0], (float)vb[1], (float)vb[2]);
+}
+
 template <int D>
-__global__ void k_vgrid(Geo g, Inputs in, SceneBufs bufs)
+__global__ void k_vgrid(Geo g, Inputs in, SceneBufs bufs, int n_v)
 {
     extern __shared__ double lds[];  // per cell: V, vx, vy, vz
     const int slot = blockIdx.x, tid = threadIdx.x;
@@ -61,7 +68,8 @@ __global__ void k_vgrid(Geo g, Inputs in, SceneBufs bufs)
     s0[2] = vv[1];
     s0[3] = vv[2];
     const long long rec = (long long)slot * g.cells;
-    bufs.vgrid[rec + tid] = make_float4((float)s0[0], (float)vv[0], (float)vv[1], (float)vv[2]);
+    bufs.vgrid[rec + tid] = vgrid_rec(s0[0], vv, n_v);
+    bufs.vmax[rec + tid] = (float)s0[0];
     __syncthreads();
     for (int m = 1; m < g.n_levels; ++m) {
         const int side = g.B >> m;
@@ -79,97 +87,109 @@ __global__ void k_vgrid(Geo g, Inputs in, SceneBufs bufs)
                 for (int j = 0; j < (1 << D); ++j) qq[j] = sc[4 * idx[j] + f];
                 so[f] = tsum<D>(qq) / (1 << D);
             }
-            bufs.vgrid[rec + g.lvl_off[m] + tid] = make_float4((float)so[0], (float)so[1], (float)so[2], (float)so[3]);
+            bufs.vgrid[rec + g.lvl_off[m] + tid] = vgrid_rec(so[0], so + 1, n_v);
+            bufs.vmax[rec + g.lvl_off[m] + tid] = (float)so[0];
         }
         __syncthreads();
     }
 }
 
-hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, hipStream_t s)
+hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, hipStream_t s)
 {
     if (n_active == 0) return hipSuccess;
     size_t shm = sizeof(double) * 4 * (size_t)g.cells;
-    if (g.dim == 2) hipLaunchKernelGGL(k_vgrid<2>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b);
-    else hipLaunchKernelGGL(k_vgrid<3>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b);
+    if (g.dim == 2) hipLaunchKernelGGL(k_vgrid<2>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b, n_v);
+    else hipLaunchKernelGGL(k_vgrid<3>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b, n_v);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------ velocity node values
-// Block (slot, level m); thread = MIP-0 voxel of the brick.  For every batch
-// wavelength and node, each voxel evaluates eta, chi at the node velocity of
-// its level-m cell; the brick is then reduced m times in the pairwise order.
+// One workgroup per active brick; one thread per (level cell, node) item.  The
+// thread walks the cell's MIP-0 voxels once, reads each voxel's line
+// parameters once, evaluates eta, chi at the node velocity for all 8 batch
+// wavelengths and accumulates them (ln values in log mode) in registers, then
+// writes the item's 64-byte record.  Values, not decisions: FP32 sums.
 template <int D>
-__global__ void k_velinterp_nodes(Geo g, Inputs in, SceneBufs bufs, LamBatch lb, int n_v, double ds0, int avg_mode)
+__global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, SceneBufs bufs, LamBatch lb, int n_v,
+                                                          float ds0, int avg_mode)
 {
-    extern __shared__ float fl[];  // [2][bvox] working values, then reduced in place
-    const int slot = blockIdx.x, m = blockIdx.y, tid = threadIdx.x;
+    const int slot = blockIdx.x;
     const int blk = bufs.active_list[slot];
-    const int B = g.B, bvox = g.bvox;
-    long long v;
-    voxel_of(g, blk, tid, D, v);
-    // level-m cell of this voxel
-    int lx = tid & (B - 1), ly = (tid >> g.log2B) & (B - 1), lz = D > 2 ? (tid >> (2 * g.log2B)) : 0;
-    const int side = B >> m;
-    int cell = (lx >> m) + side * ((ly >> m) + side * (lz >> m));
-    const long long rec = (long long)slot * g.cells + g.lvl_off[m];
-    const float Vc = bufs.vgrid[rec + cell].x;
-    const int ncell = D == 2 ? side * side : side * side * side;
+    const int B = g.B;
+    const int bc0 = blk % g.nb[0], bc1 = (blk / g.nb[0]) % g.nb[1], bc2 = blk / (g.nb[0] * g.nb[1]);
     const bool logm = avg_mode == RT_AVG_LOG;
-    float* fe = fl;
-    float* fc = fl + bvox;
-    for (int l = 0; l < lb.nl; ++l) {
-        for (int kn = 0; kn < n_v; ++kn) {
-            float uk = Vc > 0.f ? -Vc + 2.0f * Vc * (float)kn / (float)(n_v - 1) : 0.f;
-            float ee = in.eta_bg[v], cc = in.chi_bg[v];
+    const int total = g.cells * n_v;
+    float lam_dl[kLam][kMaxLines];
+    float k0[kMaxLines];
+    for (int k = 0; k < kMaxLines; ++k) {
+        k0[k] = (float)(lb.lam0[k] / kCkms);
+        for (int l = 0; l < kLam; ++l) lam_dl[l][k] = (float)(lb.lam[l] - lb.lam0[k]);
+    }
+    for (int item = threadIdx.x; item < total; item += blockDim.x) {
+        // items ordered coarse level first so the long ones start early
+        int rem = item, m = g.n_levels - 1;
+        for (; m > 0; --m) {
+            int nc = g.lvl_off[m + 1] - g.lvl_off[m];
+            if (rem < nc * n_v) break;
+            rem -= nc * n_v;
+        }
+        const int cell = rem / n_v, kn = rem - cell * n_v;
+        const int side = B >> m, size = 1 << m;
+        const int cx = cell % side, cy = (cell / side) % side, cz = D > 2 ? cell / (side * side) : 0;
+        const long long rec = (long long)slot * g.cells + g.lvl_off[m] + cell;
+        const float Vc = bufs.vmax[rec];
+        const float uk = Vc > 0.f ? -Vc + 2.0f * Vc * (float)kn / (float)(n_v - 1) : 0.f;
+        float ae[kLam], ac[kLam];
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) ae[l] = ac[l] = 0.f;
+        const int nvx = D > 2 ? size * size * size : size * size;
+        for (int q = 0; q < nvx; ++q) {
+            int qx = q & (size - 1), qy = (q >> m) & (size - 1), qz = D > 2 ? q >> (2 * m) : 0;
+            long long v = (long long)(bc0 * B + cx * size + qx) +
+                          (long long)g.n[0] * ((long long)(bc1 * B + cy * size + qy) +
+                                               (long long)g.n[1] * (bc2 * B + cz * size + qz));
+            float eb = in.eta_bg[v], cb = in.chi_bg[v];
+            float es[kMaxLines], cs[kMaxLines], a0[kMaxLines], idl[kMaxLines];
             for (int k = 0; k < lb.n_lines; ++k) {
                 long long o = (long long)k * in.nvox + v;
-                float idl = in.inv_dld[o];
-                float x = ((float)(lb.lam[l] - lb.lam0[k]) + (float)(lb.lam0[k] / kCkms) * uk) * idl;
-                float phi = line_shape(lb.profile, x, in.damp[o], lb.lam[l], lb.lam0[k], idl);
-                ee += in.eta_star[o] * phi;
-                cc += in.chi_star[o] * phi;
+                es[k] = in.eta_star[o];
+                cs[k] = in.chi_star[o];
+                a0[k] = in.damp[o];
+                idl[k] = in.inv_dld[o];
             }
-            if (m > 0 && logm) {
-                float se = ee * (float)ds0, sc = cc * (float)ds0;
-                ee = __logf(se > 1e-37f ? se : 1e-37f);
-                cc = __logf(sc > 1e-37f ? sc : 1e-37f);
-            }
-            // pairwise reduction of the brick into level-m cells, level by level
-            // (sub-level s holds (B >> s)^D values at the front of the array).
-            fe[tid] = ee;
-            fc[tid] = cc;
-            __syncthreads();
-            for (int s = 1; s <= m; ++s) {
-                const int sd = B >> s;
-                const int nc = D == 2 ? sd * sd : sd * sd * sd;
-                float re = 0.f, rc = 0.f;
-                if (tid < nc) {
-                    int idx[8];
-                    children<D>(tid, sd, idx);
-                    float q[8];
-                    for (int j = 0; j < (1 << D); ++j) q[j] = fe[idx[j]];
-                    re = tsum<D>(q) / (float)(1 << D);
-                    for (int j = 0; j < (1 << D); ++j) q[j] = fc[idx[j]];
-                    rc = tsum<D>(q) / (float)(1 << D);
+#pragma unroll
+            for (int l = 0; l < kLam; ++l) {
+                float ee = eb, cc = cb;
+                for (int k = 0; k < lb.n_lines; ++k) {
+                    float x = fmaf(k0[k], uk, lam_dl[l][k]) * idl[k];
+                    float phi = line_shape(lb.profile, x, a0[k], lb.lam[l], lb.lam0[k], idl[k]);
+                    ee = fmaf(es[k], phi, ee);
+                    cc = fmaf(cs[k], phi, cc);
                 }
-                __syncthreads();
-                if (tid < nc) {
-                    fe[tid] = re;
-                    fc[tid] = rc;
-                }
-                __syncthreads();
-            }
-            if (tid < ncell) {
-                float oe = fe[tid], oc = fc[tid];
                 if (m > 0 && logm) {
-                    oe = __expf(oe) / (float)ds0;
-                    oc = __expf(oc) / (float)ds0;
+                    float se = ee * ds0, sc = cc * ds0;
+                    ee = __logf(se > 1e-37f ? se : 1e-37f);
+                    cc = __logf(sc > 1e-37f ? sc : 1e-37f);
                 }
-                float* r = bufs.vnodes + (((rec + tid) * n_v + kn) * kLam + l) * 2;
-                r[0] = oe;
-                r[1] = oc;
+                ae[l] += ee;
+                ac[l] += cc;
             }
-            __syncthreads();
+        }
+        const float inv = 1.0f / (float)nvx;
+        float4* out = (float4*)(bufs.vnodes + ((rec * n_v + kn) * kLam) * 2);
+#pragma unroll
+        for (int l = 0; l < kLam; l += 2) {
+            float r[4];
+            for (int j = 0; j < 2; ++j) {
+                float oe = ae[l + j] * inv, oc = ac[l + j] * inv;
+                if (m > 0 && logm) {
+                    oe = __expf(oe) / ds0;
+                    oc = __expf(oc) / ds0;
+                }
+                r[2 * j] = oe;
+                r[2 * j + 1] = oc;
+            }
+            out[l / 2] = make_float4(r[0], r[1], r[2], r[3]);
         }
     }
 }
@@ -178,10 +198,12 @@ hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBuf
                                   const LamBatch& lb, int n_v, double ds0, int avg_mode, hipStream_t s)
 {
     if (n_active == 0) return hipSuccess;
-    size_t shm = sizeof(float) * 2 * (size_t)g.bvox;
-    dim3 grid((unsigned)n_active, (unsigned)g.n_levels);
-    if (g.dim == 2) hipLaunchKernelGGL(k_velinterp_nodes<2>, grid, dim3(g.bvox), shm, s, g, in, b, lb, n_v, ds0, avg_mode);
-    else hipLaunchKernelGGL(k_velinterp_nodes<3>, grid, dim3(g.bvox), shm, s, g, in, b, lb, n_v, ds0, avg_mode);
+    if (g.dim == 2)
+        hipLaunchKernelGGL(k_velinterp_nodes2<2>, dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, (float)ds0,
+                           avg_mode);
+    else
+        hipLaunchKernelGGL(k_velinterp_nodes2<3>, dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, (float)ds0,
+                           avg_mode);
     return hipGetLastError();
 }
 

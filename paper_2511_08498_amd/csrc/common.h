@@ -30,7 +30,7 @@ struct Geo {
     int lvl_off[kMaxLevels + 1];  // first cell of each level inside a block record
     long long nblocks;
     int n_state_words;
-    int pad_;
+    int feat_level;   // level whose statistics are kept as neural-cache features (min(2, n_levels - 1))
 };
 
 // Wavelength constants of one batch (line model).  Doubles: the kernels form
@@ -54,9 +54,11 @@ struct SceneBufs {
     int8_t* levels;         // [nblocks] current batch
     uint64_t* states;       // [n_state_words]
     void* vals;             // [n_active][cells][kLam][2] static emission values (storage dtype)
-    float4* vgrid;          // [n_active][cells] velocity grid: V, vbar (velocity interpolation)
+    float4* vgrid;          // [n_active][cells] velocity grid: (n_v-1)/(2V) (0 if V = 0), vbar
+    float* vmax;            // [n_active][cells] V = max |v| over the cell's MIP-0 voxels
     float* vnodes;          // [n_active][cells][n_v][kLam][2] node values (velocity interpolation)
     float* cav;             // [n_active][cells][cav_rec] line parameters (Core and Voigt)
+    float4* fstats;         // [n_active][cells at feat_level][kLam]: mean, var of ln(chi ds0), mean, var of ln(eta ds0)
     unsigned long long* err;  // [2]: step-cap hits, first ray id (min)
 };
 
@@ -115,7 +117,7 @@ hipError_t launch_build_static(const Geo& g, const Inputs& in, const SceneBufs& 
                                int vrule, const LamBatch& lb, int lam_begin, double ds0, double T, double tau_thin,
                                int cap, int avg_mode, int storage, int write_values, hipStream_t s);
 hipError_t launch_pack_states(const Geo& g, const int8_t* levels, uint64_t* states, hipStream_t s);
-hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, hipStream_t s);
+hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, hipStream_t s);
 hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
                                   const LamBatch& lb, int n_v, double ds0, int avg_mode, hipStream_t s);
 hipError_t launch_cav_chain(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_lines,
@@ -152,8 +154,46 @@ struct TraceLaunch {
     LamBatch lb;
     unsigned long long* stats;
     unsigned long long* err;
+    // truncated march (neural radiance cache)
+    int trunc;
+    int gen;
+    double t_trunc;
+    const uint8_t* fallback;   // [nblocks] 1 = march on past t_trunc
+    const float4* fstats;
+    float* I_near;
+    float* T_near;
+    float* I_far;
+    float4* feat;              // [n_dir][n_probes]
+    float4* fstat_out;         // [n_dir][nl][n_probes]
 };
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s);
+
+// One job of the batched persistent trace (static emission).
+struct BatchJob {
+    Geo g;
+    const uint64_t* states;
+    const int32_t* slot;
+    const void* vals;
+    const int32_t* active_list;
+    const float* dirs;
+    float* I;
+    long long n_probes;
+    unsigned tile0;     // first queue tile of this job
+    int tiles;          // 64-probe tiles per direction
+    int n_dir;
+    int nl;
+    int mode;
+    int max_level;
+    int graded;
+    int step_cap;
+    int storage;
+    float I0;
+    float ds0;
+    float level_dist[kMaxLevels];
+};
+hipError_t launch_batched(const BatchJob* d_jobs, int n_jobs, unsigned total_tiles, int wg_waves, int n_wgs,
+                          int tiles_per_pop, unsigned* counter, unsigned* claims, unsigned long long* err,
+                          hipStream_t s);
 hipError_t launch_debug_visited(const TraceLaunch& t, int probe_vox, float wx, float wy, float wz, int cap,
                                 int32_t* cells, double* tt, int32_t* count, hipStream_t s);
 

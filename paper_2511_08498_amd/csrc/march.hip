@@ -66,7 +66,8 @@ __device__ __forceinline__ int graded_cap(const float* ld, int nlev, int d2, dou
 
 // Traverses the adapted grid from voxel centre pv upwind along -w.  Calls
 // vis.seg(c, level, block, t0, t1) for every non-empty cell in order of
-// increasing t.  Returns 0 when the ray left the grid, 1 at the step cap.
+// increasing t.  Returns 0 when the ray left the grid, 1 at the step cap and
+// 2 when the visitor asked to stop (truncated march).
 // With `graded`, a block's level is also capped by the path length at which
 // the ray enters it (ld: level_dist).
 template <int D, class Vis>
@@ -139,7 +140,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         }
         const double tn = (double)d2s0 * 0.5 * iw[s0];
         if (lvl >= 0) {
-            vis.seg(c, lvl, blk, t, tn);
+            if (vis.seg(c, lvl, blk, t, tn)) return 2;
             ++cnt.segs;
         } else {
             ++cnt.empty;
@@ -192,15 +193,15 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
 // One segment, one wavelength, front to back:
 //   I += T (eta dt) g(tau),  T *= exp(-tau),  g(tau) = (1 - exp(-tau)) / tau,
 // which is S (1 - exp(-tau)) with S = eta/chi and stays finite at chi = 0.
-// g uses its Taylor series below tau = 1/16 (no cancellation in 1 - exp).
+// g uses 1 - tau/2 + tau^2/6 below tau = 1/32 (truncation < tau^3/24 < 1.3e-6
+// relative) and (1 - exp(-tau)) / tau above (cancellation < 2e-6 relative).
 __device__ __forceinline__ void rte_step(float& I, float& Tr, float eta, float chi, float dt)
 {
     float tau = chi * dt;
     float e = __expf(-tau);
-    float gp = fmaf(tau, fmaf(tau, fmaf(tau, fmaf(tau, fmaf(tau, -1.0f / 720.0f, 1.0f / 120.0f), -1.0f / 24.0f),
-                                        1.0f / 6.0f), -0.5f), 1.0f);
+    float gp = fmaf(tau, fmaf(tau, 1.0f / 6.0f, -0.5f), 1.0f);
     float gd = (1.0f - e) * __builtin_amdgcn_rcpf(tau);
-    float gg = tau < 0.0625f ? gp : gd;
+    float gg = tau < 0.03125f ? gp : gd;
     I = fmaf(Tr * (eta * dt), gg, I);
     Tr *= e;
 }
@@ -268,49 +269,155 @@ __device__ __forceinline__ int local_index(const Geo& g, const int* c, int lvl, 
     return li;
 }
 
-// ------------------------------------------------------------- visitors
-template <int D, typename T>
-struct VisStatic {
-    const TraceLaunch* tl;
-    long long cur_blk;
-    long long base;
-    float dsf;
+// --------------------------------------------------------- accumulators
+// Plain: the whole ray, front to back.
+struct AccPlain {
+    static constexpr bool kTrunc = false;
     float I[kLam], Tr[kLam];
-    __device__ void init(const TraceLaunch* t, const float*)
+    __device__ void init(const TraceLaunch*)
     {
-        tl = t;
-        cur_blk = -1;
-        base = 0;
-        dsf = t->ds0;
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
             I[l] = 0.f;
             Tr[l] = 1.f;
         }
     }
-    __device__ __forceinline__ void seg(const int* c, int lvl, long long blk, double t0, double t1)
+    __device__ __forceinline__ bool add(const float* e, const float* x, const int*, int, long long, double t0,
+                                        double t1, float dsf)
     {
-        if (blk != cur_blk) {
-            cur_blk = blk;
-            base = (long long)tl->slot[blk] * tl->g.cells;
-        }
-        const T* r = (const T*)tl->vals + (base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D)) * (kLam * 2);
-        float e[kLam], x[kLam];
-        load_rec<T>(r, e, x);
         float dt = (float)(t1 - t0) * dsf;
 #pragma unroll
         for (int l = 0; l < kLam; ++l) rte_step(I[l], Tr[l], e[l], x[l], dt);
+        return false;
     }
 };
 
-template <int D>
+// Truncated: the near field t < t_trunc and the far field t >= t_trunc are
+// accumulated separately (the cell that straddles t_trunc is split there,
+// exactly, since eta and chi are constant in it).  Generation mode keeps
+// marching to record the far field; inference mode stops at t_trunc, unless
+// the block reached there is flagged in the fallback map, in which case the
+// ray continues as a full march.  t* = max(t_trunc, entry of the first
+// non-empty cell beyond it): the far field from t* equals the one from t_trunc.
+struct AccTrunc {
+    static constexpr bool kTrunc = true;
+    float In[kLam], Tn[kLam], If[kLam], Tf[kLam];
+    double tt;
+    const uint8_t* fallback;
+    int gen, reached, fb, tlvl;
+    int tc[3];
+    long long tblk;
+    double tstar;
+    __device__ void init(const TraceLaunch* t)
+    {
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            In[l] = 0.f;
+            Tn[l] = 1.f;
+            If[l] = 0.f;
+            Tf[l] = 1.f;
+        }
+        tt = t->t_trunc;
+        fallback = t->fallback;
+        gen = t->gen;
+        reached = fb = 0;
+        tlvl = 0;
+        tc[0] = tc[1] = tc[2] = 0;
+        tblk = 0;
+        tstar = 0.0;
+    }
+    __device__ __forceinline__ void near(const float* e, const float* x, double t0, double t1, float dsf)
+    {
+        float dt = (float)(t1 - t0) * dsf;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) rte_step(In[l], Tn[l], e[l], x[l], dt);
+    }
+    __device__ __forceinline__ void far(const float* e, const float* x, double t0, double t1, float dsf)
+    {
+        float dt = (float)(t1 - t0) * dsf;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) rte_step(If[l], Tf[l], e[l], x[l], dt);
+    }
+    __device__ __forceinline__ bool add(const float* e, const float* x, const int* c, int lvl, long long blk,
+                                        double t0, double t1, float dsf)
+    {
+        if (reached) {
+            if (fb) near(e, x, t0, t1, dsf);
+            else far(e, x, t0, t1, dsf);
+            return false;
+        }
+        if (t1 <= tt) {
+            near(e, x, t0, t1, dsf);
+            return false;
+        }
+        reached = 1;
+        tstar = t0 > tt ? t0 : tt;
+        tc[0] = c[0];
+        tc[1] = c[1];
+        tc[2] = c[2];
+        tlvl = lvl;
+        tblk = blk;
+        if (fallback && fallback[blk]) {
+            // full march from here on, without splitting this cell: the result is
+            // bit-identical to the plain march
+            fb = 1;
+            near(e, x, t0, t1, dsf);
+            return false;
+        }
+        if (t0 < tt) near(e, x, t0, tt, dsf);
+        if (!gen) return true;
+        far(e, x, tstar, t1, dsf);
+        return false;
+    }
+};
+
+// ------------------------------------------------------------- visitors
+template <int D, typename T, class Acc = AccPlain>
+struct VisStatic {
+    using AccT = Acc;
+    const Geo* g;
+    const int32_t* slot;
+    const T* vals;
+    long long cur_blk;
+    long long base;
+    float dsf;
+    Acc acc;
+    __device__ void init_src(const Geo* geo, const int32_t* sl, const void* v, float ds0)
+    {
+        g = geo;
+        slot = sl;
+        vals = (const T*)v;
+        cur_blk = -1;
+        base = 0;
+        dsf = ds0;
+    }
+    __device__ void init(const TraceLaunch* t, const float*)
+    {
+        init_src(&t->g, t->slot, t->vals, t->ds0);
+        acc.init(t);
+    }
+    __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
+    {
+        if (blk != cur_blk) {
+            cur_blk = blk;
+            base = (long long)slot[blk] * g->cells;
+        }
+        const T* r = vals + (base + g->lvl_off[lvl] + local_index(*g, c, lvl, D)) * (kLam * 2);
+        float e[kLam], x[kLam];
+        load_rec<T>(r, e, x);
+        return acc.add(e, x, c, lvl, blk, t0, t1, dsf);
+    }
+};
+
+template <int D, class Acc = AccPlain>
 struct VisVelinterp {
+    using AccT = Acc;
     const TraceLaunch* tl;
     long long cur_blk;
     long long base;
     float dsf;
     float w[3];
-    float I[kLam], Tr[kLam];
+    Acc acc;
     __device__ void init(const TraceLaunch* t, const float* wf)
     {
         tl = t;
@@ -320,46 +427,41 @@ struct VisVelinterp {
         w[0] = wf[0];
         w[1] = wf[1];
         w[2] = D > 2 ? wf[2] : 0.f;
-#pragma unroll
-        for (int l = 0; l < kLam; ++l) {
-            I[l] = 0.f;
-            Tr[l] = 1.f;
-        }
+        acc.init(t);
     }
-    __device__ __forceinline__ void seg(const int* c, int lvl, long long blk, double t0, double t1)
+    __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
     {
         if (blk != cur_blk) {
             cur_blk = blk;
             base = (long long)tl->slot[blk] * tl->g.cells;
         }
-        long long cell = base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D);
-        float4 vg = tl->vgrid[cell];  // V, vbar
+        const unsigned cell = (unsigned)(base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D));
+        // vgrid = (s, vbar): node coordinate f = (u + V)/(2V) (n_v - 1) = u s + (n_v - 1)/2,
+        // s = (n_v - 1)/(2V) (0 when V = 0: all nodes are equal, the middle one is used)
+        float4 vg = tl->vgrid[cell];
         float u = vg.y * w[0] + vg.z * w[1] + (D > 2 ? vg.w * w[2] : 0.f);
         const int nv = tl->n_v;
-        int kn = 0;
-        float wt = 0.f;
-        if (vg.x > 0.f) {
-            float f = (u + vg.x) / (2.0f * vg.x) * (float)(nv - 1);
-            kn = (int)floorf(f);
-            kn = kn < 0 ? 0 : (kn > nv - 2 ? nv - 2 : kn);
-            wt = f - (float)kn;
-        }
-        const float* r0 = tl->vnodes + (cell * nv + kn) * (kLam * 2);
+        float f = fmaf(u, vg.x, 0.5f * (float)(nv - 1));
+        int kn = (int)floorf(f);
+        kn = kn < 0 ? 0 : (kn > nv - 2 ? nv - 2 : kn);
+        float wt = f - (float)kn;
+        const float* r0 = tl->vnodes + (cell * (unsigned)nv + (unsigned)kn) * (unsigned)(kLam * 2);
         float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
         load_rec<float>(r0, e0, x0);
         load_rec<float>(r0 + kLam * 2, e1, x1);
-        float dt = (float)(t1 - t0) * dsf;
+        float ee[kLam], xx[kLam];
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
-            float ee = fmaf(wt, e1[l] - e0[l], e0[l]);
-            float xx = fmaf(wt, x1[l] - x0[l], x0[l]);
-            rte_step(I[l], Tr[l], ee, xx, dt);
+            ee[l] = fmaf(wt, e1[l] - e0[l], e0[l]);
+            xx[l] = fmaf(wt, x1[l] - x0[l], x0[l]);
         }
+        return acc.add(ee, xx, c, lvl, blk, t0, t1, dsf);
     }
 };
 
-template <int D>
+template <int D, class Acc = AccPlain>
 struct VisCav {
+    using AccT = Acc;
     const TraceLaunch* tl;
     long long cur_blk;
     long long base;
@@ -368,7 +470,7 @@ struct VisCav {
     float dl[kLam][kMaxLines];  // lam - lam0
     float k0[kMaxLines];        // lam0 / c
     float rr[kLam][kMaxLines];  // lam / lam0
-    float I[kLam], Tr[kLam];
+    Acc acc;
     __device__ void init(const TraceLaunch* t, const float* wf)
     {
         tl = t;
@@ -387,13 +489,9 @@ struct VisCav {
                 rr[l][k] = (float)(t->lb.lam[l] / t->lb.lam0[k]);
             }
         }
-#pragma unroll
-        for (int l = 0; l < kLam; ++l) {
-            I[l] = 0.f;
-            Tr[l] = 1.f;
-        }
+        acc.init(t);
     }
-    __device__ __forceinline__ void seg(const int* c, int lvl, long long blk, double t0, double t1)
+    __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
     {
         if (blk != cur_blk) {
             cur_blk = blk;
@@ -417,8 +515,8 @@ struct VisCav {
         float vz = 0.f;
         if (D > 2) vz = ((const float*)r)[4 * nln + 4];
         float u = bgv.z * w[0] + bgv.w * w[1] + vz * w[2];
-        float dt = (float)(t1 - t0) * dsf;
         const bool voigt = tl->lb.profile == RT_PROFILE_VOIGT;
+        float eo[kLam], xo[kLam];
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
             float ee = bgv.x, xx = bgv.y;
@@ -437,8 +535,10 @@ struct VisCav {
                     xx = fmaf(ls[k][1], phi, xx);
                 }
             }
-            rte_step(I[l], Tr[l], ee, xx, dt);
+            eo[l] = ee;
+            xo[l] = xx;
         }
+        return acc.add(eo, xo, c, lvl, blk, t0, t1, dsf);
     }
 };
 
@@ -483,11 +583,46 @@ __global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
     Vis vis;
     vis.init(&t, wf);
     Counters cnt = {0, 0, 0};
-    int capped = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+    int rc = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+    int capped = rc == 1;
     const int nl = t.lb.nl;
+    if constexpr (!Vis::AccT::kTrunc) {
 #pragma unroll
-    for (int l = 0; l < kLam; ++l) {
-        if (l < nl) t.I[((long long)dir * nl + l) * t.n_probes + probe] = fmaf(vis.Tr[l], t.I0, vis.I[l]);
+        for (int l = 0; l < kLam; ++l) {
+            if (l < nl) t.I[((long long)dir * nl + l) * t.n_probes + probe] = fmaf(vis.acc.Tr[l], t.I0, vis.acc.I[l]);
+        }
+    } else {
+        const auto& A = vis.acc;
+        const bool query = A.reached && !A.fb;
+        const long long pidx = dir * t.n_probes + probe;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            if (l >= nl) continue;
+            const long long q = ((long long)dir * nl + l) * t.n_probes + probe;
+            t.I_near[q] = query ? A.In[l] : fmaf(A.Tn[l], t.I0, A.In[l]);
+            t.T_near[q] = query ? A.Tn[l] : 0.f;
+            if (t.I_far) t.I_far[q] = query ? fmaf(A.Tf[l], t.I0, A.If[l]) : t.I0;
+        }
+        float px = 0.f, py = 0.f, pz = 0.f;
+        if (query) {
+            px = (float)((double)pv[0] + 0.5 - A.tstar * (double)wf[0]);
+            py = (float)((double)pv[1] + 0.5 - A.tstar * (double)wf[1]);
+            if (D > 2) pz = (float)((double)pv[2] + 0.5 - A.tstar * (double)wf[2]);
+            else pz = 0.5f;
+        }
+        t.feat[pidx] = make_float4(px, py, pz, query ? 1.f : 0.f);
+        // level statistics of the feature-level cell at the truncation point
+        const int fl = t.g.feat_level;
+        const int sl = t.g.log2B - fl;
+        int lx = (A.tc[0] & (t.g.B - 1)) >> fl, ly = (A.tc[1] & (t.g.B - 1)) >> fl;
+        int lz = D > 2 ? ((A.tc[2] & (t.g.B - 1)) >> fl) : 0;
+        long long fcell = query ? (long long)t.slot[A.tblk] * (1ll << (D * sl)) + lx + (ly << sl) + (lz << (2 * sl)) : 0;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            if (l >= nl) continue;
+            float4 st = query ? t.fstats[fcell * kLam + l] : make_float4(0.f, 0.f, 0.f, 0.f);
+            t.fstat_out[((long long)dir * nl + l) * t.n_probes + probe] = st;
+        }
     }
     if (t.stats) {
         atomicAdd(&t.stats[0], (unsigned long long)cnt.segs);
@@ -513,24 +648,31 @@ static hipError_t launch_one(const TraceLaunch& t, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)
+template <class Acc>
+static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
 {
     if (t.emission == RT_EMIS_STATIC) {
         if (t.g.dim == 2) {
-            if (t.storage == RT_F32) return launch_one<2, VisStatic<2, float>>(t, s);
-            if (t.storage == RT_BF16) return launch_one<2, VisStatic<2, __hip_bfloat16>>(t, s);
-            return launch_one<2, VisStatic<2, __half>>(t, s);
+            if (t.storage == RT_F32) return launch_one<2, VisStatic<2, float, Acc>>(t, s);
+            if (t.storage == RT_BF16) return launch_one<2, VisStatic<2, __hip_bfloat16, Acc>>(t, s);
+            return launch_one<2, VisStatic<2, __half, Acc>>(t, s);
         }
-        if (t.storage == RT_F32) return launch_one<3, VisStatic<3, float>>(t, s);
-        if (t.storage == RT_BF16) return launch_one<3, VisStatic<3, __hip_bfloat16>>(t, s);
-        return launch_one<3, VisStatic<3, __half>>(t, s);
+        if (t.storage == RT_F32) return launch_one<3, VisStatic<3, float, Acc>>(t, s);
+        if (t.storage == RT_BF16) return launch_one<3, VisStatic<3, __hip_bfloat16, Acc>>(t, s);
+        return launch_one<3, VisStatic<3, __half, Acc>>(t, s);
     }
     if (t.emission == RT_EMIS_VELINTERP) {
-        if (t.g.dim == 2) return launch_one<2, VisVelinterp<2>>(t, s);
-        return launch_one<3, VisVelinterp<3>>(t, s);
+        if (t.g.dim == 2) return launch_one<2, VisVelinterp<2, Acc>>(t, s);
+        return launch_one<3, VisVelinterp<3, Acc>>(t, s);
     }
-    if (t.g.dim == 2) return launch_one<2, VisCav<2>>(t, s);
-    return launch_one<3, VisCav<3>>(t, s);
+    if (t.g.dim == 2) return launch_one<2, VisCav<2, Acc>>(t, s);
+    return launch_one<3, VisCav<3, Acc>>(t, s);
+}
+
+hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)
+{
+    if (t.trunc) return launch_trace_acc<AccTrunc>(t, s);
+    return launch_trace_acc<AccPlain>(t, s);
 }
 
 // --------------------------------------------------- debug: visited cells
@@ -539,7 +681,7 @@ struct VisRecord {
     double* tt;
     int cap;
     int n;
-    __device__ void seg(const int* c, int lvl, long long, double t0, double t1)
+    __device__ bool seg(const int* c, int lvl, long long, double t0, double t1)
     {
         if (n < cap) {
             cells[4 * n] = c[0];
@@ -550,6 +692,7 @@ struct VisRecord {
             tt[2 * n + 1] = t1;
         }
         ++n;
+        return false;
     }
 };
 
@@ -580,6 +723,85 @@ hipError_t launch_debug_visited(const TraceLaunch& t, int probe_vox, float wx, f
     else
         hipLaunchKernelGGL(k_debug_visited<3>, dim3(1), dim3(64), shm, s, t, probe_vox, wx, wy, wz, cap, cells, tt,
                            count);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------ batched persistent
+// One queue of 64-probe tiles over all jobs (scenes).  Each wave pops tiles
+// with one atomic per `tiles_per_pop` tiles and traces them until the queue is
+// empty, so uneven scenes and uneven ray lengths balance dynamically.  Every
+// wave exits once the counter has passed the last tile.
+template <int D, typename T>
+__device__ __forceinline__ void batched_ray(const BatchJob& J, long long dir, long long probe, unsigned long long* err)
+{
+    long long slot = probe >> (D * J.g.log2B);
+    int local = (int)(probe & (J.g.bvox - 1));
+    int blk = J.active_list[slot];
+    int pv[3] = {0, 0, 0};
+    pv[0] = (blk % J.g.nb[0]) * J.g.B + (local & (J.g.B - 1));
+    pv[1] = ((blk / J.g.nb[0]) % J.g.nb[1]) * J.g.B + ((local >> J.g.log2B) & (J.g.B - 1));
+    if (D > 2) pv[2] = (blk / (J.g.nb[0] * J.g.nb[1])) * J.g.B + (local >> (2 * J.g.log2B));
+    float wf[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int a = 0; a < D; ++a) wf[a] = J.dirs[dir * D + a];
+    VisStatic<D, T> vis;
+    vis.init_src(&J.g, J.slot, J.vals, J.ds0);
+    vis.acc.init(nullptr);
+    Counters cnt = {0, 0, 0};
+    int capped = hdda<D>(J.g, J.states, J.mode, J.max_level, J.graded, J.level_dist, pv, wf, J.step_cap, vis, cnt) == 1;
+#pragma unroll
+    for (int l = 0; l < kLam; ++l)
+        if (l < J.nl) J.I[((long long)dir * J.nl + l) * J.n_probes + probe] = fmaf(vis.acc.Tr[l], J.I0, vis.acc.I[l]);
+    if (capped) {
+        atomicAdd(&err[0], 1ull);
+        atomicMin(&err[1], (unsigned long long)(J.tile0 * 64ull + (unsigned long long)(dir * J.tiles * 64 + probe)));
+    }
+}
+
+__global__ void k_reset_queue(unsigned* counter) { *counter = 0u; }
+
+__global__ void __launch_bounds__(512) k_batched(const BatchJob* __restrict__ jobs, int n_jobs, unsigned total_tiles, int tiles_per_pop,
+                          unsigned* counter, unsigned* claims, unsigned long long* err)
+{
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        unsigned base = 0;
+        if (lane == 0) base = atomicAdd(counter, (unsigned)tiles_per_pop);
+        base = __shfl(base, 0, 64);
+        if (base >= total_tiles) break;
+        for (int q = 0; q < tiles_per_pop; ++q) {
+            const unsigned tile = base + (unsigned)q;
+            if (tile >= total_tiles) break;
+            int j = 0;
+            while (j + 1 < n_jobs && jobs[j + 1].tile0 <= tile) ++j;
+            const BatchJob& J = jobs[j];
+            const long long lt = (long long)(tile - J.tile0);
+            const long long dir = lt / J.tiles;
+            const long long probe = (lt - dir * J.tiles) * 64 + lane;
+            if (claims && lane == 0) atomicAdd(&claims[tile], 1u);
+            if (probe >= J.n_probes) continue;
+            if (J.g.dim == 2) {
+                if (J.storage == RT_F32) batched_ray<2, float>(J, dir, probe, err);
+                else if (J.storage == RT_BF16) batched_ray<2, __hip_bfloat16>(J, dir, probe, err);
+                else batched_ray<2, __half>(J, dir, probe, err);
+            } else {
+                if (J.storage == RT_F32) batched_ray<3, float>(J, dir, probe, err);
+                else if (J.storage == RT_BF16) batched_ray<3, __hip_bfloat16>(J, dir, probe, err);
+                else batched_ray<3, __half>(J, dir, probe, err);
+            }
+        }
+    }
+}
+
+hipError_t launch_batched(const BatchJob* d_jobs, int n_jobs, unsigned total_tiles, int wg_waves, int n_wgs,
+                          int tiles_per_pop, unsigned* counter, unsigned* claims, unsigned long long* err,
+                          hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_batched, dim3((unsigned)n_wgs), dim3((unsigned)(64 * wg_waves)), 0, s, d_jobs, n_jobs,
+                       total_tiles, tiles_per_pop, counter, claims, err);
     return hipGetLastError();
 }
 

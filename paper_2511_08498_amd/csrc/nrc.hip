@@ -1,0 +1,836 @@
+// Neural radiance cache: a small MLP that supplies the far-field intensity at
+// the point where a ray is truncated, so the march stops after a fixed path
+// length (256 -> 4 x 64 SiLU -> 1, BF16 weights and activations, FP32
+// accumulation on the matrix cores).
+//
+// Input of one query (a ray truncated at point x, direction w, batch
+// wavelength lam): 16-frequency Fourier features (sin, cos) of the
+// normalised position (3), the direction (3) and the wavelength offset (1)
+// = 224 values, then 4 level statistics of the cell at x (mean and variance
+// of ln chi, mean of ln S, variance of ln eta), zero padded to 256.  The
+// output is ln(I_far) / 10.
+//
+// Matrix layout of v_mfma_f32_16x16x32_bf16 used here: lane i holds
+// A[i % 16][k-slice of group i / 16] and B[same k-slice][i % 16] (the same
+// k-slots for A and B), and D[4 (i / 16) + j][i % 16], j = 0..3.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "scene_impl.h"
+
+namespace rt {
+
+constexpr int kFeat = 256;
+constexpr int kHid = 64;
+constexpr int kNFreq = 16;
+constexpr int kRaw = 12;  // pos 3, dir 3, lam 1, stats 4, weight 1
+
+// parameter layout (FP32 master copy and BF16 working copy share it)
+constexpr int kOffW1 = 0;
+constexpr int kOffB1 = kOffW1 + kHid * kFeat;
+constexpr int kOffW2 = kOffB1 + kHid;
+constexpr int kOffB2 = kOffW2 + kHid * kHid;
+constexpr int kOffW3 = kOffB2 + kHid;
+constexpr int kOffB3 = kOffW3 + kHid * kHid;
+constexpr int kOffW4 = kOffB3 + kHid;
+constexpr int kOffB4 = kOffW4 + kHid * kHid;
+constexpr int kOffW5 = kOffB4 + kHid;
+constexpr int kOffB5 = kOffW5 + kHid;
+constexpr int kNParams = kOffB5 + 1;
+constexpr int kParamsPadded = (kNParams + 255) & ~255;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ __forceinline__ float silu_grad(float z)
+{
+    float s = 1.0f / (1.0f + __expf(-z));
+    return s * (1.0f + z * (1.0f - s));
+}
+
+// Encoded input value k of a query with raw features r (pos 3, dir 3, lam, stats 4).
+__device__ __forceinline__ float encode(const float* r, int k, float lg2fmax)
+{
+    if (k < 224) {
+        int q = k >> 5, j = (k & 31) >> 1;
+        float f = exp2f((float)j * lg2fmax * (1.0f / 15.0f));
+        // reduce to whole turns before the (fast) sine and cosine
+        float turns = f * r[q];
+        turns -= rintf(turns);
+        float arg = 6.283185307179586f * turns;
+        return (k & 1) ? __cosf(arg) : __sinf(arg);
+    }
+    if (k < 228) return r[7 + (k - 224)];
+    return 0.0f;
+}
+
+// ----------------------------------------------------------- forward pass
+struct NrcFwd {
+    const __bf16* wb;     // BF16 parameters
+    const float* wf;      // FP32 parameters (biases, output layer)
+    float lg2fmax;
+    int mode;             // 0: training rows, 1: inference-compose
+    long long rows;
+    // training rows
+    const float* raw;     // [n][kRaw]
+    const float* target;  // [n]
+    long long n_raw;
+    unsigned long long seed;
+    int step;
+    int sequential;       // rows taken in order (gradient check) instead of sampled
+    __bf16* x_out;        // [rows][256] encoded inputs (training)
+    float* z_out;         // [4][rows][64] pre-activations (training)
+    __bf16* h_out;        // [4][rows][64] activations (training)
+    float* dy;            // [rows] dLoss/dy (training)
+    float* yhat;          // [rows] predictions (optional)
+    float* loss_part;     // [gridDim] partial loss sums (training)
+    // inference-compose rows q = (d nl + l) np + p
+    const float4* feat;   // [n_dir][np] x, y, z, flag
+    const float4* fstat;  // [n_dir][nl][np] level statistics
+    const float* dirs;    // [n_dir][dim]
+    int dim;
+    int nl;
+    long long np;
+    float lamoff[kLam];
+    float inv_n[3];
+    const float* I_near;
+    const float* T_near;
+    float* I_out;
+};
+
+__device__ __forceinline__ unsigned long long mix64(unsigned long long x)
+{
+    x += 0x9E3779B97F4A7C15ull;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+    return x ^ (x >> 31);
+}
+
+// raw features (11 used) and weight/target of one row
+__device__ __forceinline__ void row_raw(const NrcFwd& a, long long row, float* r, float& w, float& tgt, bool& valid)
+{
+    valid = row < a.rows;
+    for (int k = 0; k < 11; ++k) r[k] = 0.f;
+    w = 0.f;
+    tgt = 0.f;
+    if (!valid) return;
+    if (a.mode == 0) {
+        long long src = a.sequential ? row : (long long)(mix64(a.seed ^ ((unsigned long long)a.step << 32) ^
+                                                                (unsigned long long)row) % (unsigned long long)a.n_raw);
+        const float* p = a.raw + src * kRaw;
+        for (int k = 0; k < 11; ++k) r[k] = p[k];
+        w = p[11];
+        tgt = a.target[src];
+    } else {
+        long long per_dir = (long long)a.nl * a.np;
+        long long d = row / per_dir;
+        long long rem = row - d * per_dir;
+        long long l = rem / a.np, p = rem - l * a.np;
+        float4 f = a.feat[d * a.np + p];
+        r[0] = f.x * a.inv_n[0];
+        r[1] = f.y * a.inv_n[1];
+        r[2] = f.z * a.inv_n[2];
+        for (int c = 0; c < a.dim; ++c) r[3 + c] = a.dirs[d * a.dim + c];
+        r[6] = a.lamoff[l];
+        float4 s = a.fstat[(d * a.nl + l) * a.np + p];
+        r[7] = s.x * 0.1f;
+        r[8] = log1pf(fmaxf(s.y, 0.f));
+        r[9] = (s.z - s.x) * 0.1f;
+        r[10] = log1pf(fmaxf(s.w, 0.f));
+        w = f.w;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sW1[kHid * kFeat];
+    __shared__ __attribute__((aligned(16))) __bf16 sW[3][kHid * kHid];
+    __shared__ __attribute__((aligned(16))) __bf16 sH[4][16 * kHid];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    {
+        const uint4* src = (const uint4*)(a.wb + kOffW1);
+        uint4* dst = (uint4*)sW1;
+        for (int i = tid; i < kHid * kFeat / 8; i += blockDim.x) dst[i] = src[i];
+        for (int L = 0; L < 3; ++L) {
+            const uint4* s2 = (const uint4*)(a.wb + kOffW2 + L * (kHid * kHid + kHid));
+            uint4* d2 = (uint4*)sW[L];
+            for (int i = tid; i < kHid * kHid / 8; i += blockDim.x) d2[i] = s2[i];
+        }
+    }
+    __syncthreads();
+    const int r16 = lane & 15, g = lane >> 4;
+    // per-lane bias / output weights for the 4 column tiles
+    float bias[4][4], w5[4];
+    for (int nt = 0; nt < 4; ++nt) {
+        int c = 16 * nt + r16;
+        bias[0][nt] = a.wf[kOffB1 + c];
+        bias[1][nt] = a.wf[kOffB2 + c];
+        bias[2][nt] = a.wf[kOffB3 + c];
+        bias[3][nt] = a.wf[kOffB4 + c];
+        w5[nt] = a.wf[kOffW5 + c];
+    }
+    const float b5 = a.wf[kOffB5];
+    float lsum = 0.f;
+    const long long n_tiles = (a.rows + 15) / 16;
+    const long long wstride = (long long)gridDim.x * 4;
+    for (long long tile = (long long)blockIdx.x * 4 + wv; tile < n_tiles; tile += wstride) {
+        const long long row_a = tile * 16 + r16;  // the row this lane feeds as an A operand
+        float r[11], w, tgt;
+        bool valid;
+        row_raw(a, row_a, r, w, tgt, valid);
+        // ---- layer 1: 256 -> 64
+        f32x4 acc[4];
+        for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < kFeat / 32; ++ks) {
+            bf16x8 av;
+            const int k0 = 32 * ks + 8 * g;
+            for (int j = 0; j < 8; ++j) av[j] = (__bf16)(valid ? encode(r, k0 + j, a.lg2fmax) : 0.f);
+            if (a.mode == 0 && a.x_out && valid) *(bf16x8*)(a.x_out + row_a * kFeat + k0) = av;
+            for (int nt = 0; nt < 4; ++nt) {
+                bf16x8 bv = *(const bf16x8*)(sW1 + (16 * nt + r16) * kFeat + k0);
+                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+            }
+        }
+        // ---- hidden layers
+        for (int L = 0; L < 4; ++L) {
+            // bias + SiLU; D element (row 4 g + j, col 16 nt + r16)
+            for (int nt = 0; nt < 4; ++nt)
+                for (int j = 0; j < 4; ++j) {
+                    float z = acc[nt][j] + bias[L][nt];
+                    float h = silu(z);
+                    const int row = 4 * g + j, col = 16 * nt + r16;
+                    sH[wv][row * kHid + col] = (__bf16)h;
+                    const long long grow = tile * 16 + row;
+                    if (a.mode == 0 && grow < a.rows) {
+                        if (a.z_out) a.z_out[((long long)L * a.rows + grow) * kHid + col] = z;
+                        if (a.h_out) a.h_out[((long long)L * a.rows + grow) * kHid + col] = (__bf16)h;
+                    }
+                    acc[nt][j] = h;
+                }
+            if (L == 3) break;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            f32x4 nacc[4];
+            for (int nt = 0; nt < 4; ++nt) nacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int ks = 0; ks < kHid / 32; ++ks) {
+                const int k0 = 32 * ks + 8 * g;
+                bf16x8 av = *(const bf16x8*)(&sH[wv][r16 * kHid + k0]);
+                for (int nt = 0; nt < 4; ++nt) {
+                    bf16x8 bv = *(const bf16x8*)(sW[L] + (16 * nt + r16) * kHid + k0);
+                    nacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, nacc[nt], 0, 0, 0);
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = nacc[nt];
+        }
+        // ---- output: y[row] = sum_c h4[row][c] w5[c] + b5 (h4 rounded to BF16 as the GEMMs see it)
+        float part[4];
+        for (int j = 0; j < 4; ++j) {
+            float s = 0.f;
+            for (int nt = 0; nt < 4; ++nt) s += (float)(__bf16)acc[nt][j] * w5[nt];
+            part[j] = s;
+        }
+        for (int o = 1; o < 16; o <<= 1)
+            for (int j = 0; j < 4; ++j) part[j] += __shfl_xor(part[j], o, 64);
+        // lanes with r16 == j hold row 4 g + j
+        float y = 0.f;
+        for (int j = 0; j < 4; ++j)
+            if (r16 == j) y = part[j] + b5;
+        if (r16 < 4) {
+            const long long grow = tile * 16 + 4 * g + r16;
+            float rr[11], ww, tt;
+            bool v2;
+            row_raw(a, grow, rr, ww, tt, v2);
+            if (v2) {
+                if (a.yhat) a.yhat[grow] = y;
+                if (a.mode == 0) {
+                    float e = y - tt;
+                    if (a.dy) a.dy[grow] = ww * 2.0f * e / (float)a.rows;
+                    lsum += ww * e * e;
+                } else if (ww > 0.f) {
+                    float yc = fminf(fmaxf(y, -8.0f), 8.0f);
+                    a.I_out[grow] = fmaf(a.T_near[grow], __expf(10.0f * yc), a.I_near[grow]);
+                } else {
+                    a.I_out[grow] = a.I_near[grow];
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (a.mode == 0 && a.loss_part) {
+        for (int o = 1; o < 64; o <<= 1) lsum += __shfl_xor(lsum, o, 64);
+        __syncthreads();  // every wave has left the tile loop: sH can be reused
+        float* wsum = (float*)&sH[0][0];
+        if (lane == 0) wsum[wv] = lsum;
+        __syncthreads();
+        if (tid == 0) a.loss_part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    }
+}
+
+hipError_t launch_nrc_forward(const NrcFwd& a, int n_wgs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_nrc_forward, dim3((unsigned)n_wgs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- generic GEMM
+// C_part[z][m][n] = sum over k in split z of A(m,k) B(k,n); A, B read with
+// arbitrary strides (BF16 or FP32, rounded to BF16), FP32 accumulation on the
+// matrix cores.  One wave per 16 x 16 tile.  M, N multiples of 16, K a
+// multiple of 32 x splits.
+template <typename TA, typename TB>
+__global__ void __launch_bounds__(256) k_gemm(const TA* A, long long sam, long long sak, const TB* B, long long sbk,
+                                              long long sbn, float* Cp, int M, int N, long long K, int splits)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tn = blockIdx.x * 4 + wv, tm = blockIdx.y, z = blockIdx.z;
+    if (tn * 16 >= N) return;
+    const int r16 = lane & 15, g = lane >> 4;
+    const long long kz = K / splits, k_begin = kz * z, k_end = k_begin + kz;
+    const long long m = (long long)tm * 16 + r16, n = (long long)tn * 16 + r16;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    for (long long k0 = k_begin; k0 < k_end; k0 += 32) {
+        bf16x8 av, bv;
+        for (int j = 0; j < 8; ++j) {
+            long long k = k0 + 8 * g + j;
+            av[j] = (__bf16)(float)A[m * sam + k * sak];
+            bv[j] = (__bf16)(float)B[k * sbk + n * sbn];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    float* C = Cp + (long long)z * M * N;
+    for (int j = 0; j < 4; ++j) C[((long long)tm * 16 + 4 * g + j) * N + n] = acc[j];
+}
+
+__global__ void k_reduce_splits(const float* Cp, int splits, long long MN, float* C)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MN) return;
+    float s = 0.f;
+    for (int z = 0; z < splits; ++z) s += Cp[(long long)z * MN + i];
+    C[i] = s;
+}
+
+template <typename TA, typename TB>
+hipError_t gemm(const TA* A, long long sam, long long sak, const TB* B, long long sbk, long long sbn, float* C,
+                float* scratch, int M, int N, long long K, int splits, hipStream_t s)
+{
+    dim3 grid((unsigned)((N / 16 + 3) / 4), (unsigned)(M / 16), (unsigned)splits);
+    if (splits == 1) {
+        hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, M, N, K, 1);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, scratch, M, N, K, splits);
+    long long MN = (long long)M * N;
+    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, scratch, splits, MN, C);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------- elementwise
+// dZ[r][c] = dH[r][c] silu'(Z[r][c]); dH either a GEMM result (FP32 [rows][64])
+// or, for the top layer, dy[r] w5[c].
+__global__ void k_dz(const float* dH, const float* dy, const float* w5, const float* Z, __bf16* dZ, long long rows)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= rows * kHid) return;
+    long long r = i / kHid;
+    int c = (int)(i - r * kHid);
+    float d = dH ? dH[i] : dy[r] * w5[c];
+    dZ[i] = (__bf16)(d * silu_grad(Z[i]));
+}
+
+// column sums over rows: out[c] = sum_r X[r][c] (X BF16 [rows][ncol]) or, with
+// h given, out[c] = sum_r dy[r] h[r][c] (output-layer weight gradient)
+template <typename T>
+__global__ void k_colsum(const T* X, const float* dy, long long rows, int ncol, float* out)
+{
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    float s = 0.f;
+    for (long long r = threadIdx.x; r < rows; r += blockDim.x) {
+        float v = (float)X[r * ncol + c];
+        s += dy ? dy[r] * v : v;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[c] = red[0];
+}
+
+__global__ void k_sum(const float* x, long long n, float* out)
+{
+    __shared__ float red[256];
+    float s = 0.f;
+    for (long long r = threadIdx.x; r < n; r += blockDim.x) s += x[r];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = red[0];
+}
+
+// Adam with FP32 master weights; refreshes the BF16 copy.
+__global__ void k_adam(float* w, float* m, float* v, const float* g, __bf16* wb, int n, float lr, float b1, float b2,
+                       float eps, float c1, float c2)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    w[i] = wi;
+    wb[i] = (__bf16)wi;
+}
+
+__global__ void k_to_bf16(const float* w, __bf16* wb, int n)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) wb[i] = (__bf16)w[i];
+}
+
+__global__ void k_fill0(float* x, long long n)
+{
+    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.f;
+}
+
+// pack generation-mode outputs into training rows (one row per (dir, lam, probe))
+struct NrcPack {
+    const float4* feat;
+    const float4* fstat;
+    const float* dirs;
+    const float* I_far;
+    int dim, nl;
+    long long np, n_dir;
+    float lamoff[kLam];
+    float inv_n[3];
+    float* raw;
+    float* target;
+    long long row0;
+};
+
+__global__ void k_nrc_pack(NrcPack a)
+{
+    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long rows = a.n_dir * a.nl * a.np;
+    if (q >= rows) return;
+    long long per_dir = (long long)a.nl * a.np;
+    long long d = q / per_dir, rem = q - d * per_dir, l = rem / a.np, p = rem - l * a.np;
+    float4 f = a.feat[d * a.np + p];
+    float4 st = a.fstat[q];
+    float* r = a.raw + (a.row0 + q) * kRaw;
+    r[0] = f.x * a.inv_n[0];
+    r[1] = f.y * a.inv_n[1];
+    r[2] = f.z * a.inv_n[2];
+    for (int c = 0; c < 3; ++c) r[3 + c] = c < a.dim ? a.dirs[d * a.dim + c] : 0.f;
+    r[6] = a.lamoff[l];
+    r[7] = st.x * 0.1f;
+    r[8] = log1pf(fmaxf(st.y, 0.f));
+    r[9] = (st.z - st.x) * 0.1f;
+    r[10] = log1pf(fmaxf(st.w, 0.f));
+    r[11] = f.w;
+    float If = a.I_far[q];
+    a.target[a.row0 + q] = f.w > 0.f ? __logf(fmaxf(If, 1e-30f)) * 0.1f : 0.f;
+}
+
+// held-out check: composed prediction vs the exact composition, per row;
+// blocks whose rows exceed the threshold fall back to the full march
+__global__ void k_nrc_validate(const float* I_pred, const float* I_near, const float* T_near, const float* I_far,
+                               const float4* feat, long long n_dir, int nl, long long np, int B, int log2B,
+                               int nb0, int nb1, int nb2, float thresh, uint8_t* fallback, float* err_out)
+{
+    long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    long long rows = n_dir * nl * np;
+    if (q >= rows) return;
+    long long per_dir = (long long)nl * np;
+    long long d = q / per_dir, rem = q - d * per_dir, p = rem - (rem / np) * np;
+    float4 f = feat[d * np + p];
+    float Itrue = fmaf(T_near[q], I_far[q], I_near[q]);
+    float e = f.w > 0.f ? fabsf(I_pred[q] - Itrue) / fmaxf(fabsf(Itrue), 1e-37f) : 0.f;
+    if (err_out) err_out[q] = e;
+    if (f.w > 0.f && e > thresh) {
+        int bx = min(max((int)floorf(f.x), 0) >> log2B, nb0 - 1);
+        int by = min(max((int)floorf(f.y), 0) >> log2B, nb1 - 1);
+        int bz = min(max((int)floorf(f.z), 0) >> log2B, nb2 - 1);
+        fallback[bx + (long long)nb0 * (by + (long long)nb1 * bz)] = 1;
+    }
+}
+
+}  // namespace rt
+
+// ---------------------------------------------------------------- host side
+using namespace rt;
+
+struct rt_nrc {
+    int max_batch = 0;
+    float lg2fmax = 0.f;
+    unsigned long long seed = 0;
+    int n_wgs = 512;
+    int step = 0;
+    int last_rows = 0;
+    float *w = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+    __bf16* wb = nullptr;
+    __bf16* X = nullptr;
+    float* Z = nullptr;
+    __bf16* H = nullptr;
+    float* dy = nullptr;
+    __bf16* dZ = nullptr;
+    float* dH = nullptr;
+    float* scratch = nullptr;
+    float* loss_part = nullptr;
+    std::vector<void*> allocs;
+    ~rt_nrc()
+    {
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t alloc(T** p, size_t n)
+    {
+        void* q = nullptr;
+        hipError_t e = hipMalloc(&q, std::max<size_t>(n * sizeof(T), 256));
+        if (e == hipSuccess) {
+            allocs.push_back(q);
+            *p = (T*)q;
+        }
+        return e;
+    }
+};
+
+#define NRC_HIP(call)                                                                                      \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess) return set_error(RT_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));  \
+    } while (0)
+
+static unsigned long long splitmix(unsigned long long& s)
+{
+    unsigned long long z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// forward over `rows` training-form rows; optional training outputs
+static hipError_t nrc_forward_rows(rt_nrc* nn, const float* raw, const float* target, long long n_raw, long long rows,
+                                   int sequential, bool train, float* yhat, hipStream_t s)
+{
+    NrcFwd a;
+    std::memset(&a, 0, sizeof(a));
+    a.wb = nn->wb;
+    a.wf = nn->w;
+    a.lg2fmax = nn->lg2fmax;
+    a.mode = 0;
+    a.rows = rows;
+    a.raw = raw;
+    a.target = target;
+    a.n_raw = n_raw;
+    a.seed = nn->seed;
+    a.step = nn->step;
+    a.sequential = sequential;
+    if (train) {
+        a.x_out = nn->X;
+        a.z_out = nn->Z;
+        a.h_out = nn->H;
+        a.dy = nn->dy;
+        a.loss_part = nn->loss_part;
+    }
+    a.yhat = yhat;
+    return launch_nrc_forward(a, nn->n_wgs, s);
+}
+
+// backward of the last training forward (rows in nn->X, Z, H, dy): gradients into nn->grad
+static hipError_t nrc_backward(rt_nrc* nn, long long rows, hipStream_t s)
+{
+    const long long R = rows;
+    const unsigned eb = (unsigned)((R * kHid + 255) / 256);
+    int splits = 1;
+    while (splits < 64 && (R / (splits * 2)) % 32 == 0 && R / (splits * 2) >= 256) splits *= 2;
+    hipError_t e;
+    const __bf16* Hl[4] = {nn->H, nn->H + R * kHid, nn->H + 2 * R * kHid, nn->H + 3 * R * kHid};
+    const float* Zl[4] = {nn->Z, nn->Z + R * kHid, nn->Z + 2 * R * kHid, nn->Z + 3 * R * kHid};
+    const int offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
+    const int offB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
+    // output layer
+    hipLaunchKernelGGL((k_colsum<__bf16>), dim3(kHid), dim3(256), 0, s, Hl[3], nn->dy, R, kHid, nn->grad + kOffW5);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, nn->dy, R, nn->grad + kOffB5);
+    // top hidden layer: dZ4 = dy w5 silu'(Z4)
+    hipLaunchKernelGGL(k_dz, dim3(eb), dim3(256), 0, s, (const float*)nullptr, nn->dy, nn->w + kOffW5, Zl[3], nn->dZ, R);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int L = 3; L >= 0; --L) {
+        // dW_L = dZ^T . (H_{L-1} or X); db_L = column sums of dZ
+        if (L > 0) {
+            e = gemm<__bf16, __bf16>(nn->dZ, 1, kHid, Hl[L - 1], kHid, 1, nn->grad + offW[L], nn->scratch, kHid, kHid, R,
+                                     splits, s);
+        } else {
+            e = gemm<__bf16, __bf16>(nn->dZ, 1, kHid, nn->X, kFeat, 1, nn->grad + offW[0], nn->scratch, kHid, kFeat, R,
+                                     splits, s);
+        }
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_colsum<__bf16>), dim3(kHid), dim3(256), 0, s, nn->dZ, (const float*)nullptr, R, kHid,
+                           nn->grad + offB[L]);
+        if (L == 0) break;
+        // dH_{L-1} = dZ_L . W_L ; dZ_{L-1} = dH silu'(Z_{L-1})
+        e = gemm<__bf16, __bf16>(nn->dZ, kHid, 1, nn->wb + offW[L], kHid, 1, nn->dH, nn->scratch, (int)R, kHid, kHid, 1, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_dz, dim3(eb), dim3(256), 0, s, nn->dH, (const float*)nullptr, (const float*)nullptr, Zl[L - 1],
+                           nn->dZ, R);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+extern "C" {
+
+rt_status rt_nrc_num_params(int32_t* n)
+{
+    if (!n) return set_error(RT_E_ARG, "null argument");
+    *n = kNParams;
+    return RT_OK;
+}
+
+rt_status rt_nrc_create(const rt_nrc_desc* d, void* stream, rt_nrc** out)
+{
+    if (!d || !out) return set_error(RT_E_ARG, "null argument");
+    *out = nullptr;
+    if (d->max_batch < 256 || d->max_batch % 256 != 0 || d->max_batch > (1 << 19))
+        return set_error(RT_E_ARG, "max_batch must be a multiple of 256 in [256, 2^19]");
+    if (!(d->freq_max >= 1.f)) return set_error(RT_E_ARG, "freq_max must be >= 1");
+    rt_nrc* nn = new (std::nothrow) rt_nrc();
+    if (!nn) return set_error(RT_E_ARG, "out of host memory");
+    nn->max_batch = d->max_batch;
+    nn->lg2fmax = std::log2(d->freq_max);
+    nn->seed = d->seed;
+    const size_t B = (size_t)d->max_batch;
+    hipError_t e = hipSuccess;
+    auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    A(nn->alloc(&nn->w, kParamsPadded));
+    A(nn->alloc(&nn->m, kParamsPadded));
+    A(nn->alloc(&nn->v, kParamsPadded));
+    A(nn->alloc(&nn->grad, kParamsPadded));
+    A(nn->alloc(&nn->wb, kParamsPadded));
+    A(nn->alloc(&nn->X, B * kFeat));
+    A(nn->alloc(&nn->Z, 4 * B * kHid));
+    A(nn->alloc(&nn->H, 4 * B * kHid));
+    A(nn->alloc(&nn->dy, B));
+    A(nn->alloc(&nn->dZ, B * kHid));
+    A(nn->alloc(&nn->dH, B * kHid));
+    A(nn->alloc(&nn->scratch, 64 * (size_t)kHid * kFeat));
+    A(nn->alloc(&nn->loss_part, (size_t)nn->n_wgs));
+    if (e != hipSuccess) {
+        delete nn;
+        return set_error(RT_E_HIP, "nrc allocation: %s", hipGetErrorString(e));
+    }
+    // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) for every weight and bias (seeded splitmix64)
+    std::vector<float> w0(kParamsPadded, 0.f);
+    unsigned long long st = d->seed;
+    struct Blk { int off, n, fan; } blks[] = {{kOffW1, kHid * kFeat, kFeat}, {kOffB1, kHid, kFeat}, {kOffW2, kHid * kHid, kHid},
+                                             {kOffB2, kHid, kHid}, {kOffW3, kHid * kHid, kHid}, {kOffB3, kHid, kHid},
+                                             {kOffW4, kHid * kHid, kHid}, {kOffB4, kHid, kHid}, {kOffW5, kHid, kHid},
+                                             {kOffB5, 1, kHid}};
+    for (const Blk& b : blks) {
+        float lim = 1.0f / std::sqrt((float)b.fan);
+        for (int i = 0; i < b.n; ++i) {
+            double u = (double)(splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+            w0[(size_t)(b.off + i)] = (float)((2.0 * u - 1.0) * lim);
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    e = hipMemcpyAsync(nn->w, w0.data(), sizeof(float) * w0.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_to_bf16, dim3((kParamsPadded + 255) / 256), dim3(256), 0, s, nn->w, nn->wb, kParamsPadded);
+        hipLaunchKernelGGL(k_fill0, dim3((kParamsPadded + 255) / 256), dim3(256), 0, s, nn->m, (long long)kParamsPadded);
+        hipLaunchKernelGGL(k_fill0, dim3((kParamsPadded + 255) / 256), dim3(256), 0, s, nn->v, (long long)kParamsPadded);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete nn;
+        return set_error(RT_E_HIP, "nrc init: %s", hipGetErrorString(e));
+    }
+    *out = nn;
+    return RT_OK;
+}
+
+void rt_nrc_destroy(rt_nrc* nn) { delete nn; }
+
+rt_status rt_nrc_get_weights(const rt_nrc* nn, float* h)
+{
+    if (!nn || !h) return set_error(RT_E_ARG, "null argument");
+    NRC_HIP(hipDeviceSynchronize());
+    NRC_HIP(hipMemcpy(h, nn->w, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    return RT_OK;
+}
+
+rt_status rt_nrc_set_weights(rt_nrc* nn, const float* h, void* stream)
+{
+    if (!nn || !h) return set_error(RT_E_ARG, "null argument");
+    hipStream_t s = (hipStream_t)stream;
+    NRC_HIP(hipMemcpyAsync(nn->w, h, sizeof(float) * kNParams, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_to_bf16, dim3((kParamsPadded + 255) / 256), dim3(256), 0, s, nn->w, nn->wb, kParamsPadded);
+    NRC_HIP(hipGetLastError());
+    NRC_HIP(hipStreamSynchronize(s));
+    return RT_OK;
+}
+
+rt_status rt_nrc_train(rt_nrc* nn, const float* d_raw, const float* d_target, int64_t n, int32_t steps, int32_t batch,
+                       float lr, void* stream)
+{
+    if (!nn || !d_raw || !d_target || n < 1 || steps < 0) return set_error(RT_E_ARG, "bad argument");
+    if (batch < 256 || batch % 256 != 0 || batch > nn->max_batch) return set_error(RT_E_ARG, "batch must be a multiple of 256 up to max_batch");
+    hipStream_t s = (hipStream_t)stream;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    for (int it = 0; it < steps; ++it) {
+        NRC_HIP(nrc_forward_rows(nn, d_raw, d_target, n, batch, 0, true, nullptr, s));
+        NRC_HIP(nrc_backward(nn, batch, s));
+        ++nn->step;
+        float c1 = 1.0f / (1.0f - std::pow(b1, (float)nn->step));
+        float c2 = 1.0f / (1.0f - std::pow(b2, (float)nn->step));
+        hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, nn->w, nn->m, nn->v, nn->grad, nn->wb,
+                           kNParams, lr, b1, b2, eps, c1, c2);
+        NRC_HIP(hipGetLastError());
+    }
+    nn->last_rows = batch;
+    return RT_OK;
+}
+
+rt_status rt_nrc_loss(const rt_nrc* nn, float* h_loss)
+{
+    if (!nn || !h_loss) return set_error(RT_E_ARG, "null argument");
+    if (nn->last_rows == 0) return set_error(RT_E_STATE, "no training step yet");
+    std::vector<float> part((size_t)nn->n_wgs);
+    NRC_HIP(hipDeviceSynchronize());
+    NRC_HIP(hipMemcpy(part.data(), nn->loss_part, sizeof(float) * part.size(), hipMemcpyDeviceToHost));
+    double t = 0;
+    for (float p : part) t += p;
+    *h_loss = (float)(t / nn->last_rows);
+    return RT_OK;
+}
+
+rt_status rt_nrc_gradients(rt_nrc* nn, const float* d_raw, const float* d_target, int64_t n, float* d_grad, void* stream)
+{
+    if (!nn || !d_raw || !d_target || !d_grad) return set_error(RT_E_ARG, "null argument");
+    if (n < 256 || n % 256 != 0 || n > nn->max_batch) return set_error(RT_E_ARG, "n must be a multiple of 256 up to max_batch");
+    hipStream_t s = (hipStream_t)stream;
+    NRC_HIP(nrc_forward_rows(nn, d_raw, d_target, n, n, 1, true, nullptr, s));
+    NRC_HIP(nrc_backward(nn, n, s));
+    NRC_HIP(hipMemcpyAsync(d_grad, nn->grad, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, s));
+    nn->last_rows = (int)n;
+    return RT_OK;
+}
+
+rt_status rt_nrc_predict(const rt_nrc* nn, const float* d_raw, int64_t n, float* d_y, void* stream)
+{
+    if (!nn || !d_raw || !d_y || n < 1) return set_error(RT_E_ARG, "bad argument");
+    NRC_HIP(nrc_forward_rows(const_cast<rt_nrc*>(nn), d_raw, d_y /* unused target */, n, n, 1, false, d_y,
+                             (hipStream_t)stream));
+    return RT_OK;
+}
+
+static void lam_offsets(const rt_scene* sc, float* out)
+{
+    const int nl = sc->batch_end - sc->batch_begin;
+    for (int l = 0; l < kLam; ++l) {
+        int il = sc->batch_begin + std::min(l, nl - 1);
+        if (!sc->lam.empty() && sc->lam.size() > 1) {
+            double lo = *std::min_element(sc->lam.begin(), sc->lam.end());
+            double hi = *std::max_element(sc->lam.begin(), sc->lam.end());
+            out[l] = (float)((sc->lam[(size_t)il] - lo) / (hi - lo));
+        } else {
+            out[l] = sc->desc.n_lam > 1 ? (float)il / (float)(sc->desc.n_lam - 1) : 0.f;
+        }
+    }
+}
+
+rt_status rt_nrc_pack(const rt_scene* sc, const float* d_dirs, int32_t n_dir, int64_t n_probes, const float* d_feat,
+                      const float* d_fstat, const float* d_I_far, float* d_raw, float* d_target, int64_t row0,
+                      void* stream)
+{
+    if (!sc || !d_dirs || !d_feat || !d_fstat || !d_I_far || !d_raw || !d_target) return set_error(RT_E_ARG, "null argument");
+    if (sc->batch_begin < 0) return set_error(RT_E_STATE, "no batch built");
+    NrcPack a;
+    std::memset(&a, 0, sizeof(a));
+    a.feat = (const float4*)d_feat;
+    a.fstat = (const float4*)d_fstat;
+    a.dirs = d_dirs;
+    a.I_far = d_I_far;
+    a.dim = sc->g.dim;
+    a.nl = sc->batch_end - sc->batch_begin;
+    a.np = n_probes;
+    a.n_dir = n_dir;
+    lam_offsets(sc, a.lamoff);
+    for (int c = 0; c < 3; ++c) a.inv_n[c] = 1.0f / (float)sc->g.n[c];
+    a.raw = d_raw;
+    a.target = d_target;
+    a.row0 = row0;
+    long long rows = (long long)n_dir * a.nl * n_probes;
+    hipLaunchKernelGGL(k_nrc_pack, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, (hipStream_t)stream, a);
+    NRC_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+static NrcFwd compose_args(const rt_nrc* nn, const rt_scene* sc, const float* d_dirs, int32_t n_dir, int64_t n_probes,
+                           const float* d_feat, const float* d_fstat, const float* d_I_near, const float* d_T_near,
+                           float* d_I)
+{
+    NrcFwd a;
+    std::memset(&a, 0, sizeof(a));
+    a.wb = nn->wb;
+    a.wf = nn->w;
+    a.lg2fmax = nn->lg2fmax;
+    a.mode = 1;
+    a.nl = sc->batch_end - sc->batch_begin;
+    a.rows = (long long)n_dir * a.nl * n_probes;
+    a.feat = (const float4*)d_feat;
+    a.fstat = (const float4*)d_fstat;
+    a.dirs = d_dirs;
+    a.dim = sc->g.dim;
+    a.np = n_probes;
+    lam_offsets(sc, a.lamoff);
+    for (int c = 0; c < 3; ++c) a.inv_n[c] = 1.0f / (float)sc->g.n[c];
+    a.I_near = d_I_near;
+    a.T_near = d_T_near;
+    a.I_out = d_I;
+    return a;
+}
+
+rt_status rt_nrc_compose(const rt_nrc* nn, const rt_scene* sc, const float* d_dirs, int32_t n_dir, int64_t n_probes,
+                         const float* d_feat, const float* d_fstat, const float* d_I_near, const float* d_T_near,
+                         float* d_I, void* stream)
+{
+    if (!nn || !sc || !d_dirs || !d_feat || !d_fstat || !d_I_near || !d_T_near || !d_I) return set_error(RT_E_ARG, "null argument");
+    if (sc->batch_begin < 0) return set_error(RT_E_STATE, "no batch built");
+    NrcFwd a = compose_args(nn, sc, d_dirs, n_dir, n_probes, d_feat, d_fstat, d_I_near, d_T_near, d_I);
+    NRC_HIP(launch_nrc_forward(a, nn->n_wgs * 4, (hipStream_t)stream));
+    return RT_OK;
+}
+
+rt_status rt_nrc_validate(const rt_nrc* nn, const rt_scene* sc, const float* d_dirs, int32_t n_dir, int64_t n_probes,
+                          const float* d_feat, const float* d_fstat, const float* d_I_near, const float* d_T_near,
+                          const float* d_I_far, float thresh, float* d_I_pred, uint8_t* d_fallback, float* d_err,
+                          void* stream)
+{
+    if (!nn || !sc || !d_I_far || !d_I_pred || !d_fallback) return set_error(RT_E_ARG, "null argument");
+    rt_status st = rt_nrc_compose(nn, sc, d_dirs, n_dir, n_probes, d_feat, d_fstat, d_I_near, d_T_near, d_I_pred, stream);
+    if (st != RT_OK) return st;
+    const int nl = sc->batch_end - sc->batch_begin;
+    long long rows = (long long)n_dir * nl * n_probes;
+    hipLaunchKernelGGL(k_nrc_validate, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d_I_pred,
+                       d_I_near, d_T_near, d_I_far, (const float4*)d_feat, (long long)n_dir, nl, (long long)n_probes,
+                       sc->g.B, sc->g.log2B, sc->g.nb[0], sc->g.nb[1], sc->g.nb[2], thresh, d_fallback, d_err);
+    NRC_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+}  // extern "C"

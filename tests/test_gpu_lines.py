@@ -76,6 +76,23 @@ def check_levels(lv_gpu, sc, lam_idx, rule, T):
     return lv
 
 
+def rays_avoiding(sc, blocks, vox, d):
+    """Mask of the rays (probe voxel, direction index) whose dense cells touch none of `blocks`."""
+    if len(blocks) == 0:
+        return np.ones(len(vox), bool)
+    n, B, dim = sc["n"], sc["brick"], sc["dim"]
+    nb = [n[a] // B for a in range(3)]
+    bad = set(int(b) for b in blocks)
+    ok = np.ones(len(vox), bool)
+    for i, (v, di) in enumerate(zip(vox, d)):
+        v = int(v)
+        pv = (v % n[0], (v // n[0]) % n[1], v // (n[0] * n[1]))[:dim]
+        cells, _, _ = orc.ray_cells(dim, n, pv, sc["dirs"][di])
+        b = (cells[:, 0] // B) + nb[0] * ((cells[:, 1] // B) + nb[1] * (cells[:, 2] // B))
+        ok[i] = not bad.intersection(b.tolist())
+    return ok
+
+
 def sample_rays(scene, n_dir, n, seed):
     rng = np.random.default_rng(seed)
     probes = scene.probe_voxels()
@@ -94,12 +111,16 @@ def test_velinterp_parity(rt, vscene):
     for lam0 in (0, 8):
         scene.build(lam0, lam0 + 8, iod_threshold=T)
         lv_gpu = scene.levels()
-        check_levels(lv_gpu, sc, list(range(lam0, lam0 + 8)), 0, T)
+        lv = check_levels(lv_gpu, sc, list(range(lam0, lam0 + 8)), 0, T)
+        # the oracle marches its own levels; rays through a block whose level sits in
+        # the threshold tie band (device and host logarithms differ there) are left out
+        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
+        assert ok.mean() > 0.8
         s = orc.Scene(sc, lam_idx=list(range(lam0, lam0 + 8)), n_v=21)
-        for mode, lev in (("vlm", lv_gpu), ("level0", np.where(lv_gpu >= 0, 0, -1).astype(np.int8))):
+        for mode, lev in (("vlm", lv), ("level0", np.where(lv >= 0, 0, -1).astype(np.int8))):
             I = scene.trace(dirs, mode=mode).cpu().numpy()[d, :, k]
             ref = orc.march(s, orc.VELINTERP, lev, vox, d)
-            st = orc.rel_err_stats(I, ref)
+            st = orc.rel_err_stats(I[ok], ref[ok])
             assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 1e-4, (mode, st)
         # approximation error against the dense Classic march (reported)
         ref_c = orc.march(s, orc.CLASSIC, None, vox, d)
@@ -118,12 +139,16 @@ def test_cav_parity(rt):
     for lam0 in (0, 8):
         scene.build(lam0, lam0 + 8, iod_threshold=T)
         lv_gpu = scene.levels()
-        check_levels(lv_gpu, sc, list(range(lam0, lam0 + 8)), 1, T)
+        lv = check_levels(lv_gpu, sc, list(range(lam0, lam0 + 8)), 1, T)
+        # the oracle marches its own levels; rays through a block whose level sits in
+        # the threshold tie band (device and host logarithms differ there) are left out
+        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
+        assert ok.mean() > 0.8
         s = orc.Scene(sc, lam_idx=list(range(lam0, lam0 + 8)))
-        for mode, lev in (("vlm", lv_gpu), ("level0", np.where(lv_gpu >= 0, 0, -1).astype(np.int8))):
+        for mode, lev in (("vlm", lv), ("level0", np.where(lv >= 0, 0, -1).astype(np.int8))):
             I = scene.trace(dirs, mode=mode).cpu().numpy()[d, :, k]
             ref = orc.march(s, orc.CAV, lev, vox, d)
-            st = orc.rel_err_stats(I, ref)
+            st = orc.rel_err_stats(I[ok], ref[ok])
             assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < 1e-3 and st["p100"] < 5e-3, (mode, st)
         ref_c = orc.march(s, orc.CLASSIC, None, vox, d)
         I = scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST).cpu().numpy()[d, :, k]

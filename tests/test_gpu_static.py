@@ -91,8 +91,8 @@ def test_levels_states_values_bit_exact(rt, cfg1, T, avg):
 def test_visited_cells_bit_exact(rt, cfg1):
     scene = rt.Scene.from_dict(cfg1)
     scene.build(0, 8, iod_threshold=1.0)
-    lv = scene.levels()
-    s = orc.Scene(cfg1)
+    s, lv, _, _ = oracle_batch(cfg1, 0, 8, 1.0)
+    assert np.array_equal(scene.levels(), lv)
     rng = np.random.default_rng(7)
     probes = scene.probe_voxels()
     dirs = list(cfg1["dirs"]) + [np.array(v, np.float32) for v in ([1, 0], [0, -1], [math.sqrt(.5), math.sqrt(.5)],
@@ -175,7 +175,7 @@ def test_hdda_example_grid_visits(rt):
         w = np.array([math.cos(th), math.sin(th)], np.float32)
         pv = (int(rng.integers(0, 32)), int(rng.integers(0, 32)))
         cells, tt = scene.visited(pv[0] + 32 * pv[1], w)
-        ex = adapted_cells_exact(2, (32, 32), 8, lv, pv, w)
+        ex = adapted_cells_exact(2, (32, 32), 8, expect, pv, w)
         assert len(ex) == len(cells)
         for i, (cc, L, a, b) in enumerate(ex):
             assert list(cells[i, :3]) == cc and cells[i, 3] == L
