@@ -419,7 +419,9 @@ static double pair_sum(int dim, const double* q)
  *   level m >= 1: xbar = mean of the 2^D children's xbar (pairwise order),
  *   Var = mean of (child - xbar)^2 (two-pass), IoD = |Var / xbar| (+inf if
  *   xbar = 0 < Var, 0 if Var = 0);
- *   a cell passes if chi_m 2^m ds0 < tau_thin (its optical side is thin) or
+ *   a cell passes if chi_a 2^m ds0 < tau_thin (its optical side is thin),
+ *   chi_a being the arithmetic mean of the MIP-0 chi it covers (the box
+ *   filter of Sect. 2.1, whatever the stored-value mode), or
  *   IoD(eta) <= T and IoD(chi) <= T;
  *   block level = largest m <= min(n_levels - 1, cap) with every cell of
  *   levels 1..m inside the block passing; -1 for an inactive block.
@@ -436,6 +438,7 @@ int64_t orc_levels(const orc_scene* s, const double* eta0, const double* chi0, c
     double* xc = (double*)malloc(sizeof(double) * tot);
     double* le = (double*)malloc(sizeof(double) * tot);
     double* lc = (double*)malloc(sizeof(double) * tot);
+    double* ac = (double*)malloc(sizeof(double) * tot); /* arithmetic mean of MIP-0 chi over the cell */
     uint8_t* pass = (uint8_t*)malloc(tot);
     int64_t nv = nvox_of(s), clamped = 0;
     int32_t nb[3] = {1, 1, 1};
@@ -451,6 +454,7 @@ int64_t orc_levels(const orc_scene* s, const double* eta0, const double* chi0, c
         xc[v] = log(qc > 1e-300 ? qc : 1e-300);
         le[v] = eta0[v];
         lc[v] = chi0[v];
+        ac[v] = chi0[v];
         pass[v] = 1;
     }
     /* levels 1..L-1 */
@@ -481,6 +485,8 @@ int64_t orc_levels(const orc_scene* s, const double* eta0, const double* chi0, c
                     double lin_e = pair_sum(D, q) / nch;
                     for (int k = 0; k < nch; ++k) q[k] = lc[off_c + idx[k]];
                     double lin_c = pair_sum(D, q) / nch;
+                    for (int k = 0; k < nch; ++k) q[k] = ac[off_c + idx[k]];
+                    ac[o] = pair_sum(D, q) / nch;
                     if (s->avg_mode == ORC_AVG_LOG) {
                         le[o] = exp(mean_e) / s->ds0;
                         lc[o] = exp(mean_c) / s->ds0;
@@ -490,7 +496,7 @@ int64_t orc_levels(const orc_scene* s, const double* eta0, const double* chi0, c
                     }
                     double iod_e = var_e == 0.0 ? 0.0 : (mean_e == 0.0 ? INFINITY : fabs(var_e / mean_e));
                     double iod_c = var_c == 0.0 ? 0.0 : (mean_c == 0.0 ? INFINITY : fabs(var_c / mean_c));
-                    int thin = lc[o] * (double)(1 << m) * s->ds0 < tau_thin;
+                    int thin = ac[o] * (double)(1 << m) * s->ds0 < tau_thin;
                     pass[o] = (uint8_t)(thin || (iod_e <= T && iod_c <= T));
                 }
     }
@@ -530,6 +536,7 @@ int64_t orc_levels(const orc_scene* s, const double* eta0, const double* chi0, c
     free(xc);
     free(le);
     free(lc);
+    free(ac);
     free(pass);
     return clamped;
 }

@@ -108,6 +108,21 @@ def test_thin_bypass(orc):
         assert np.all(lv == expect), (chi0, lv)
 
 
+def test_thin_bypass_uses_box_filtered_chi(orc):
+    """The thin test measures a merged cell's optical side with the box-filtered (arithmetic mean) chi of Sect. 2.1:
+    one dense voxel among thin ones keeps its block at full resolution, even though the geometric mean of chi
+    (the stored value in LOG mode) is far below the threshold."""
+    n, B, L = (2, 2), 2, 2
+    s = orc.Scene(scene(n, B, L), avg_mode=orc.AVG_LOG)
+    eta = np.array([1.0, 1e-3, 2e-3, 3e-3])  # IoD of ln eta fails
+    chi = np.array([0.2, 1e-6, 1e-6, 1e-6])  # mean 0.05 -> 0.05 x 2 = 0.1 < 0.25; geometric mean ~ 1e-5
+    assert orc.levels_one(s, eta, chi, np.ones(1, np.uint8), T=1e-2)[0] == 1
+    chi = np.array([0.6, 1e-6, 1e-6, 1e-6])  # mean 0.15 -> 0.3 >= 0.25: not thin, IoD decides -> level 0
+    assert orc.levels_one(s, eta, chi, np.ones(1, np.uint8), T=1e-2)[0] == 0
+    # the same cell with a uniform thin chi is averaged
+    assert orc.levels_one(s, eta, np.full(4, 0.1), np.ones(1, np.uint8), T=1e-2)[0] == 1
+
+
 def test_state_packing_512(orc):
     """3 bits per block, 21 blocks per 64-bit word: 512^2 with 16^2 blocks -> 49 words, 392 B."""
     g = json.load(open(os.path.join(GOLD, "block_state_packing.json")))
