@@ -41,6 +41,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "formal-solution Gsegments/s: dense vs VLM+HDDA vs NRC; p99.9 rel err vs FP64"
 HBM_PEAK = 8.0e12  # B/s
+VALU_ISSUE_PEAK = 256 * 2.4e9  # wave64 VALU instructions per second: 256 CUs x 1 per clock (4 SIMD16, non-packed)
+MARCH_SOURCES = ("march.hip", "common.h", "profile.h")
+
+
+def march_source_hash():
+    """SHA-256 over the sources the march kernels are compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in MARCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2511_08498_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_counters(name):
+    """Counter summary profiles/<name>.json if it was taken on the current march sources, else None."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        c = json.load(fh)
+    return c if c.get("march_source_sha256") == march_source_hash() else None
 
 
 def log(*a):
@@ -61,10 +83,18 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"],
+                    help="cfg2: 2D velocity interpolation (default, the headline line); cfg3: 3D Core and Voigt "
+                         "per storage dtype; cfg4: 48-scene batched vs sequential; cfg5: radiance cache on cfg3")
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=21)
     ap.add_argument("--iod", type=float, default=1e-2)
+    ap.add_argument("--avg", default="log", choices=["log", "linear"], help="stored level values: geometric or "
+                    "arithmetic mean of the children")
+    ap.add_argument("--tau-thin", type=float, default=0.25, help="thin bypass threshold on a cell's optical side")
+    ap.add_argument("--grade-scale", type=float, default=1.0, help="multiplies the cascade level distances")
+    ap.add_argument("--iod-frame", default="rest", choices=["rest", "core"],
+                    help="velocity interpolation: level test with lines at rest (the paper) or core-closest")
     ap.add_argument("--no-grading", action="store_true", help="plain VLM (no distance-graded cap)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
@@ -74,11 +104,27 @@ def main():
                     help="profiling only: trace the first N wavelength batches per step (0 = all)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="profiling only: first run a device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--pairs", type=int, default=8192, help="cfg3/cfg5: oracle sample size (probe, direction pairs)")
+    ap.add_argument("--dtypes", default="f32,bf16,f16", help="cfg3: storage dtypes to time")
+    ap.add_argument("--nrc-steps", type=int, default=3000, help="cfg5: Adam steps")
+    ap.add_argument("--nrc-train-probes", type=int, default=1024, help="cfg5: training probes per wavelength batch")
+    ap.add_argument("--nrc-held-probes", type=int, default=128, help="cfg5: held-out probes per wavelength batch")
+    ap.add_argument("--scenes", type=int, default=0, help="cfg4: first N scenes only (0 = all 48)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (--gpus %d requested); the path shards by "
               "wavelength batch with no exchange, see the design notes." % args.gpus)
         sys.exit(2)
+    if args.workload == "cfg3":
+        return bench_cfg3(args)
+    if args.workload == "cfg4":
+        return bench_cfg4(args)
+    if args.workload == "cfg5":
+        return bench_cfg5(args)
+    return bench_cfg2(args)
+
+
+def bench_cfg2(args):
 
     import numpy as np
     import torch
@@ -107,7 +153,7 @@ def main():
         del src, dst
     dirs = torch.from_numpy(sc["dirs"]).to(dev)
     n_dir = dirs.shape[0]
-    level_dist = None if args.no_grading else rt.CASCADE_LEVEL_DIST
+    level_dist = None if args.no_grading else [v * args.grade_scale for v in rt.CASCADE_LEVEL_DIST]
     scene = rt.Scene.from_dict(sc, emission=args.emission, n_v=args.n_v)
     n_probes = scene.info["n_probes"]
     I_all = torch.empty((nb_lam, n_dir, 8, n_probes), dtype=torch.float32, device=dev)
@@ -118,7 +164,8 @@ def main():
 
     def step(record=False, stats=None):
         for b in range(nb_lam):
-            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod)
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
@@ -141,15 +188,16 @@ def main():
     log("step %.1f ms; mean trace launch %.2f ms" % (ms_step, mean_trace_ms))
 
     # ---- segment counts (untimed pass with device counters)
-    stats = torch.zeros(4, dtype=torch.int64, device=dev)
+    stats = torch.zeros(5, dtype=torch.int64, device=dev)
     step(stats=stats)
     torch.cuda.synchronize()
     segs_step = int(stats[0].item())
+    lane_util = (int(stats[0].item()) + int(stats[2].item())) / max(64 * int(stats[4].item()), 1)
     seglam_step = segs_step * 8
     dense_scene = rt.Scene.from_dict(sc, emission="static", dense=True)
     probes_vox = torch.from_numpy(scene.probe_voxels()).to(dev)
     dense_scene.build(0, 8)
-    dstats = torch.zeros(4, dtype=torch.int64, device=dev)
+    dstats = torch.zeros(5, dtype=torch.int64, device=dev)
     tmp = torch.empty((n_dir, 8, n_probes), dtype=torch.float32, device=dev)
     dense_scene.trace(dirs, probes=probes_vox, mode="level0", out=tmp, stats=dstats)
     torch.cuda.synchronize()
@@ -163,8 +211,18 @@ def main():
     bps = bytes_per_seg_lam(args.emission, "f32", sc["dim"])
     seglam_launch = seglam_step / nb_lam
     achieved = bps * seglam_launch / (mean_trace_ms / 1e3)
+    # measured DRAM bytes and VALU issue per launch from the committed rocprofv3 counter summary,
+    # only while it matches the kernel sources (else null)
+    cnt = measured_counters("counters_%s_cfg2" % args.emission) if args.n_v == 21 else None
+    traffic = None
+    valu = None
+    if cnt is not None:
+        traffic = cnt["hbm_bytes_per_launch"]
+        valu = {"valu_insts_per_launch": cnt["valu_insts_per_launch"],
+                "issue_frac": cnt["valu_insts_per_launch"] / (VALU_ISSUE_PEAK * mean_trace_ms / 1e3),
+                "measured_hbm_gbs": traffic / (mean_trace_ms * 1e6)}
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None,
+                "frac": achieved / HBM_PEAK, "traffic": traffic, "valu": valu,
                 "kernel": "k_trace<2, VisVelinterp<2>>" if args.emission == "velinterp" else "k_trace",
                 "bytes_per_seg_lam": bps, "seg_lam_per_launch": seglam_launch,
                 "mean_launch_ms": mean_trace_ms}
@@ -172,13 +230,15 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "Gsegments/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "2D 1024^2, 16^2 bricks, 40%% active, 2 Gaussian lines + continuum, |v| <= 30 km/s, "
-                                  "%s (n_v=%d), 4-level VLM T=%g, thin 0.25, %s, 64 dirs, 256 lambda (32 batches of 8), "
-                                  "all %d probes" % (args.emission, args.n_v, args.iod,
-                                                     "plain VLM" if args.no_grading else "cascade-graded levels",
-                                                     n_probes),
+           "config": {"workload": (
+               "2D 1024^2, 16^2 bricks, 40%% active, 2 Gaussian lines + continuum, |v| <= 30 km/s, %s (n_v=%d), "
+               "4-level VLM T=%g, %s means, thin %g, level test %s frame, %s, 64 dirs, 256 lambda (32 batches of 8), "
+               "all %d probes" % (args.emission, args.n_v, args.iod, args.avg, args.tau_thin, args.iod_frame,
+                                  "plain VLM" if args.no_grading else "cascade-graded levels x%g" % args.grade_scale,
+                                  n_probes)),
                       "value_kind": "dense-equivalent segment-wavelength updates per second"},
            "raw_gseg_s": raw, "seg_lam_per_step": seglam_step, "dense_seg_lam_per_step": dense_seglam_step,
+           "lane_utilisation": lane_util,
            "roofline": roofline}
 
     # ---- comparators
@@ -198,14 +258,16 @@ def main():
         del dc
         torch.cuda.synchronize()
         ta = time.perf_counter()
-        sp_stats = torch.zeros(4, dtype=torch.int64, device=dev)
+        sp_stats = torch.zeros(5, dtype=torch.int64, device=dev)
         for b in range(nbc):
-            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod)
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
             scene.trace(dirs, mode="level0", out=tmp)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         for b in range(nbc):
-            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod)
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
             scene.trace(dirs, mode="level0", out=tmp, stats=sp_stats)
         torch.cuda.synchronize()
         cmp["sparse_" + args.emission] = {"gseg_s": dense_cells * 8 * nbc / (tb - ta) / 1e9,
@@ -249,6 +311,437 @@ def main():
                         **{k2: err[k2] for k2 in err if k2.startswith("p")}}
         out["cpu_baseline"]["calibration_rate_gseg_s"] = rate / 1e9
     print(json.dumps(out), flush=True)
+
+
+# ----------------------------------------------------------------------------- shared helpers
+def _env():
+    import numpy as np
+    import torch
+
+    import paper_2511_08498_amd as rt
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    return np, torch, rt, dev
+
+
+def _oracle_classic(sc, probe_vox, k, d, lam_idx, n_threads):
+    """FP64 dense Classic march (the oracle) on (probe, direction) pairs: ref [pair][lam], seg-lam, seconds."""
+    import oracle as orc
+    s = orc.Scene(sc, lam_idx=lam_idx)
+    ta = time.perf_counter()
+    ref, nseg = orc.march(s, orc.CLASSIC, None, probe_vox[k], d, n_threads=n_threads, want_nseg=True)
+    return ref, int(nseg.sum()) * len(lam_idx), time.perf_counter() - ta
+
+
+def _err(got, ref):
+    import oracle as orc
+    e = orc.rel_err_stats(got, ref)
+    return {k2: e[k2] for k2 in e if k2.startswith("p") or k2 in ("n", "n_ref_zero_mismatch")}
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+# ----------------------------------------------------------------------------- cfg3
+def bench_cfg3(args):
+    """3D 256^3 Core-and-Voigt scene, storage FP32 / BF16 / FP16: time per full solve (16 batches),
+    march-kernel roofline, error of each dtype against the FP64 dense Classic oracle."""
+    np, torch, rt, dev = _env()
+    from synth import make_cfg3
+    tg = time.time()
+    sc = make_cfg3()
+    log("cfg3 scene generated in %.1fs (%d active bricks)" % (time.time() - tg, int(sc["block_active"].sum())))
+    nb = sc["lam"].size // 8
+    if args.batches:
+        nb = min(nb, args.batches)
+    dirs = torch.from_numpy(sc["dirs"]).to(dev)
+    n_dir = dirs.shape[0]
+    level_dist = None if args.no_grading else [v * args.grade_scale for v in rt.CASCADE_LEVEL_DIST]
+    scene = rt.Scene.from_dict(sc, emission="cav")
+    n_probes = scene.info["n_probes"]
+    probe_vox = scene.probe_voxels()
+    out = torch.empty((n_dir, 8, n_probes), dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(2026)
+    k = rng.choice(n_probes, min(args.pairs, n_probes), replace=False)
+    d = rng.integers(0, n_dir, k.size).astype(np.int32)
+    kk, dd = torch.from_numpy(k).long().to(dev), torch.from_numpy(d).long().to(dev)
+    stream = torch.cuda.current_stream()
+    res = {}
+    for dt in args.dtypes.split(","):
+        got = torch.empty((k.size, nb * 8), dtype=torch.float32, device=dev)
+        evs = []
+
+        def solve(record=False, gather=False):
+            for b in range(nb):
+                scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage=dt)
+                if record:
+                    e0, e1 = _events(torch)
+                    e0.record(stream)
+                scene.trace(dirs, mode="vlm", level_dist=level_dist, out=out)
+                if record:
+                    e1.record(stream)
+                    evs.append((e0, e1))
+                if gather:
+                    got[:, 8 * b:8 * b + 8] = out[dd, :, kk]
+
+        for _ in range(args.warmup):
+            solve()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            solve(record=True)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ta) * 1e3 / max(args.steps, 1)
+        solve(gather=True)
+        torch.cuda.synchronize()
+        res[dt] = {"ms_per_solve": ms, "mean_trace_ms": float(np.mean([a.elapsed_time(b) for a, b in evs])),
+                   "got": got.cpu().numpy()}
+        log("cfg3 %s: %.1f ms per solve, trace %.2f ms" % (dt, ms, res[dt]["mean_trace_ms"]))
+    # segment counts: levels come from the FP64 chain of the MIP-0 values, not from the storage dtype
+    stats = torch.zeros(5, dtype=torch.int64, device=dev)
+    for b in range(nb):
+        scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin)
+        scene.trace(dirs, mode="vlm", level_dist=level_dist, out=out, stats=stats)
+    torch.cuda.synchronize()
+    seglam = int(stats[0].item()) * 8
+    # dense comparator: Core and Voigt at MIP 0 on the full grid (every brick stored), one batch
+    dense = rt.Scene.from_dict(sc, emission="cav", dense=True)
+    pv = torch.from_numpy(probe_vox).to(dev)
+    dstats = torch.zeros(5, dtype=torch.int64, device=dev)
+    dense.build(0, 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin)
+    dense.trace(dirs, probes=pv, mode="level0", out=out)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    dense.build(0, 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin)
+    dense.trace(dirs, probes=pv, mode="level0", out=out, stats=dstats)
+    torch.cuda.synchronize()
+    dense_ms_batch = (time.perf_counter() - ta) * 1e3
+    dense_cells = int(dstats[0].item())
+    del dense
+    torch.cuda.empty_cache()
+    nthreads = min(os.cpu_count() or 1, 16)
+    ref, cpu_seglam, cpu_s = _oracle_classic(sc, probe_vox, k, d, list(range(nb * 8)), nthreads)
+    log("cfg3 oracle: %d pairs x %d lambda in %.1fs" % (k.size, nb * 8, cpu_s))
+    dense_seglam = dense_cells * 8 * nb
+    out_line = {"workload": "cfg3", "config": {
+        "workload": "3D 256^3, 8^3 bricks, %d active (25%%), slab + %d loops, 2 Voigt lines (Core and Voigt) + "
+                    "grey continuum, |v| <= 30 km/s, 4-level VLM T=%g, %s, 32 Fibonacci directions, %d lambda "
+                    "(%d batches of 8), all %d probes" % (
+                        int(sc["block_active"].sum()), int(sc["n_loops"]), args.iod,
+                        "plain VLM" if args.no_grading else "cascade-graded levels", nb * 8, nb, n_probes)},
+        "seg_lam_per_solve": seglam, "dense_seg_lam_per_solve": dense_seglam,
+        "dense_classic_gpu": {"ms_per_batch": dense_ms_batch, "ms_per_solve_extrapolated": dense_ms_batch * nb},
+        "cpu_baseline": {"value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
+                         "kind": "oracle", "sample": "%d seeded (probe, direction) pairs x %d wavelengths, FP64 "
+                                                     "dense Classic (exact Voigt), %.1f s" % (k.size, nb * 8, cpu_s)},
+        "dtypes": {}}
+    for dt, r in res.items():
+        bps = bytes_per_seg_lam("cav", dt, 3)
+        out_line["dtypes"][dt] = {
+            "ms_per_solve": r["ms_per_solve"], "mean_trace_ms": r["mean_trace_ms"],
+            "raw_gseg_s": seglam / (r["ms_per_solve"] / 1e3) / 1e9,
+            "dense_equiv_gseg_s": dense_seglam / (r["ms_per_solve"] / 1e3) / 1e9,
+            "speedup_vs_dense_classic": dense_ms_batch * nb / r["ms_per_solve"],
+            "trace_bytes_per_seg_lam": bps,
+            "trace_hbm_frac_streamed": bps * seglam / nb / (r["mean_trace_ms"] / 1e3) / HBM_PEAK,
+            "error_vs_fp64_classic": _err(r["got"], ref)}
+    if "f32" in res:
+        for dt in res:
+            if dt != "f32":
+                out_line["dtypes"][dt]["speedup_vs_f32"] = res["f32"]["ms_per_solve"] / res[dt]["ms_per_solve"]
+                out_line["dtypes"][dt]["error_vs_gpu_f32"] = _err(res[dt]["got"], res["f32"]["got"].astype(np.float64))
+    print(json.dumps(out_line), flush=True)
+
+
+# ----------------------------------------------------------------------------- cfg4
+def bench_cfg4(args):
+    """48 uneven scenes (2D 64^2-1024^2, 3D 64^3-192^3, 2-5 levels, 16-64 directions, 64-256
+    wavelengths), BF16 storage: sequential per-scene launches vs one persistent batched launch per
+    wavelength-batch wave (eager and graph-replayed), with the autotuned launch shape."""
+    np, torch, rt, dev = _env()
+    from synth import cfg4_specs, make_cfg4_scene
+    specs = cfg4_specs()
+    if args.scenes:
+        specs = specs[:args.scenes]
+    level_dist = None if args.no_grading else [v * args.grade_scale for v in rt.CASCADE_LEVEL_DIST]
+    items = []
+    tg = time.time()
+    for i, sp in enumerate(specs):
+        sc = make_cfg4_scene(sp)
+        s = rt.Scene.from_dict(sc, emission="static")
+        dirs = torch.from_numpy(sc["dirs"]).to(dev)
+        out = torch.empty((dirs.shape[0], 8, s.info["n_probes"]), dtype=torch.float32, device=dev)
+        items.append({"spec": sp, "scene": s, "dirs": dirs, "out": out, "nb": sp["n_lam"] // 8})
+        del sc
+        if i % 8 == 7:
+            log("cfg4: %d scenes resident (%.0fs)" % (i + 1, time.time() - tg))
+    waves = max(it["nb"] for it in items)
+    if args.batches:
+        waves = min(waves, args.batches)
+
+    def build_wave(b, stream=None):
+        for it in items:
+            if it["nb"] > b:
+                it["scene"].build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                                   storage="bf16", stream=stream)
+
+    def sequential(stats=None):
+        for b in range(waves):
+            build_wave(b)
+            for it in items:
+                if it["nb"] > b:
+                    it["scene"].trace(it["dirs"], mode="vlm", level_dist=level_dist, out=it["out"], stats=stats)
+
+    def jobs(part):
+        return [{"scene": items[i]["scene"], "dirs": items[i]["dirs"], "out": items[i]["out"],
+                 "level_dist": level_dist} for i in part]
+
+    parts = sorted({tuple(i for i, it in enumerate(items) if it["nb"] > b) for b in range(waves)}, key=len,
+                   reverse=True)
+    build_wave(0)
+    best, tune_ms = rt.batch_autotune(jobs(parts[0]), reps=2)
+    log("cfg4 autotune: %s (%.2f ms)" % (best, tune_ms))
+    batches = {p: rt.Batch(jobs(p), **best) for p in parts}
+    stream = torch.cuda.current_stream()
+
+    def part_of(b):
+        return tuple(i for i, it in enumerate(items) if it["nb"] > b)
+
+    run_ev = []
+
+    def batched(record=False, st=None):
+        for b in range(waves):
+            build_wave(b, stream=st)
+            if record:
+                e0, e1 = _events(torch)
+                e0.record(stream)
+            batches[part_of(b)].run(st)
+            if record:
+                e1.record(stream)
+                run_ev.append((e0, e1))
+
+    # correctness: wave 0 batched == sequential, bit for bit
+    build_wave(0)
+    for it in items:
+        it["scene"].trace(it["dirs"], mode="vlm", level_dist=level_dist, out=it["out"])
+    ref0 = [it["out"].clone() for it in items]
+    for it in items:
+        it["out"].fill_(-1.0)
+    batches[part_of(0)].run()
+    torch.cuda.synchronize()
+    identical = all(torch.equal(r, it["out"]) for r, it in zip(ref0, items))
+    del ref0
+    # timing
+    sequential()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        sequential()
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - ta) * 1e3 / args.steps
+    batched()
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for _ in range(args.steps):
+        batched(record=True)
+    torch.cuda.synchronize()
+    ms_bat = (time.perf_counter() - ta) * 1e3 / args.steps
+    run_ms = [a.elapsed_time(b) for a, b in run_ev]
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        with rt.Graph(side) as g:
+            batched(st=side)
+        g.replay()
+        side.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            g.replay()
+        side.synchronize()
+        ms_graph = (time.perf_counter() - ta) * 1e3 / args.steps
+    torch.cuda.synchronize()
+    stats = torch.zeros(5, dtype=torch.int64, device=dev)
+    sequential(stats=stats)
+    torch.cuda.synchronize()
+    seglam = int(stats[0].item()) * 8
+    n2 = sum(1 for it in items if it["spec"]["dim"] == 2)
+    out_line = {"workload": "cfg4", "config": {
+        "workload": "%d scenes (%d 2D 64^2-1024^2 with 16^2 bricks, %d 3D 64^3-192^3 with 8^3 bricks), 2-5 level "
+                    "VLM T=%g, %s, static Gaussian line + continuum, 16-64 directions, 64-256 wavelengths, BF16 "
+                    "storage, all probes" % (len(items), n2, len(items) - n2, args.iod,
+                                             "plain VLM" if args.no_grading else "cascade-graded levels")},
+        "waves": waves, "seg_lam_per_solve": seglam, "batched_equals_sequential": identical,
+        "autotuned": best, "autotune_ms": tune_ms,
+        "sequential": {"ms_per_solve": ms_seq, "raw_gseg_s": seglam / ms_seq / 1e6},
+        "batched_eager": {"ms_per_solve": ms_bat, "raw_gseg_s": seglam / ms_bat / 1e6,
+                          "mean_persistent_launch_ms": float(np.mean(run_ms)),
+                          "sum_persistent_launch_ms": float(np.sum(run_ms)) / args.steps},
+        "batched_graph": {"ms_per_solve": ms_graph, "raw_gseg_s": seglam / ms_graph / 1e6},
+        "speedup_batched_vs_sequential": ms_seq / ms_bat, "speedup_graph_vs_sequential": ms_seq / ms_graph}
+    print(json.dumps(out_line), flush=True)
+
+
+# ----------------------------------------------------------------------------- cfg5
+def bench_cfg5(args):
+    """Radiance cache on the cfg3 scene (BF16 storage): generation of training rows from truncated
+    full marches, Adam training, held-out check and fallback map, then the timed truncated march +
+    cache against the plain FP32 and BF16 marches; errors against the FP64 oracle (gain test: the
+    same truncation without the cache)."""
+    np, torch, rt, dev = _env()
+    from synth import make_cfg3
+    T_TRUNC, THRESH = 32.0, 5e-3
+    tg = time.time()
+    sc = make_cfg3()
+    log("cfg5 scene generated in %.1fs" % (time.time() - tg))
+    nb = sc["lam"].size // 8
+    if args.batches:
+        nb = min(nb, args.batches)
+    dirs = torch.from_numpy(sc["dirs"]).to(dev)
+    n_dir = dirs.shape[0]
+    level_dist = None if args.no_grading else [v * args.grade_scale for v in rt.CASCADE_LEVEL_DIST]
+    scene = rt.Scene.from_dict(sc, emission="cav")
+    n_probes = scene.info["n_probes"]
+    probe_vox = scene.probe_voxels()
+    rng = np.random.default_rng(5)
+    ptr, phd = args.nrc_train_probes, args.nrc_held_probes
+    sel = [rng.choice(n_probes, ptr + phd, replace=False) for _ in range(nb)]
+    tr_probes = [torch.from_numpy(probe_vox[s_[:ptr]]).to(dev) for s_ in sel]
+    hd_probes = [torch.from_numpy(probe_vox[s_[ptr:]]).to(dev) for s_ in sel]
+    rows_b = n_dir * 8 * ptr
+    raw = torch.zeros((nb * rows_b, 12), dtype=torch.float32, device=dev)
+    tgt = torch.zeros(nb * rows_b, dtype=torch.float32, device=dev)
+    nn = rt.Nrc(max_batch=2 ** 14, freq_max=sc["n"][0] / 2.0, seed=5)
+    torch.cuda.synchronize()
+    ta = time.perf_counter()
+    for b in range(nb):
+        scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage="bf16")
+        tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=tr_probes[b], level_dist=level_dist)
+        nn.pack(scene, tr, raw, tgt, b * rows_b)
+    torch.cuda.synchronize()
+    gen_s = time.perf_counter() - ta
+    q_frac_train = float(raw[:, 11].mean().item())
+    log("cfg5 generation: %d rows in %.2fs (query fraction %.3f)" % (raw.shape[0], gen_s, q_frac_train))
+    ta = time.perf_counter()
+    nn.train(raw, tgt, steps=1, batch=2 ** 14, lr=1e-3)
+    loss0 = nn.loss()
+    done = 1
+    while done < args.nrc_steps:
+        n = min(500, args.nrc_steps - done)
+        nn.train(raw, tgt, steps=n, batch=2 ** 14, lr=1e-3)
+        done += n
+        log("cfg5 training: %d steps, loss %.3e" % (done, nn.loss()))
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - ta
+    loss1 = nn.loss()
+    # held-out check -> fallback map
+    fb = torch.zeros(scene.info["n_blocks"], dtype=torch.uint8, device=dev)
+    held_err = []
+    for b in range(nb):
+        scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage="bf16")
+        tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=hd_probes[b], level_dist=level_dist)
+        _, err = nn.validate(scene, tr, THRESH, fb)
+        q = (tr["feat"][..., 3] > 0)[:, None, :].expand_as(err)
+        held_err.append(err[q].cpu().numpy())
+    torch.cuda.synchronize()
+    held_err = np.concatenate(held_err) if held_err else np.zeros(1)
+    n_flag = int(fb.sum().item())
+    log("cfg5 held-out: median %.3e p99.9 %.3e; %d blocks flagged" % (
+        np.median(held_err), np.percentile(held_err, 99.9, method="higher"), n_flag))
+    # timed solves on all probes
+    kk_np = rng.choice(n_probes, min(args.pairs, n_probes), replace=False)
+    d_np = rng.integers(0, n_dir, kk_np.size).astype(np.int32)
+    kk, dd = torch.from_numpy(kk_np).long().to(dev), torch.from_numpy(d_np).long().to(dev)
+    out = torch.empty((n_dir, 8, n_probes), dtype=torch.float32, device=dev)
+    outc = torch.empty_like(out)
+    stream = torch.cuda.current_stream()
+
+    def plain(dt, gather=None):
+        for b in range(nb):
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage=dt)
+            scene.trace(dirs, mode="vlm", level_dist=level_dist, out=out)
+            if gather is not None:
+                gather[:, 8 * b:8 * b + 8] = out[dd, :, kk]
+
+    nrc_ev = []
+
+    def cached(gather=None, gather_cut=None, fallback=fb, record=False):
+        qsum = 0
+        for b in range(nb):
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage="bf16")
+            if record:
+                e0, e1 = _events(torch)
+                e0.record(stream)
+            tr = scene.trace_truncated(dirs, T_TRUNC, gen=False, fallback=fallback, level_dist=level_dist)
+            if record:
+                e1.record(stream)
+            nn.compose(scene, tr, out=outc)
+            if record:
+                e2 = torch.cuda.Event(enable_timing=True)
+                e2.record(stream)
+                nrc_ev.append((e0, e1, e2))
+            if gather is not None:
+                gather[:, 8 * b:8 * b + 8] = outc[dd, :, kk]
+                gather_cut[:, 8 * b:8 * b + 8] = tr["I_near"][dd, :, kk]
+                qsum += int((tr["feat"][..., 3] > 0).sum().item())
+            del tr
+        return qsum
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    ms_f32 = timed(lambda: plain("f32"))
+    ms_bf16 = timed(lambda: plain("bf16"))
+    ms_nrc = timed(lambda: cached(record=True))
+    tr_ms = float(np.mean([a.elapsed_time(b) for a, b, _ in nrc_ev]))
+    comp_ms = float(np.mean([b.elapsed_time(c) for _, b, c in nrc_ev]))
+    log("cfg5 solve ms: plain f32 %.1f, plain bf16 %.1f, cache %.1f (trace %.2f + compose %.2f per batch)" % (
+        ms_f32, ms_bf16, ms_nrc, tr_ms, comp_ms))
+    g_f32 = torch.empty((kk.numel(), nb * 8), device=dev)
+    g_bf16, g_nrc, g_cut, g_nrc0, g_cut0 = (torch.empty_like(g_f32) for _ in range(5))
+    plain("f32", g_f32)
+    plain("bf16", g_bf16)
+    queries = cached(g_nrc, g_cut)
+    queries0 = cached(g_nrc0, g_cut0, fallback=None)
+    torch.cuda.synchronize()
+    nthreads = min(os.cpu_count() or 1, 16)
+    ref, cpu_seglam, cpu_s = _oracle_classic(sc, probe_vox, kk_np, d_np, list(range(nb * 8)), nthreads)
+    f32_np = g_f32.cpu().numpy().astype(np.float64)
+    rays = n_dir * n_probes
+    out_line = {"workload": "cfg5", "config": {
+        "workload": "radiance cache on the 3D 256^3 Core-and-Voigt scene (%d active bricks), BF16 storage, "
+                    "truncation at path %g, %d lambda, 32 directions, all %d probes; %d training rows, %d held-out "
+                    "probes per batch; MLP 256-4x64 SiLU-1 BF16 MFMA, Adam lr 1e-3 batch 16384, %d steps" % (
+                        int(sc["block_active"].sum()), T_TRUNC, nb * 8, n_probes, raw.shape[0], phd, args.nrc_steps)},
+        "timing_ms_per_solve": {"plain_f32": ms_f32, "plain_bf16": ms_bf16, "cache": ms_nrc,
+                                "cache_trace_per_batch": tr_ms, "cache_compose_per_batch": comp_ms},
+        "speedup_cache_vs_plain_f32": ms_f32 / ms_nrc, "speedup_cache_vs_plain_bf16": ms_bf16 / ms_nrc,
+        "speedup_bf16_vs_f32": ms_f32 / ms_bf16,
+        "generation_s": gen_s, "training_s": train_s, "loss_first": loss0, "loss_last": loss1,
+        "held_out_rel_err": {"n": int(held_err.size), "p50": float(np.median(held_err)),
+                             "p99": float(np.percentile(held_err, 99, method="higher")),
+                             "p99.9": float(np.percentile(held_err, 99.9, method="higher"))},
+        "fallback_blocks": n_flag, "fallback_block_frac": n_flag / int(sc["block_active"].sum()),
+        "query_ray_frac": queries / (rays * nb), "query_ray_frac_without_fallback": queries0 / (rays * nb),
+        "error_vs_fp64_classic": {"plain_f32": _err(f32_np, ref), "plain_bf16": _err(g_bf16.cpu().numpy(), ref),
+                                  "cache": _err(g_nrc.cpu().numpy(), ref),
+                                  "truncated_no_cache": _err(g_cut.cpu().numpy(), ref),
+                                  "cache_without_fallback": _err(g_nrc0.cpu().numpy(), ref),
+                                  "truncated_no_cache_no_fallback": _err(g_cut0.cpu().numpy(), ref)},
+        "error_vs_gpu_plain_f32": {"plain_bf16": _err(g_bf16.cpu().numpy(), f32_np),
+                                   "cache": _err(g_nrc.cpu().numpy(), f32_np),
+                                   "truncated_no_cache": _err(g_cut.cpu().numpy(), f32_np)},
+        "cpu_baseline": {"value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
+                         "kind": "oracle", "sample": "%d pairs x %d wavelengths, FP64 dense Classic, %.1f s" % (
+                             kk_np.size, nb * 8, cpu_s)}}
+    print(json.dumps(out_line), flush=True)
 
 
 if __name__ == "__main__":

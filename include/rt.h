@@ -150,18 +150,30 @@ typedef struct rt_scene_inputs {
  * Build parameters of one wavelength batch (Sect. 2.2, 4.1).
  *   iod_threshold  T: a level-m cell passes if IoD[ln(eta ds0)] <= T and
  *                  IoD[ln(chi ds0)] <= T, IoD = |Var/Mean| over its 2^D children.
- *   tau_thin       a cell also passes if chi_m 2^m ds0 < tau_thin.
+ *   tau_thin       a cell also passes if chi_a 2^m ds0 < tau_thin, chi_a being the
+ *                  arithmetic (box-filter, Sect. 2.1) mean of the MIP-0 chi it covers.
  *   max_level      cap on the selected level (-1: none).
  *   avg_mode       rt_avg for the stored level values (the IoD always uses ln values).
- *   storage        rt_dtype of the stored values (BF16/F16 round to nearest even).
+ *   storage        rt_dtype of the stored values (BF16/F16 round to nearest even):
+ *                  static emission values, Core-and-Voigt line parameters;
+ *                  velocity-interpolation nodes are FP32 only (RT_E_UNSUPPORTED).
+ *   iod_frame      line model with velocity interpolation: the frame in which the
+ *                  MIP-0 eta, chi of the level test are evaluated.  RT_IOD_REST (0):
+ *                  every line at rest (Sect. 3.1); RT_IOD_CORE (1): each voxel's line
+ *                  at the projected velocity within [-|v|, |v|] closest to putting the
+ *                  batch wavelength in its core (the Core-and-Voigt frame of Sect. 3.2,
+ *                  which sees velocity gradients in line cores).  Core and Voigt always
+ *                  uses RT_IOD_CORE; static emission ignores it.
  */
+typedef enum rt_iod_frame { RT_IOD_REST = 0, RT_IOD_CORE = 1 } rt_iod_frame;
+
 typedef struct rt_build_params {
     double iod_threshold;
     double tau_thin;
     int32_t max_level;
     int32_t avg_mode;
     int32_t storage;
-    int32_t reserved_;
+    int32_t iod_frame;
 } rt_build_params;
 
 /*
@@ -171,9 +183,11 @@ typedef struct rt_build_params {
  *   I0         boundary intensity entering at the upwind end of every ray.
  *   step_cap   maximum traversal steps per ray (0: sum of the grid sides x 2 + 16).
  *              A ray that reaches it stops and is recorded as a device error.
- *   d_stats    optional device uint64 [4], accumulated (not cleared):
+ *   d_stats    optional device uint64 [5], accumulated (not cleared):
  *              [0] segments applied (non-empty cells), [1] rays,
- *              [2] empty-block steps, [3] level changes.
+ *              [2] empty-block steps, [3] level changes, [4] the sum over
+ *              wavefronts of their longest ray in steps ([0] + [2]), so that
+ *              ([0] + [2]) / (64 [4]) is the SIMD lane utilisation.
  *   level_dist distance-graded level cap (VLM mode): level m >= 1 is used only
  *              in blocks the ray enters at path length t >= level_dist[m]
  *              (index units; the probe's own block is entered at t = 0).
@@ -221,6 +235,15 @@ typedef struct rt_scene rt_scene;
  * by rt_scene_destroy.  Errors: RT_E_ARG (shape/enum/pointer), RT_E_HIP.
  */
 rt_status rt_scene_create(const rt_scene_desc* desc, const rt_scene_inputs* inputs, void* stream, rt_scene** out);
+
+/*
+ * rt_scene_workspace_bytes -- device bytes rt_scene_create allocates for this
+ * descriptor when n_active blocks are active (n_active = the block count gives
+ * the upper bound; after creation rt_scene_info.storage_bytes is the same
+ * figure).  Host only: no device work, inputs not needed.  Errors: RT_E_ARG,
+ * RT_E_UNSUPPORTED as for rt_scene_create.
+ */
+rt_status rt_scene_workspace_bytes(const rt_scene_desc* desc, int64_t n_active, size_t* h_bytes);
 
 /*
  * rt_scene_build -- for wavelengths [lam_begin, lam_end) (at most
@@ -374,7 +397,10 @@ void rt_graph_destroy(rt_graph* graph);
  *   d_I_far  [n_dir][nl][n_probes]  gen != 0 only: exact far-field intensity
  *                                   arriving at the truncation point (incl. I0)
  *   d_feat   [n_dir][n_probes][4]   truncation point x, y, z (index space; z = 0.5
- *                                   in 2D) and 1 if the ray needs a query
+ *                                   in 2D) and q: 0 if the ray needs no query,
+ *                                   else 1 + the index of the block whose cell
+ *                                   holds the truncation point (the block the
+ *                                   fallback map is indexed by)
  *   d_fstat  [n_dir][nl][n_probes][4] level statistics of the cell there: mean
  *                                   and variance of ln(chi ds0), of ln(eta ds0)
  * The complete intensity is I = I_near + T_near I_far.  The truncation point
@@ -382,7 +408,8 @@ void rt_graph_destroy(rt_graph* graph);
  * in empty space (the far field is the same).  Rays that leave the grid
  * before it need no query.  In inference mode (gen = 0) a ray whose
  * truncation block is flagged in d_fallback (uint8 [n_blocks], nullable)
- * keeps marching to the boundary and needs no query.  Asynchronous.
+ * keeps marching to the boundary and needs no query.  Grids of 2^24 blocks or
+ * more are rejected (q must stay exact in FP32).  Asynchronous.
  */
 rt_status rt_trace_truncated(const rt_scene* scene, const rt_trace_params* params, float t_trunc, int32_t gen,
                              const uint8_t* d_fallback, const float* d_dirs, int32_t n_dir, const int32_t* d_probes,
@@ -411,6 +438,8 @@ typedef struct rt_nrc_desc {
 
 typedef struct rt_nrc rt_nrc;
 
+/* Device bytes rt_nrc_create allocates for this descriptor (host only, no device work). */
+rt_status rt_nrc_workspace_bytes(const rt_nrc_desc* desc, size_t* h_bytes);
 rt_status rt_nrc_num_params(int32_t* h_n);
 rt_status rt_nrc_create(const rt_nrc_desc* desc, void* stream, rt_nrc** out);
 void rt_nrc_destroy(rt_nrc* nrc);

@@ -34,7 +34,7 @@ EXPORTS = (
     "rt_batch_destroy", "rt_batch_autotune", "rt_graph_begin", "rt_graph_end", "rt_graph_launch",
     "rt_graph_destroy", "rt_trace_truncated", "rt_nrc_num_params", "rt_nrc_create", "rt_nrc_destroy",
     "rt_nrc_get_weights", "rt_nrc_set_weights", "rt_nrc_pack", "rt_nrc_train", "rt_nrc_loss", "rt_nrc_gradients",
-    "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate",
+    "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate", "rt_scene_workspace_bytes", "rt_nrc_workspace_bytes",
 )
 _VOID = ("rt_scene_destroy", "rt_last_error", "rt_version", "rt_batch_destroy", "rt_graph_destroy", "rt_nrc_destroy")
 
@@ -56,7 +56,7 @@ class RtSceneInputs(ctypes.Structure):
 
 class RtBuildParams(ctypes.Structure):
     _fields_ = [("iod_threshold", ctypes.c_double), ("tau_thin", ctypes.c_double), ("max_level", ctypes.c_int32),
-                ("avg_mode", ctypes.c_int32), ("storage", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
+                ("avg_mode", ctypes.c_int32), ("storage", ctypes.c_int32), ("iod_frame", ctypes.c_int32)]
 
 
 class RtTraceParams(ctypes.Structure):
@@ -139,6 +139,8 @@ def lib():
     L.rt_graph_destroy.argtypes = [_P]
     L.rt_graph_destroy.restype = None
     L.rt_trace_truncated.argtypes = [_P, _P, ctypes.c_float, i32, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P, _P]
+    L.rt_scene_workspace_bytes.argtypes = [_P, i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.rt_nrc_workspace_bytes.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
     L.rt_nrc_num_params.argtypes = [_P]
     L.rt_nrc_create.argtypes = [_P, _P, ctypes.POINTER(_P)]
     L.rt_nrc_destroy.argtypes = [_P]
@@ -176,6 +178,46 @@ def _stream(stream=None):
     return _P(s.cuda_stream)
 
 
+def _scene_desc(dim, n, brick, n_levels, model, emission, profile, n_v, dense, ds0, n_lam_static, lam, lam0):
+    """rt_scene_desc of a scene (plus the wavelength arrays it points to, which must stay alive)."""
+    n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
+    d = RtSceneDesc()
+    d.dim = int(dim)
+    for a in range(3):
+        d.n[a] = n[a]
+    d.brick = int(brick)
+    d.n_levels = int(n_levels)
+    d.model = MODEL[model]
+    d.emission = EMISSION[emission]
+    d.profile = PROFILE[profile]
+    d.n_v = int(n_v)
+    d.dense = 1 if dense else 0
+    d.ds0 = float(ds0)
+    if model == "static":
+        d.n_lam = int(n_lam_static)
+        return d, None, None
+    lam = np.ascontiguousarray(lam, np.float64)
+    lam0 = np.ascontiguousarray(lam0, np.float64)
+    d.n_lam, d.n_lines = lam.size, lam0.size
+    d.h_lam, d.h_lam0 = _np_ptr(lam), _np_ptr(lam0)
+    return d, lam, lam0
+
+
+def scene_workspace_bytes(sc, n_active=None, emission=None, n_v=21, dense=False):
+    """Device bytes a scene made from the synthetic scene dict `sc` holds (host only; n_active
+    defaults to the dict's active-block count, or every block when dense)."""
+    model = sc["model"]
+    emis = "static" if model == "static" else (emission or "static")
+    d, lam, lam0 = _scene_desc(sc["dim"], sc["n"], sc["brick"], sc["n_levels"], model, emis,
+                               sc.get("profile", "gauss"), n_v, dense, sc.get("ds0", 1.0),
+                               sc["eta"].shape[0] if model == "static" else None, sc.get("lam"), sc.get("lam0"))
+    if n_active is None:
+        n_active = sc["block_active"].size if dense else int(sc["block_active"].sum())
+    v = ctypes.c_size_t(0)
+    _check(lib().rt_scene_workspace_bytes(ctypes.byref(d), int(n_active), ctypes.byref(v)))
+    return v.value
+
+
 class Scene:
     """A scene resident on the GPU: inputs (device tensors) + the library's handle.
 
@@ -205,31 +247,14 @@ class Scene:
             t = t.to(device=self.device, dtype=dt).contiguous()
             return t
 
-        d = RtSceneDesc()
-        d.dim = self.dim
-        for a in range(3):
-            d.n[a] = self.n[a]
-        d.brick = self.brick
-        d.n_levels = int(n_levels)
-        d.model = MODEL[model]
-        d.emission = EMISSION[emission]
-        d.profile = PROFILE[profile]
-        d.n_v = int(n_v)
-        d.dense = 1 if dense else 0
-        d.ds0 = float(ds0)
+        d, self.lam, self.lam0 = _scene_desc(self.dim, self.n, self.brick, n_levels, model, emission, profile, n_v,
+                                             dense, ds0, None if eta is None else eta.shape[0], lam, lam0)
         inp = RtSceneInputs()
         if model == "static":
             te, tc = dev(eta), dev(chi)
             self._keep.update(eta=te, chi=tc)
-            d.n_lam = int(te.shape[0])
             inp.d_eta, inp.d_chi = te.data_ptr(), tc.data_ptr()
-            self.lam = None
         else:
-            self.lam = np.ascontiguousarray(lam, np.float64)
-            self.lam0 = np.ascontiguousarray(lam0, np.float64)
-            d.n_lam = self.lam.size
-            d.n_lines = self.lam0.size
-            d.h_lam, d.h_lam0 = _np_ptr(self.lam), _np_ptr(self.lam0)
             for k, v in (("eta_star", eta_star), ("chi_star", chi_star), ("damp", damp), ("inv_dld", inv_dld),
                          ("eta_bg", eta_bg), ("chi_bg", chi_bg), ("vel", vel)):
                 t = dev(v)
@@ -273,8 +298,9 @@ class Scene:
         return {k: getattr(inf, k) for k, _ in RtSceneInfo._fields_ if k != "reserved_"}
 
     def build(self, lam_begin, lam_end, iod_threshold=1e-2, tau_thin=0.25, max_level=-1, avg_mode="log",
-              storage="f32", stream=None):
+              storage="f32", iod_frame="rest", stream=None):
         p = RtBuildParams()
+        p.iod_frame = {"rest": 0, "core": 1}[iod_frame]
         p.iod_threshold = float(iod_threshold)
         p.tau_thin = float(tau_thin)
         p.max_level = int(max_level)
@@ -600,3 +626,12 @@ class Nrc:
                                      float(thresh), pred.data_ptr(), fallback.data_ptr(), err.data_ptr(),
                                      _stream(stream)))
         return pred, err
+
+
+def nrc_workspace_bytes(max_batch=65536, freq_max=64.0, seed=0):
+    """Device bytes a cache with this maximum batch holds (host only)."""
+    d = RtNrcDesc()
+    d.max_batch, d.freq_max, d.seed = int(max_batch), float(freq_max), int(seed)
+    v = ctypes.c_size_t(0)
+    _check(lib().rt_nrc_workspace_bytes(ctypes.byref(d), ctypes.byref(v)))
+    return v.value

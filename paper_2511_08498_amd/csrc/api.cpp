@@ -68,12 +68,11 @@ const char* rt_last_error(void) { return g_err.c_str(); }
 
 const char* rt_version(void) { return "rt 0.1 (gfx950)"; }
 
-rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, void* stream, rt_scene** out)
+}  // extern "C"
+
+// Descriptor checks shared by rt_scene_create and rt_scene_workspace_bytes (inp may be null: no input checks).
+static rt_status check_desc(const rt_scene_desc* d, const rt_scene_inputs* inp)
 {
-    g_err.clear();
-    if (!d || !inp || !out) return fail(RT_E_ARG, "null argument");
-    *out = nullptr;
-    hipStream_t s = (hipStream_t)stream;
     if (d->dim != 2 && d->dim != 3) return fail(RT_E_ARG, "dim must be 2 or 3 (got %d)", d->dim);
     if (d->brick != 8 && d->brick != 16) return fail(RT_E_ARG, "brick must be 8 or 16 (got %d)", d->brick);
     const int log2B = ilog2(d->brick);
@@ -93,15 +92,15 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     if (d->n_lam < 1) return fail(RT_E_ARG, "n_lam must be >= 1");
     if (d->model == RT_MODEL_STATIC) {
         if (d->emission != RT_EMIS_STATIC) return fail(RT_E_ARG, "static model supports only RT_EMIS_STATIC");
-        if (!inp->d_eta || !inp->d_chi) return fail(RT_E_ARG, "static model needs d_eta and d_chi");
+        if (inp && (!inp->d_eta || !inp->d_chi)) return fail(RT_E_ARG, "static model needs d_eta and d_chi");
     } else if (d->model == RT_MODEL_LINES) {
         if (d->n_lines < 1 || d->n_lines > RT_MAX_LINES) return fail(RT_E_ARG, "n_lines must be in [1, %d]", RT_MAX_LINES);
         if (d->profile != RT_PROFILE_GAUSS && d->profile != RT_PROFILE_VOIGT) return fail(RT_E_ARG, "bad profile");
         if (d->emission < RT_EMIS_STATIC || d->emission > RT_EMIS_CAV) return fail(RT_E_ARG, "bad emission");
         if (d->emission == RT_EMIS_VELINTERP && d->n_v < 2) return fail(RT_E_ARG, "n_v must be >= 2");
         if (!d->h_lam || !d->h_lam0) return fail(RT_E_ARG, "lines model needs h_lam and h_lam0");
-        if (!inp->d_eta_star || !inp->d_chi_star || !inp->d_damp || !inp->d_inv_dld || !inp->d_eta_bg ||
-            !inp->d_chi_bg || !inp->d_vel)
+        if (inp && (!inp->d_eta_star || !inp->d_chi_star || !inp->d_damp || !inp->d_inv_dld || !inp->d_eta_bg ||
+                    !inp->d_chi_bg || !inp->d_vel))
             return fail(RT_E_ARG, "lines model needs every line input");
         for (int l = 0; l < d->n_lam; ++l)
             if (!(d->h_lam[l] > 0.0)) return fail(RT_E_ARG, "wavelengths must be positive");
@@ -110,11 +109,12 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     } else {
         return fail(RT_E_ARG, "bad model %d", d->model);
     }
+    return RT_OK;
+}
 
-    rt_scene* sc = new (std::nothrow) rt_scene();
-    if (!sc) return fail(RT_E_ARG, "out of host memory");
-    sc->desc = *d;
-    Geo& g = sc->g;
+static void make_geo(const rt_scene_desc* d, Geo& g)
+{
+    const int log2B = ilog2(d->brick);
     std::memset(&g, 0, sizeof(g));
     g.dim = d->dim;
     g.B = d->brick;
@@ -135,6 +135,56 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     g.cells = off;
     g.n_state_words = (int)((g.nblocks + kStatesPerWord - 1) / kStatesPerWord);
     g.feat_level = std::min(2, d->n_levels - 1);
+}
+
+// Bytes of one allocation as rt_scene::alloc makes it.
+static size_t alloc_bytes(size_t count, size_t elem) { return std::max<size_t>(count * elem, 256); }
+
+// Device bytes of a scene with na active blocks: the same list of buffers rt_scene_create allocates.
+static size_t scene_bytes(const rt_scene_desc* d, const Geo& g, long long na)
+{
+    const size_t nb = (size_t)g.nblocks, cells = (size_t)na * g.cells;
+    size_t b = alloc_bytes(nb, 4) + alloc_bytes(nb, 1) + alloc_bytes(nb, 4) + alloc_bytes(nb, 4) + alloc_bytes(1, 4) +
+               alloc_bytes(nb, 1) + alloc_bytes((size_t)g.n_state_words, 8) + alloc_bytes(2, 8);
+    b += alloc_bytes(((size_t)na << (d->dim * (g.log2B - g.feat_level))) * kLam, 16);
+    if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) b += alloc_bytes(cells * kLam * 2, 4);
+    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP)
+        b += alloc_bytes(cells, 16) + alloc_bytes(cells, 4) + alloc_bytes(cells * (size_t)d->n_v * kLam * 2, 4);
+    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
+        const size_t rec = (size_t)cav_rec_floats(d->n_lines);
+        b += alloc_bytes(cells * rec, 4) + alloc_bytes(cells * rec, 2);
+    }
+    return b;
+}
+
+extern "C" {
+
+rt_status rt_scene_workspace_bytes(const rt_scene_desc* d, int64_t n_active, size_t* h_bytes)
+{
+    g_err.clear();
+    if (!d || !h_bytes) return fail(RT_E_ARG, "null argument");
+    RT_TRY(check_desc(d, nullptr));
+    Geo g;
+    make_geo(d, g);
+    if (n_active < 0 || n_active > g.nblocks) return fail(RT_E_ARG, "n_active must be in [0, %lld]", g.nblocks);
+    *h_bytes = scene_bytes(d, g, n_active);
+    return RT_OK;
+}
+
+rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, void* stream, rt_scene** out)
+{
+    g_err.clear();
+    if (!d || !inp || !out) return fail(RT_E_ARG, "null argument");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    RT_TRY(check_desc(d, inp));
+    const int log2B = ilog2(d->brick);
+
+    rt_scene* sc = new (std::nothrow) rt_scene();
+    if (!sc) return fail(RT_E_ARG, "out of host memory");
+    sc->desc = *d;
+    Geo& g = sc->g;
+    make_geo(d, g);
     if (d->model == RT_MODEL_LINES) {
         sc->lam.assign(d->h_lam, d->h_lam + d->n_lam);
         sc->lam0.assign(d->h_lam0, d->h_lam0 + d->n_lines);
@@ -220,6 +270,7 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
         sc->cav_rec = cav_rec_floats(d->n_lines);
         if ((st = sc->alloc(&B.cav, cells * (size_t)sc->cav_rec)) != RT_OK) return cleanup(st);
+        if ((st = sc->alloc((uint16_t**)&B.cav_lp, cells * (size_t)sc->cav_rec)) != RT_OK) return cleanup(st);
         size_t shm = sizeof(double) * (size_t)(4 * d->n_lines + 2 + d->dim) * g.cells;
         if (shm > 160 * 1024) return cleanup(fail(RT_E_UNSUPPORTED, "too many lines for the LDS chain"));
         if ((e = launch_cav_chain(g, in, B, na, d->n_lines, d->ds0, RT_AVG_LOG, s)) != hipSuccess)
@@ -258,20 +309,26 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     if (p->avg_mode != RT_AVG_LOG && p->avg_mode != RT_AVG_LINEAR) return fail(RT_E_ARG, "bad avg_mode");
     if (p->storage < RT_F32 || p->storage > RT_F16) return fail(RT_E_ARG, "bad storage dtype");
     const bool static_emis = d.model == RT_MODEL_STATIC || d.emission == RT_EMIS_STATIC;
-    if (!static_emis && p->storage != RT_F32)
-        return fail(RT_E_UNSUPPORTED, "reduced-precision storage is implemented for static emission");
+    if (d.emission == RT_EMIS_VELINTERP && p->storage != RT_F32)
+        return fail(RT_E_UNSUPPORTED, "velocity-interpolation nodes are stored in FP32");
     if (d.emission == RT_EMIS_CAV && p->avg_mode != RT_AVG_LOG)
         return fail(RT_E_UNSUPPORTED, "core-and-voigt chains are built in log mode");
     LamBatch lb = make_batch(sc, lam_begin, lam_end);
     const Geo& g = sc->g;
     int cap = p->max_level < 0 ? -1 : p->max_level;
     RT_HIP(launch_fill_levels(g, sc->b.levels, s));
-    int vrule = (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_CAV) ? 1 : 0;
+    if (p->iod_frame != RT_IOD_REST && p->iod_frame != RT_IOD_CORE) return fail(RT_E_ARG, "bad iod_frame");
+    const int vrule = (d.model == RT_MODEL_LINES && (d.emission == RT_EMIS_CAV || p->iod_frame == RT_IOD_CORE)) ? 1 : 0;
     RT_HIP(launch_build_static(g, sc->in, sc->b, sc->n_active, d.model, vrule, lb, lam_begin, d.ds0, p->iod_threshold,
                                p->tau_thin, cap, p->avg_mode, p->storage, static_emis ? 1 : 0, s));
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_VELINTERP)
         RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, d.ds0, p->avg_mode, s));
     RT_HIP(launch_pack_states(g, sc->b.levels, sc->b.states, s));
+    if (d.emission == RT_EMIS_CAV && p->storage != RT_F32 && sc->cav_lp_dtype != p->storage) {
+        // the chain does not depend on the wavelength: encode it once per dtype
+        RT_HIP(launch_cav_encode(sc->b.cav, sc->b.cav_lp, (long long)sc->n_active * g.cells * sc->cav_rec, p->storage, s));
+        sc->cav_lp_dtype = p->storage;
+    }
     sc->batch_begin = lam_begin;
     sc->batch_end = lam_end;
     sc->storage = p->storage;
@@ -292,6 +349,7 @@ TraceLaunch rt::make_trace(const rt_scene* sc, const rt_trace_params* p)
     t.vgrid = sc->b.vgrid;
     t.vnodes = sc->b.vnodes;
     t.cav = sc->b.cav;
+    t.cav_lp = sc->b.cav_lp;
     t.mode = p->mode;
     t.max_level = p->max_level < 0 ? 127 : p->max_level;
     t.graded = 0;
@@ -357,6 +415,7 @@ rt_status rt_trace_truncated(const rt_scene* sc, const rt_trace_params* p, float
     if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace_truncated before rt_scene_build");
     if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
     if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
+    if (sc->g.nblocks >= (1ll << 24)) return fail(RT_E_UNSUPPORTED, "truncated march needs fewer than 2^24 blocks");
     const long long all = (long long)sc->n_active * sc->g.bvox;
     if (!d_probes && n_probes != all) return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld", all);
     if (n_probes <= 0) return n_probes == 0 ? RT_OK : fail(RT_E_ARG, "n_probes must be >= 0");

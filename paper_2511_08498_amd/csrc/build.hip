@@ -242,6 +242,8 @@ __global__ void k_build_static(Geo g, Inputs in, SceneBufs bufs, int model, int 
                     for (int j = 0; j < nch; ++j) q[j] = sc[4 * idx[j] + f];
                     st[f] = tree_sum<D>(q) / nch;
                 }
+                // stored values: geometric (LOG) or arithmetic (LINEAR) mean; slots 2 and 3
+                // always carry the arithmetic means of the MIP-0 values the cell covers
                 double le, lc;
                 if (avg_mode == RT_AVG_LOG) {
                     le = exp(st[0]) / ds0;
@@ -253,11 +255,12 @@ __global__ void k_build_static(Geo g, Inputs in, SceneBufs bufs, int model, int 
                 double* so = lds + 4 * (g.lvl_off[m] + tid);
                 so[0] = st[0];
                 so[1] = st[1];
-                so[2] = le;
-                so[3] = lc;
+                so[2] = st[2];
+                so[3] = st[3];
                 double iod_e = var[0] == 0.0 ? 0.0 : (st[0] == 0.0 ? __builtin_inf() : fabs(var[0] / st[0]));
                 double iod_c = var[1] == 0.0 ? 0.0 : (st[1] == 0.0 ? __builtin_inf() : fabs(var[1] / st[1]));
-                int thin = lc * (double)(1 << m) * ds0 < tau_thin;
+                // thin bypass on the cell's optical side with the box-filtered chi
+                int thin = st[3] * (double)(1 << m) * ds0 < tau_thin;
                 int pass = thin || (iod_e <= T_iod && iod_c <= T_iod);
                 if (!pass) pass_all[m] = 0;
                 if (bufs.fstats && m == g.feat_level)

@@ -281,3 +281,25 @@ hipError_t launch_cav_chain(const Geo& g, const Inputs& in, const SceneBufs& b, 
 }
 
 }  // namespace rt
+
+namespace rt {
+
+// Reduced-precision copy of the Core-and-Voigt chain (round to nearest even).
+template <typename T>
+__global__ void k_cav_encode(const float* cav, T* out, long long n)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = Codec<T>::enc(cav[i]);
+}
+
+hipError_t launch_cav_encode(const float* cav, void* out, long long n, int storage, hipStream_t s)
+{
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (storage == RT_BF16)
+        hipLaunchKernelGGL(k_cav_encode<__hip_bfloat16>, dim3(nb), dim3(256), 0, s, cav, (__hip_bfloat16*)out, n);
+    else
+        hipLaunchKernelGGL(k_cav_encode<__half>, dim3(nb), dim3(256), 0, s, cav, (__half*)out, n);
+    return hipGetLastError();
+}
+
+}  // namespace rt

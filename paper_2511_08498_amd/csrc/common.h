@@ -58,6 +58,7 @@ struct SceneBufs {
     float* vmax;            // [n_active][cells] V = max |v| over the cell's MIP-0 voxels
     float* vnodes;          // [n_active][cells][n_v][kLam][2] node values (velocity interpolation)
     float* cav;             // [n_active][cells][cav_rec] line parameters (Core and Voigt)
+    void* cav_lp;           // the same in BF16 or FP16 (reduced-precision storage), 2 bytes per value
     float4* fstats;         // [n_active][cells at feat_level][kLam]: mean, var of ln(chi ds0), mean, var of ln(eta ds0)
     unsigned long long* err;  // [2]: step-cap hits, first ray id (min)
 };
@@ -124,6 +125,7 @@ hipError_t launch_cav_chain(const Geo& g, const Inputs& in, const SceneBufs& b, 
                             double ds0, int avg_mode, hipStream_t s);
 hipError_t launch_read_cells(const Geo& g, const SceneBufs& b, int storage, int n, const int32_t* cells,
                              float* out, hipStream_t s);
+hipError_t launch_cav_encode(const float* cav, void* out, long long n, int storage, hipStream_t s);
 
 // march.hip
 struct TraceLaunch {
@@ -134,6 +136,7 @@ struct TraceLaunch {
     const float4* vgrid;
     const float* vnodes;
     const float* cav;
+    const void* cav_lp;  // BF16/FP16 copy of cav, used when storage != RT_F32
     const float* dirs;
     int n_dir;
     int mode;

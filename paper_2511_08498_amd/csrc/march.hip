@@ -191,18 +191,29 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
 
 // ------------------------------------------------------------ RTE update
 // One segment, one wavelength, front to back:
-//   I += T (eta dt) g(tau),  T *= exp(-tau),  g(tau) = (1 - exp(-tau)) / tau,
+//   I += T eta dt g(tau),  T *= exp(-tau),  g(tau) = (1 - exp(-tau)) / tau,
 // which is S (1 - exp(-tau)) with S = eta/chi and stays finite at chi = 0.
-// g uses 1 - tau/2 + tau^2/6 below tau = 1/32 (truncation < tau^3/24 < 1.3e-6
-// relative) and (1 - exp(-tau)) / tau above (cancellation < 2e-6 relative).
-__device__ __forceinline__ void rte_step(float& I, float& Tr, float eta, float chi, float dt)
+// The exponent is taken in base 2, a = chi dt log2(e) (exp(-tau) = 2^-a), and
+// h = dt g(tau) is (1 - 2^-a) / chi above tau = 1/32 (cancellation < 2e-6
+// relative) and the series dt (1 - tau/2 + tau^2/6) = dt + q1 a + q2 a^2 below
+// (truncation < tau^3/24 < 1.3e-6 relative).  dt, dt log2(e), q1 = -dt ln2/2
+// and q2 = dt ln2^2/6 are per-segment constants shared by the wavelength batch.
+struct SegK {
+    float dt, dtl, q1, q2;
+    __device__ __forceinline__ explicit SegK(float d)
+        : dt(d), dtl(d * 1.4426950408889634f), q1(d * -0.34657359027997264f), q2(d * 0.08007550231970024f)
+    {
+    }
+};
+
+__device__ __forceinline__ void rte_step(float& I, float& Tr, float eta, float chi, const SegK& k)
 {
-    float tau = chi * dt;
-    float e = __expf(-tau);
-    float gp = fmaf(tau, fmaf(tau, 1.0f / 6.0f, -0.5f), 1.0f);
-    float gd = (1.0f - e) * __builtin_amdgcn_rcpf(tau);
-    float gg = tau < 0.03125f ? gp : gd;
-    I = fmaf(Tr * (eta * dt), gg, I);
+    const float a = chi * k.dtl;
+    const float e = __builtin_amdgcn_exp2f(-a);
+    const float hs = fmaf(a, fmaf(a, k.q2, k.q1), k.dt);
+    const float hd = (1.0f - e) * __builtin_amdgcn_rcpf(chi);
+    const float h = a < 0.045084220027780106f ? hs : hd;  // tau < 1/32
+    I = fmaf(Tr * eta, h, I);
     Tr *= e;
 }
 
@@ -269,6 +280,32 @@ __device__ __forceinline__ int local_index(const Geo& g, const int* c, int lvl, 
     return li;
 }
 
+// Four consecutive values of a record, decoded to FP32 (index i counts groups of 4).
+template <typename T>
+__device__ __forceinline__ float4 load4(const T* r, int i);
+
+template <>
+__device__ __forceinline__ float4 load4<float>(const float* r, int i)
+{
+    return ((const float4*)r)[i];
+}
+
+template <>
+__device__ __forceinline__ float4 load4<__hip_bfloat16>(const __hip_bfloat16* r, int i)
+{
+    const uint2 v = ((const uint2*)r)[i];
+    return make_float4(bf16_lo(v.x), bf16_hi(v.x), bf16_lo(v.y), bf16_hi(v.y));
+}
+
+template <>
+__device__ __forceinline__ float4 load4<__half>(const __half* r, int i)
+{
+    uint2 v = ((const uint2*)r)[i];
+    const float2 a = __half22float2(*reinterpret_cast<__half2*>(&v.x));
+    const float2 b = __half22float2(*reinterpret_cast<__half2*>(&v.y));
+    return make_float4(a.x, a.y, b.x, b.y);
+}
+
 // --------------------------------------------------------- accumulators
 // Plain: the whole ray, front to back.
 struct AccPlain {
@@ -285,9 +322,9 @@ struct AccPlain {
     __device__ __forceinline__ bool add(const float* e, const float* x, const int*, int, long long, double t0,
                                         double t1, float dsf)
     {
-        float dt = (float)(t1 - t0) * dsf;
+        const SegK k((float)(t1 - t0) * dsf);
 #pragma unroll
-        for (int l = 0; l < kLam; ++l) rte_step(I[l], Tr[l], e[l], x[l], dt);
+        for (int l = 0; l < kLam; ++l) rte_step(I[l], Tr[l], e[l], x[l], k);
         return false;
     }
 };
@@ -328,15 +365,15 @@ struct AccTrunc {
     }
     __device__ __forceinline__ void near(const float* e, const float* x, double t0, double t1, float dsf)
     {
-        float dt = (float)(t1 - t0) * dsf;
+        const SegK k((float)(t1 - t0) * dsf);
 #pragma unroll
-        for (int l = 0; l < kLam; ++l) rte_step(In[l], Tn[l], e[l], x[l], dt);
+        for (int l = 0; l < kLam; ++l) rte_step(In[l], Tn[l], e[l], x[l], k);
     }
     __device__ __forceinline__ void far(const float* e, const float* x, double t0, double t1, float dsf)
     {
-        float dt = (float)(t1 - t0) * dsf;
+        const SegK k((float)(t1 - t0) * dsf);
 #pragma unroll
-        for (int l = 0; l < kLam; ++l) rte_step(If[l], Tf[l], e[l], x[l], dt);
+        for (int l = 0; l < kLam; ++l) rte_step(If[l], Tf[l], e[l], x[l], k);
     }
     __device__ __forceinline__ bool add(const float* e, const float* x, const int* c, int lvl, long long blk,
                                         double t0, double t1, float dsf)
@@ -439,12 +476,14 @@ struct VisVelinterp {
         // vgrid = (s, vbar): node coordinate f = (u + V)/(2V) (n_v - 1) = u s + (n_v - 1)/2,
         // s = (n_v - 1)/(2V) (0 when V = 0: all nodes are equal, the middle one is used)
         float4 vg = tl->vgrid[cell];
-        float u = vg.y * w[0] + vg.z * w[1] + (D > 2 ? vg.w * w[2] : 0.f);
+        float u = fmaf(vg.z, w[1], vg.y * w[0]);
+        if (D > 2) u = fmaf(vg.w, w[2], u);
         const int nv = tl->n_v;
         float f = fmaf(u, vg.x, 0.5f * (float)(nv - 1));
         int kn = (int)floorf(f);
         kn = kn < 0 ? 0 : (kn > nv - 2 ? nv - 2 : kn);
         float wt = f - (float)kn;
+        // the two node records around u are adjacent (128 B)
         const float* r0 = tl->vnodes + (cell * (unsigned)nv + (unsigned)kn) * (unsigned)(kLam * 2);
         float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
         load_rec<float>(r0, e0, x0);
@@ -459,7 +498,7 @@ struct VisVelinterp {
     }
 };
 
-template <int D, class Acc = AccPlain>
+template <int D, typename T = float, class Acc = AccPlain>
 struct VisCav {
     using AccT = Acc;
     const TraceLaunch* tl;
@@ -498,22 +537,22 @@ struct VisCav {
             base = (long long)tl->slot[blk] * tl->g.cells;
         }
         long long cell = base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D);
-        const float4* r = (const float4*)(tl->cav + cell * tl->cav_rec);
+        const T* r = (const T*)(sizeof(T) == 4 ? (const void*)tl->cav : tl->cav_lp) + cell * tl->cav_rec;
         const int nln = tl->lb.n_lines;
         float ls[kMaxLines][4];
 #pragma unroll
         for (int k = 0; k < kMaxLines; ++k) {
             if (k < nln) {
-                float4 q = r[k];
+                float4 q = load4<T>(r, k);
                 ls[k][0] = q.x;
                 ls[k][1] = q.y;
                 ls[k][2] = q.z;
                 ls[k][3] = q.w;
             }
         }
-        float4 bgv = r[nln];  // eta_bg, chi_bg, vx, vy
+        float4 bgv = load4<T>(r, nln);  // eta_bg, chi_bg, vx, vy
         float vz = 0.f;
-        if (D > 2) vz = ((const float*)r)[4 * nln + 4];
+        if (D > 2) vz = load4<T>(r, nln + 1).x;
         float u = bgv.z * w[0] + bgv.w * w[1] + vz * w[2];
         const bool voigt = tl->lb.profile == RT_PROFILE_VOIGT;
         float eo[kLam], xo[kLam];
@@ -543,24 +582,11 @@ struct VisCav {
 };
 
 // ------------------------------------------------------------ trace kernel
+// One ray (direction dir, probe index probe) of a trace launch.
 template <int D, class Vis>
-__global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
+__device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* sts, long long dir, long long probe,
+                                          Counters& cnt)
 {
-    extern __shared__ uint64_t sts[];
-    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
-    __syncthreads();
-    // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; give
-    // each XCD a contiguous range of (direction, probe tile) work.
-    const unsigned G = gridDim.x, wg = blockIdx.x;
-    const unsigned q = G / 8u, r = G % 8u, xcd = wg % 8u, i = wg / 8u;
-    const unsigned lwg = xcd < r ? xcd * (q + 1u) + i : r * (q + 1u) + (xcd - r) * q + i;
-    const long long tiles = (t.n_probes + 63) / 64;
-    const long long wave = (long long)lwg * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const long long dir = wave / tiles;
-    const long long probe = (wave - dir * tiles) * 64 + lane;
-    if (dir >= t.n_dir || probe >= t.n_probes) return;
-
     int pv[3] = {0, 0, 0};
     if (t.probes) {
         long long v = t.probes[probe];
@@ -582,7 +608,6 @@ __global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
 
     Vis vis;
     vis.init(&t, wf);
-    Counters cnt = {0, 0, 0};
     int rc = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
     int capped = rc == 1;
     const int nl = t.lb.nl;
@@ -610,7 +635,9 @@ __global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
             if (D > 2) pz = (float)((double)pv[2] + 0.5 - A.tstar * (double)wf[2]);
             else pz = 0.5f;
         }
-        t.feat[pidx] = make_float4(px, py, pz, query ? 1.f : 0.f);
+        // w: 0 without a query, else 1 + the block whose cell holds the truncation point
+        // (exact in FP32 up to 2^24 blocks; the held-out check flags this block)
+        t.feat[pidx] = make_float4(px, py, pz, query ? (float)(A.tblk + 1) : 0.f);
         // level statistics of the feature-level cell at the truncation point
         const int fl = t.g.feat_level;
         const int sl = t.g.log2B - fl;
@@ -624,15 +651,45 @@ __global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
             t.fstat_out[((long long)dir * nl + l) * t.n_probes + probe] = st;
         }
     }
-    if (t.stats) {
-        atomicAdd(&t.stats[0], (unsigned long long)cnt.segs);
-        atomicAdd(&t.stats[1], 1ull);
-        atomicAdd(&t.stats[2], (unsigned long long)cnt.empty);
-        atomicAdd(&t.stats[3], (unsigned long long)cnt.lvlchg);
-    }
     if (capped) {
         atomicAdd(&t.err[0], 1ull);
         atomicMin(&t.err[1], (unsigned long long)(dir * t.n_probes + probe));
+    }
+}
+
+template <int D, class Vis>
+__global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
+{
+    extern __shared__ uint64_t sts[];
+    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
+    __syncthreads();
+    // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; give
+    // each XCD a contiguous range of (direction, probe tile) work.
+    const unsigned G = gridDim.x, wg = blockIdx.x;
+    const unsigned q = G / 8u, r = G % 8u, xcd = wg % 8u, i = wg / 8u;
+    const unsigned lwg = xcd < r ? xcd * (q + 1u) + i : r * (q + 1u) + (xcd - r) * q + i;
+    const long long tiles = (t.n_probes + 63) / 64;
+    // one direction per wave: keep the wave index (and with it the direction, its
+    // step signs and reciprocals) in scalar registers
+    const long long wave = (long long)lwg * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const long long dir = wave / tiles;
+    const long long probe = (wave - dir * tiles) * 64 + lane;
+    Counters cnt = {0, 0, 0};
+    if (dir < t.n_dir && probe < t.n_probes) trace_ray<D, Vis>(t, sts, dir, probe, cnt);
+    if (t.stats) {
+        // the whole wave is active again here; [4] sums the longest ray of each wave
+        // (in traversal steps), so ([0] + [2]) / (64 [4]) is the lane utilisation
+        const bool live = dir < t.n_dir && probe < t.n_probes;
+        unsigned steps = cnt.segs + cnt.empty, wmax = steps;
+        for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (unsigned)__shfl_xor((int)wmax, o, 64));
+        if (live) {
+            atomicAdd(&t.stats[0], (unsigned long long)cnt.segs);
+            atomicAdd(&t.stats[1], 1ull);
+            atomicAdd(&t.stats[2], (unsigned long long)cnt.empty);
+            atomicAdd(&t.stats[3], (unsigned long long)cnt.lvlchg);
+        }
+        if (lane == 0 && dir < t.n_dir) atomicAdd(&t.stats[4], (unsigned long long)wmax);
     }
 }
 
@@ -665,8 +722,14 @@ static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
         if (t.g.dim == 2) return launch_one<2, VisVelinterp<2, Acc>>(t, s);
         return launch_one<3, VisVelinterp<3, Acc>>(t, s);
     }
-    if (t.g.dim == 2) return launch_one<2, VisCav<2, Acc>>(t, s);
-    return launch_one<3, VisCav<3, Acc>>(t, s);
+    if (t.g.dim == 2) {
+        if (t.storage == RT_F32) return launch_one<2, VisCav<2, float, Acc>>(t, s);
+        if (t.storage == RT_BF16) return launch_one<2, VisCav<2, __hip_bfloat16, Acc>>(t, s);
+        return launch_one<2, VisCav<2, __half, Acc>>(t, s);
+    }
+    if (t.storage == RT_F32) return launch_one<3, VisCav<3, float, Acc>>(t, s);
+    if (t.storage == RT_BF16) return launch_one<3, VisCav<3, __hip_bfloat16, Acc>>(t, s);
+    return launch_one<3, VisCav<3, __half, Acc>>(t, s);
 }
 
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)

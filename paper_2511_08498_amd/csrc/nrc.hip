@@ -440,7 +440,7 @@ __global__ void k_nrc_pack(NrcPack a)
     r[8] = log1pf(fmaxf(st.y, 0.f));
     r[9] = (st.z - st.x) * 0.1f;
     r[10] = log1pf(fmaxf(st.w, 0.f));
-    r[11] = f.w;
+    r[11] = f.w > 0.f ? 1.f : 0.f;
     float If = a.I_far[q];
     a.target[a.row0 + q] = f.w > 0.f ? __logf(fmaxf(If, 1e-30f)) * 0.1f : 0.f;
 }
@@ -448,8 +448,8 @@ __global__ void k_nrc_pack(NrcPack a)
 // held-out check: composed prediction vs the exact composition, per row;
 // blocks whose rows exceed the threshold fall back to the full march
 __global__ void k_nrc_validate(const float* I_pred, const float* I_near, const float* T_near, const float* I_far,
-                               const float4* feat, long long n_dir, int nl, long long np, int B, int log2B,
-                               int nb0, int nb1, int nb2, float thresh, uint8_t* fallback, float* err_out)
+                               const float4* feat, long long n_dir, int nl, long long np, long long n_blocks,
+                               float thresh, uint8_t* fallback, float* err_out)
 {
     long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long rows = n_dir * nl * np;
@@ -461,10 +461,8 @@ __global__ void k_nrc_validate(const float* I_pred, const float* I_near, const f
     float e = f.w > 0.f ? fabsf(I_pred[q] - Itrue) / fmaxf(fabsf(Itrue), 1e-37f) : 0.f;
     if (err_out) err_out[q] = e;
     if (f.w > 0.f && e > thresh) {
-        int bx = min(max((int)floorf(f.x), 0) >> log2B, nb0 - 1);
-        int by = min(max((int)floorf(f.y), 0) >> log2B, nb1 - 1);
-        int bz = min(max((int)floorf(f.z), 0) >> log2B, nb2 - 1);
-        fallback[bx + (long long)nb0 * (by + (long long)nb1 * bz)] = 1;
+        long long blk = (long long)f.w - 1;  // block of the truncation point, recorded by the march
+        if (blk >= 0 && blk < n_blocks) fallback[blk] = 1;
     }
 }
 
@@ -591,7 +589,24 @@ static hipError_t nrc_backward(rt_nrc* nn, long long rows, hipStream_t s)
     return hipGetLastError();
 }
 
+// Device bytes of the cache's buffers for a maximum batch B (the list rt_nrc_create allocates).
+static size_t nrc_bytes(size_t B, int n_wgs)
+{
+    auto a = [](size_t count, size_t elem) { return std::max<size_t>(count * elem, 256); };
+    return 4 * a(kParamsPadded, 4) + a(kParamsPadded, 2) + a(B * kFeat, 2) + a(4 * B * kHid, 4) + a(4 * B * kHid, 2) +
+           a(B, 4) + a(B * kHid, 2) + a(B * kHid, 4) + a(64 * (size_t)kHid * kFeat, 4) + a((size_t)n_wgs, 4);
+}
+
 extern "C" {
+
+rt_status rt_nrc_workspace_bytes(const rt_nrc_desc* d, size_t* h_bytes)
+{
+    if (!d || !h_bytes) return set_error(RT_E_ARG, "null argument");
+    if (d->max_batch < 256 || d->max_batch % 256 != 0 || d->max_batch > (1 << 19))
+        return set_error(RT_E_ARG, "max_batch must be a multiple of 256 in [256, 2^19]");
+    *h_bytes = nrc_bytes((size_t)d->max_batch, 512);
+    return RT_OK;
+}
 
 rt_status rt_nrc_num_params(int32_t* n)
 {
@@ -828,7 +843,7 @@ rt_status rt_nrc_validate(const rt_nrc* nn, const rt_scene* sc, const float* d_d
     long long rows = (long long)n_dir * nl * n_probes;
     hipLaunchKernelGGL(k_nrc_validate, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d_I_pred,
                        d_I_near, d_T_near, d_I_far, (const float4*)d_feat, (long long)n_dir, nl, (long long)n_probes,
-                       sc->g.B, sc->g.log2B, sc->g.nb[0], sc->g.nb[1], sc->g.nb[2], thresh, d_fallback, d_err);
+                       (long long)sc->g.nblocks, thresh, d_fallback, d_err);
     NRC_HIP(hipGetLastError());
     return RT_OK;
 }

@@ -27,6 +27,7 @@ struct rt_scene {
     int batch_begin = -1, batch_end = -1;
     int storage = RT_F32;
     int cav_rec = 0;
+    int cav_lp_dtype = -1;  // dtype currently encoded in b.cav_lp (-1: none)
 
     ~rt_scene()
     {

@@ -343,6 +343,7 @@ def make_cfg3(seed: int = 3, n: int = 256, B: int = 8, z_slab: int = 48, n_lam_p
         chi_star.append(np.where(bmask, (50.0 if l == 0 else 2.0) * dens * math.sqrt(math.pi) * dld_ref, 0.0))
         inv_dld.append(np.where(bmask, C_KMS / (l0 * vD), 0.0))
     chi_star = np.stack(chi_star)
+    inv_dld = np.stack(inv_dld)
     eta_star = chi_star * S
     damp = np.stack([np.where(bmask, a0, 0.0)] * 2)
     chi_bg = np.where(bmask, 1e-3 * dens, 0.0)

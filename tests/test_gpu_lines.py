@@ -129,6 +129,19 @@ def test_velinterp_parity(rt, vscene):
     assert lv_gpu.max() >= 1
 
 
+def test_velinterp_core_frame_levels(rt, vscene):
+    """Velocity interpolation with the level test in the core-closest frame: levels follow the oracle's rule 1."""
+    sc = vscene
+    T = 1e-2
+    scene = rt.Scene.from_dict(sc, emission="velinterp", n_v=21)
+    for lam0 in (0, 8):
+        scene.build(lam0, lam0 + 8, iod_threshold=T, iod_frame="core")
+        lv_core = scene.levels()
+        check_levels(lv_core, sc, list(range(lam0, lam0 + 8)), 1, T)
+        scene.build(lam0, lam0 + 8, iod_threshold=T)
+        assert np.all(lv_core <= scene.levels() + 3)  # both valid level maps
+
+
 def test_cav_parity(rt):
     import torch
     sc = cav_scene()
@@ -155,6 +168,35 @@ def test_cav_parity(rt):
         print("CaV VLM(graded) vs Classic:", orc.rel_err_stats(I, ref_c))
 
 
+@pytest.mark.parametrize("storage,bound", [("bf16", 5e-2), ("f16", 1e-2)])
+def test_cav_reduced_precision_storage(rt, storage, bound):
+    """Core and Voigt with the line-parameter chain stored in BF16 / FP16 (round to nearest even) against the FP64
+    oracle on the same adapted cells.  Bound from the storage rounding (2^-9 BF16, 2^-12 FP16 relative on each of
+    eta*, chi*, a, 1/dlD and v): the profile argument's relative error is amplified by up to 2 x^2 in the Gaussian
+    core-to-wing range (x <~ 3), about 5 % (BF16) and 1 % (FP16) at p99.9 over the sample."""
+    import torch
+    sc = cav_scene()
+    T = 0.1
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    scene = rt.Scene.from_dict(sc, emission="cav")
+    k, vox, d = sample_rays(scene, 8, 300, 3)
+    scene.build(0, 8, iod_threshold=T)
+    I32 = scene.trace(dirs, mode="vlm").cpu().numpy()[d, :, k]
+    lv_gpu = scene.levels()
+    scene.build(0, 8, iod_threshold=T, storage=storage)
+    assert np.array_equal(scene.levels(), lv_gpu)  # levels do not depend on the storage dtype
+    I = scene.trace(dirs, mode="vlm").cpu().numpy()[d, :, k]
+    lv = check_levels(lv_gpu, sc, list(range(0, 8)), 1, T)
+    ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
+    s = orc.Scene(sc, lam_idx=list(range(0, 8)))
+    ref = orc.march(s, orc.CAV, lv, vox, d)
+    st = orc.rel_err_stats(I[ok], ref[ok])
+    st32 = orc.rel_err_stats(I32[ok], ref[ok])
+    print("CaV %s storage vs FP64: p99.9 %.3g max %.3g (FP32 storage: p99.9 %.3g)" % (
+        storage, st["p99.9"], st["p100"], st32["p99.9"]))
+    assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < bound
+
+
 def test_cav_level0_dense_is_classic(rt, vscene):
     """A dense scene traced at level 0 with Core and Voigt is the DenseClassic march."""
     import torch
@@ -169,3 +211,10 @@ def test_cav_level0_dense_is_classic(rt, vscene):
     ref = orc.march(s, orc.CLASSIC, None, vox, d)
     st = orc.rel_err_stats(I, ref)
     assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 2e-5, st
+
+
+def test_workspace_bytes_match_allocation(rt, vscene):
+    """The host-only size query equals what rt_scene_create allocated (velocity nodes, Core-and-Voigt chains)."""
+    for sc, emis in ((vscene, "velinterp"), (cav_scene(), "cav")):
+        s = rt.Scene.from_dict(sc, emission=emis)
+        assert s.info["storage_bytes"] == rt.scene_workspace_bytes(sc, n_active=s.info["n_active"], emission=emis)

@@ -62,7 +62,8 @@ def test_generation_mode_composes_to_full_march(rt, setup):
     I = full.cpu().numpy().astype(np.float64)
     In, Tn, If = (gen[k].cpu().numpy().astype(np.float64) for k in ("I_near", "T_near", "I_far"))
     flag = gen["feat"].cpu().numpy()[..., 3]
-    assert set(np.unique(flag)) <= {0.0, 1.0}
+    # 0, or 1 + the index of an active block
+    assert np.all(flag == np.round(flag)) and np.all((flag == 0) | sc["block_active"][np.maximum(flag.astype(int) - 1, 0)].astype(bool))
     q = flag[:, None, :] > 0
     assert 0.2 < q.mean() < 0.95  # both kinds of rays are present
     comp = In + Tn * If
@@ -86,8 +87,9 @@ def test_truncation_points_match_oracle_segments(rt, setup):
     fstat = gen["fstat"].cpu().numpy()
     probes = scene.probe_voxels()
     rng = np.random.default_rng(11)
-    lchi = np.log(sc["chi"][0:8].astype(np.float64) * sc["ds0"])
-    leta = np.log(sc["eta"][0:8].astype(np.float64) * sc["ds0"])
+    with np.errstate(divide="ignore"):  # empty bricks (chi = eta = 0) are never a truncation cell
+        lchi = np.log(sc["chi"][0:8].astype(np.float64) * sc["ds0"])
+        leta = np.log(sc["eta"][0:8].astype(np.float64) * sc["ds0"])
     n_q = 0
     for d in range(dirs.shape[0]):
         w = sc["dirs"][d]
@@ -100,7 +102,8 @@ def test_truncation_points_match_oracle_segments(rt, setup):
                 continue
             k = k[0]
             n_q += 1
-            assert feat[d, pi, 3] == 1.0
+            # the block holding the truncation cell, recorded as 1 + its index
+            assert feat[d, pi, 3] == 1 + cells[k, 0] // 8 + 8 * (cells[k, 1] // 8)
             ts = max(t_in[k], T_TRUNC)
             x = np.array(pv, np.float64) + 0.5 - ts * w.astype(np.float64)
             assert np.max(np.abs(feat[d, pi, :2] - x)) < 2e-5
@@ -223,7 +226,7 @@ def test_cache_compose_validate_and_gain(rt, setup):
     nn.pack(scene, gen, raw, tgt, 0)
     torch.cuda.synchronize()
     # packed rows: flag column equals the query flag of (dir, probe), targets ln(I_far)/10
-    flag = gen["feat"][..., 3]
+    flag = (gen["feat"][..., 3] > 0).float()
     assert torch.equal(raw[:, 11].view(nd, nl, npb), flag[:, None, :].expand(nd, nl, npb))
     If = gen["I_far"]
     qm = flag[:, None, :].expand(nd, nl, npb) > 0
@@ -254,7 +257,7 @@ def test_cache_compose_validate_and_gain(rt, setup):
     inf2 = scene.trace_truncated(dirs, T_TRUNC, gen=False, fallback=fb)
     I2 = nn.compose(scene, inf2)
     ft = gen["feat"].cpu().numpy()
-    blk = (np.clip(np.floor(ft[..., 0]), 0, 63).astype(int) // 8) + 8 * (np.clip(np.floor(ft[..., 1]), 0, 63).astype(int) // 8)
+    blk = np.maximum(ft[..., 3].astype(int) - 1, 0)
     fell = (ft[..., 3] > 0) & flagged[blk]
     fell3 = np.broadcast_to(fell[:, None, :], full.shape)
     assert fell.sum() > 0

@@ -128,8 +128,8 @@ def test_graded_intensities(rt, cfg1):
     st = orc.rel_err_stats(I, ref)
     assert st["p100"] < TOL_SAME_CELLS, st
     # grading only ever lowers levels: never more segments than plain VLM
-    stats_g = torch.zeros(4, dtype=torch.int64, device="cuda")
-    stats_p = torch.zeros(4, dtype=torch.int64, device="cuda")
+    stats_g = torch.zeros(5, dtype=torch.int64, device="cuda")
+    stats_p = torch.zeros(5, dtype=torch.int64, device="cuda")
     scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST, stats=stats_g)
     scene.trace(dirs, mode="vlm", stats=stats_p)
     assert stats_g[0].item() >= stats_p[0].item() and stats_g[1].item() == stats_p[1].item() == 8 * probes.size
@@ -303,3 +303,9 @@ def test_reduced_precision_storage(rt, cfg1, storage):
     st = orc.rel_err_stats(I, ref)
     assert st["p99.9"] < (5e-3 if storage == "bf16" else 1e-3), st
     print(storage, "storage vs FP64:", st)
+
+
+def test_workspace_bytes_match_allocation(rt, cfg1):
+    for dense in (False, True):
+        s = rt.Scene.from_dict(cfg1, dense=dense)
+        assert s.info["storage_bytes"] == rt.scene_workspace_bytes(cfg1, dense=dense)

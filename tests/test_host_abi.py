@@ -1,0 +1,55 @@
+"""Host-only entry points of the C ABI (no device work): size queries and descriptor validation."""
+import pytest
+
+from synth import make_cfg1
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import paper_2511_08498_amd as rt
+    rt.lib()
+    return rt
+
+
+def _layout_bytes(nb, n_state_words, na, cells, feat_cells, n_lam_batch=8):
+    """Device layout of a static scene, each buffer at least 256 B: morton, active, slot, active list,
+    active count, levels, states, error counters, level statistics [na][feat cells][8] float4,
+    values [na][cells][8][eta, chi] float."""
+    a = lambda n: max(n, 256)  # noqa: E731
+    return (a(4 * nb) + a(nb) + a(4 * nb) + a(4 * nb) + a(4) + a(nb) + a(8 * n_state_words) + a(16)
+            + a(16 * na * feat_cells * n_lam_batch) + a(4 * 2 * n_lam_batch * na * cells))
+
+
+def test_scene_workspace_bytes_static(rt):
+    sc = make_cfg1()
+    na = int(sc["block_active"].sum())
+    # 64^2, 8^2 bricks, 4 levels: 64 + 16 + 4 + 1 cells per brick, level-2 statistics (2^2 cells per brick)
+    assert rt.scene_workspace_bytes(sc) == _layout_bytes(64, 4, na, 85, 4)
+    assert rt.scene_workspace_bytes(sc, dense=True) == _layout_bytes(64, 4, 64, 85, 4)
+    assert rt.scene_workspace_bytes(sc, n_active=0) == _layout_bytes(64, 4, 0, 85, 4)
+
+
+def test_scene_descriptor_validation(rt):
+    sc = make_cfg1()
+    cases = [(dict(sc, n=(60, 64, 1)), rt.RT_E_ARG),            # not a multiple of the brick
+             (dict(sc, n_levels=5), rt.RT_E_ARG),                 # 8^2 bricks allow levels 0..3
+             (dict(sc, dim=3, n=(64, 64, 64), brick=16), rt.RT_E_UNSUPPORTED)]  # 3D uses 8^3 bricks
+    for bad, status in cases:
+        with pytest.raises(rt.RtError) as e:
+            rt.scene_workspace_bytes(bad)
+        assert e.value.status == status
+    with pytest.raises(rt.RtError) as e:
+        rt.scene_workspace_bytes(sc, n_active=65)
+    assert e.value.status == rt.RT_E_ARG
+
+
+def test_nrc_workspace_bytes(rt):
+    B = 16384
+    # weights/Adam/gradient (FP32, padded to 256) + BF16 copy, activations, gradients, split-K scratch, loss partials
+    npad = (rt.nrc_num_params() + 255) // 256 * 256
+    expect = (4 * 4 * npad + 2 * npad + 2 * B * 256 + 4 * 4 * B * 64 + 2 * 4 * B * 64 + 4 * B + 2 * B * 64
+              + 4 * B * 64 + 4 * 64 * 64 * 256 + 4 * 512)
+    assert rt.nrc_workspace_bytes(B) == expect
+    for bad in (0, 300, 1 << 20):
+        with pytest.raises(rt.RtError):
+            rt.nrc_workspace_bytes(bad)
