@@ -93,7 +93,7 @@ def _c(a, dt):
 class Scene:
     """Keeps numpy inputs alive and exposes an OrcScene struct."""
 
-    def __init__(self, sc: dict, lam_idx=None, n_v: int = 21, avg_mode: int = AVG_LOG):
+    def __init__(self, sc: dict, lam_idx=None, n_v: int = 21, avg_mode: int = AVG_LINEAR):
         self.sc = sc
         self.dim = sc["dim"]
         self.n = tuple(int(v) for v in sc["n"])
