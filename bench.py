@@ -89,8 +89,8 @@ def main():
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=21)
     ap.add_argument("--iod", type=float, default=1e-2)
-    ap.add_argument("--avg", default="log", choices=["log", "linear"], help="stored level values: geometric or "
-                    "arithmetic mean of the children")
+    ap.add_argument("--avg", default="linear", choices=["log", "linear"], help="stored level values: arithmetic "
+                    "(box filter, default) or geometric mean of the children")
     ap.add_argument("--tau-thin", type=float, default=0.25, help="thin bypass threshold on a cell's optical side")
     ap.add_argument("--grade-scale", type=float, default=1.0, help="multiplies the cascade level distances")
     ap.add_argument("--iod-frame", default="rest", choices=["rest", "core"],

@@ -74,9 +74,13 @@ typedef enum rt_emission {
     RT_EMIS_CAV = 2        /* Core and Voigt (Sect. 3.2): profile evaluated on the fly, lines model only */
 } rt_emission;
 
+/* Stored level values.  LINEAR is the box filter of Sect. 2.1 and the one the
+ * thin bypass of Sect. 2.2 assumes (the emergent intensity of a thin cell is
+ * linear in eta); LOG keeps the geometric mean, which underestimates the
+ * emission of cells mixing dense and near-empty voxels. */
 typedef enum rt_avg {
     RT_AVG_LOG = 0,   /* level value = exp(mean of ln(q ds0)) / ds0 (geometric mean) */
-    RT_AVG_LINEAR = 1 /* level value = arithmetic mean of the children */
+    RT_AVG_LINEAR = 1 /* level value = arithmetic mean of the children (box filter) */
 } rt_avg;
 
 typedef enum rt_dtype { RT_F32 = 0, RT_BF16 = 1, RT_F16 = 2 } rt_dtype;

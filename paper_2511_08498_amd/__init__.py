@@ -297,7 +297,7 @@ class Scene:
         _check(lib().rt_scene_get_info(self.h, ctypes.byref(inf)))
         return {k: getattr(inf, k) for k, _ in RtSceneInfo._fields_ if k != "reserved_"}
 
-    def build(self, lam_begin, lam_end, iod_threshold=1e-2, tau_thin=0.25, max_level=-1, avg_mode="log",
+    def build(self, lam_begin, lam_end, iod_threshold=1e-2, tau_thin=0.25, max_level=-1, avg_mode="linear",
               storage="f32", iod_frame="rest", stream=None):
         p = RtBuildParams()
         p.iod_frame = {"rest": 0, "core": 1}[iod_frame]

@@ -273,8 +273,9 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
         if ((st = sc->alloc((uint16_t**)&B.cav_lp, cells * (size_t)sc->cav_rec)) != RT_OK) return cleanup(st);
         size_t shm = sizeof(double) * (size_t)(4 * d->n_lines + 2 + d->dim) * g.cells;
         if (shm > 160 * 1024) return cleanup(fail(RT_E_UNSUPPORTED, "too many lines for the LDS chain"));
-        if ((e = launch_cav_chain(g, in, B, na, d->n_lines, d->ds0, RT_AVG_LOG, s)) != hipSuccess)
+        if ((e = launch_cav_chain(g, in, B, na, d->n_lines, d->ds0, RT_AVG_LINEAR, s)) != hipSuccess)
             return cleanup(fail(RT_E_HIP, "core-and-voigt chain: %s", hipGetErrorString(e)));
+        sc->cav_mode = RT_AVG_LINEAR;
     }
     *out = sc;
     return RT_OK;
@@ -311,8 +312,6 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     const bool static_emis = d.model == RT_MODEL_STATIC || d.emission == RT_EMIS_STATIC;
     if (d.emission == RT_EMIS_VELINTERP && p->storage != RT_F32)
         return fail(RT_E_UNSUPPORTED, "velocity-interpolation nodes are stored in FP32");
-    if (d.emission == RT_EMIS_CAV && p->avg_mode != RT_AVG_LOG)
-        return fail(RT_E_UNSUPPORTED, "core-and-voigt chains are built in log mode");
     LamBatch lb = make_batch(sc, lam_begin, lam_end);
     const Geo& g = sc->g;
     int cap = p->max_level < 0 ? -1 : p->max_level;
@@ -324,6 +323,12 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_VELINTERP)
         RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, d.ds0, p->avg_mode, s));
     RT_HIP(launch_pack_states(g, sc->b.levels, sc->b.states, s));
+    if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_CAV && p->avg_mode != sc->cav_mode) {
+        // the wavelength-independent chain follows the stored-value mode of the build
+        RT_HIP(launch_cav_chain(g, sc->in, sc->b, sc->n_active, d.n_lines, d.ds0, p->avg_mode, s));
+        sc->cav_mode = p->avg_mode;
+        sc->cav_lp_dtype = -1;
+    }
     if (d.emission == RT_EMIS_CAV && p->storage != RT_F32 && sc->cav_lp_dtype != p->storage) {
         // the chain does not depend on the wavelength: encode it once per dtype
         RT_HIP(launch_cav_encode(sc->b.cav, sc->b.cav_lp, (long long)sc->n_active * g.cells * sc->cav_rec, p->storage, s));

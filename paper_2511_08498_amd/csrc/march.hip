@@ -336,12 +336,15 @@ struct AccPlain {
 // the block reached there is flagged in the fallback map, in which case the
 // ray continues as a full march.  t* = max(t_trunc, entry of the first
 // non-empty cell beyond it): the far field from t* equals the one from t_trunc.
+template <bool Gen>
 struct AccTrunc {
     static constexpr bool kTrunc = true;
-    float In[kLam], Tn[kLam], If[kLam], Tf[kLam];
+    static constexpr bool kGen = Gen;  // generation mode: also accumulate the far field
+    float In[kLam], Tn[kLam];
+    float If[Gen ? kLam : 1], Tf[Gen ? kLam : 1];
     double tt;
-    const uint8_t* fallback;
-    int gen, reached, fb, tlvl;
+    const uint8_t* fallback;  // inference only
+    int reached, fb, tlvl;
     int tc[3];
     long long tblk;
     double tstar;
@@ -351,12 +354,16 @@ struct AccTrunc {
         for (int l = 0; l < kLam; ++l) {
             In[l] = 0.f;
             Tn[l] = 1.f;
-            If[l] = 0.f;
-            Tf[l] = 1.f;
+        }
+        if constexpr (Gen) {
+#pragma unroll
+            for (int l = 0; l < kLam; ++l) {
+                If[l] = 0.f;
+                Tf[l] = 1.f;
+            }
         }
         tt = t->t_trunc;
-        fallback = t->fallback;
-        gen = t->gen;
+        fallback = Gen ? nullptr : t->fallback;
         reached = fb = 0;
         tlvl = 0;
         tc[0] = tc[1] = tc[2] = 0;
@@ -371,16 +378,19 @@ struct AccTrunc {
     }
     __device__ __forceinline__ void far(const float* e, const float* x, double t0, double t1, float dsf)
     {
-        const SegK k((float)(t1 - t0) * dsf);
+        if constexpr (Gen) {
+            const SegK k((float)(t1 - t0) * dsf);
 #pragma unroll
-        for (int l = 0; l < kLam; ++l) rte_step(If[l], Tf[l], e[l], x[l], k);
+            for (int l = 0; l < kLam; ++l) rte_step(If[l], Tf[l], e[l], x[l], k);
+        }
     }
     __device__ __forceinline__ bool add(const float* e, const float* x, const int* c, int lvl, long long blk,
                                         double t0, double t1, float dsf)
     {
         if (reached) {
-            if (fb) near(e, x, t0, t1, dsf);
-            else far(e, x, t0, t1, dsf);
+            // generation: the far field; inference continues past the point only after a fallback
+            if constexpr (Gen) far(e, x, t0, t1, dsf);
+            else near(e, x, t0, t1, dsf);
             return false;
         }
         if (t1 <= tt) {
@@ -394,17 +404,21 @@ struct AccTrunc {
         tc[2] = c[2];
         tlvl = lvl;
         tblk = blk;
-        if (fallback && fallback[blk]) {
-            // full march from here on, without splitting this cell: the result is
-            // bit-identical to the plain march
-            fb = 1;
-            near(e, x, t0, t1, dsf);
+        if constexpr (!Gen) {
+            if (fallback && fallback[blk]) {
+                // full march from here on, without splitting this cell: the result is
+                // bit-identical to the plain march
+                fb = 1;
+                near(e, x, t0, t1, dsf);
+                return false;
+            }
+            if (t0 < tt) near(e, x, t0, tt, dsf);
+            return true;
+        } else {
+            if (t0 < tt) near(e, x, t0, tt, dsf);
+            far(e, x, tstar, t1, dsf);
             return false;
         }
-        if (t0 < tt) near(e, x, t0, tt, dsf);
-        if (!gen) return true;
-        far(e, x, tstar, t1, dsf);
-        return false;
     }
 };
 
@@ -626,7 +640,7 @@ __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* 
             const long long q = ((long long)dir * nl + l) * t.n_probes + probe;
             t.I_near[q] = query ? A.In[l] : fmaf(A.Tn[l], t.I0, A.In[l]);
             t.T_near[q] = query ? A.Tn[l] : 0.f;
-            if (t.I_far) t.I_far[q] = query ? fmaf(A.Tf[l], t.I0, A.If[l]) : t.I0;
+            if constexpr (Vis::AccT::kGen) t.I_far[q] = query ? fmaf(A.Tf[l], t.I0, A.If[l]) : t.I0;
         }
         float px = 0.f, py = 0.f, pz = 0.f;
         if (query) {
@@ -734,7 +748,7 @@ static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
 
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)
 {
-    if (t.trunc) return launch_trace_acc<AccTrunc>(t, s);
+    if (t.trunc) return t.gen ? launch_trace_acc<AccTrunc<true>>(t, s) : launch_trace_acc<AccTrunc<false>>(t, s);
     return launch_trace_acc<AccPlain>(t, s);
 }
 

@@ -28,6 +28,7 @@ struct rt_scene {
     int storage = RT_F32;
     int cav_rec = 0;
     int cav_lp_dtype = -1;  // dtype currently encoded in b.cav_lp (-1: none)
+    int cav_mode = -1;      // rt_avg the Core-and-Voigt chain was built with (-1: none)
 
     ~rt_scene()
     {

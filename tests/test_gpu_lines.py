@@ -168,6 +168,26 @@ def test_cav_parity(rt):
         print("CaV VLM(graded) vs Classic:", orc.rel_err_stats(I, ref_c))
 
 
+def test_cav_chain_follows_the_averaging_mode(rt):
+    """The Core-and-Voigt chain is rebuilt when a build asks for the other stored-value mode: LOG, then LINEAR
+    again, each against the oracle in the same mode on the same cells."""
+    import torch
+    sc = cav_scene()
+    T = 0.1
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    scene = rt.Scene.from_dict(sc, emission="cav")
+    k, vox, d = sample_rays(scene, 8, 200, 4)
+    for avg in ("log", "linear"):
+        scene.build(0, 8, iod_threshold=T, avg_mode=avg)
+        lv_gpu = scene.levels()
+        lv = check_levels(lv_gpu, sc, list(range(0, 8)), 1, T)
+        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
+        s = orc.Scene(sc, lam_idx=list(range(0, 8)), avg_mode=orc.AVG_LOG if avg == "log" else orc.AVG_LINEAR)
+        I = scene.trace(dirs, mode="vlm").cpu().numpy()[d, :, k]
+        st = orc.rel_err_stats(I[ok], orc.march(s, orc.CAV, lv, vox, d)[ok])
+        assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < 1e-3 and st["p100"] < 5e-3, (avg, st)
+
+
 @pytest.mark.parametrize("storage,bound", [("bf16", 5e-2), ("f16", 1e-2)])
 def test_cav_reduced_precision_storage(rt, storage, bound):
     """Core and Voigt with the line-parameter chain stored in BF16 / FP16 (round to nearest even) against the FP64

@@ -37,7 +37,7 @@ def cfg1():
     return make_cfg1()
 
 
-def oracle_batch(sc, lam0, lam1, T, avg=orc.AVG_LOG):
+def oracle_batch(sc, lam0, lam1, T, avg=orc.AVG_LINEAR):
     s = orc.Scene(sc, avg_mode=avg)
     lvs, st_e, st_c = orc.static_level_values(s, sc["eta"][lam0:lam1], sc["chi"][lam0:lam1], sc["block_active"], T=T)
     s.set_static_levels(st_e, st_c)
