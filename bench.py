@@ -104,9 +104,12 @@ def main():
                     help="profiling only: trace the first N wavelength batches per step (0 = all)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="profiling only: first run a device-to-device copy of this many MiB (counter calibration)")
+    ap.add_argument("--ladder", action="store_true", help="cfg2: error of other settings on the sampled rays")
     ap.add_argument("--pairs", type=int, default=8192, help="cfg3/cfg5: oracle sample size (probe, direction pairs)")
     ap.add_argument("--dtypes", default="f32,bf16,f16", help="cfg3: storage dtypes to time")
     ap.add_argument("--nrc-steps", type=int, default=3000, help="cfg5: Adam steps")
+    ap.add_argument("--nrc-freq", type=float, default=0.0, help="cfg5: highest encoding frequency (0: grid side / 2)")
+    ap.add_argument("--nrc-lr", type=float, default=1e-3, help="cfg5: Adam learning rate")
     ap.add_argument("--nrc-train-probes", type=int, default=1024, help="cfg5: training probes per wavelength batch")
     ap.add_argument("--nrc-held-probes", type=int, default=128, help="cfg5: held-out probes per wavelength batch")
     ap.add_argument("--scenes", type=int, default=0, help="cfg4: first N scenes only (0 = all 48)")
@@ -275,6 +278,24 @@ def bench_cfg2(args):
                                           "ms_per_batch": (tb - ta) * 1e3 / nbc}
         vlm_ms_batch = ms_step / nb_lam
         cmp["speedup_vs_dense_classic"] = cmp["dense_classic"]["ms_per_batch"] / vlm_ms_batch
+        if args.emission == "velinterp":
+            # the accuracy-preserving setting: no merging, 81 velocity nodes (error filled in below)
+            scene81 = rt.Scene.from_dict(sc, emission="velinterp", n_v=81)
+            kw81 = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin)
+            for b in range(nbc):
+                scene81.build(8 * b, 8 * b + 8, **kw81)
+                scene81.trace(dirs, mode="level0", out=tmp)
+            torch.cuda.synchronize()
+            ta = time.perf_counter()
+            for b in range(nbc):
+                scene81.build(8 * b, 8 * b + 8, **kw81)
+                scene81.trace(dirs, mode="level0", out=tmp)
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            cmp["sparse_velinterp_nv81"] = {"gseg_s": dense_cells * 8 * nbc / (tb - ta) / 1e9,
+                                            "ms_per_batch": (tb - ta) * 1e3 / nbc,
+                                            "speedup_vs_dense_classic":
+                                                cmp["dense_classic"]["ms_per_batch"] / ((tb - ta) * 1e3 / nbc)}
         out["comparators"] = cmp
 
     # ---- accuracy and CPU baseline on a seeded ray sample
@@ -310,7 +331,57 @@ def bench_cfg2(args):
         out["error"] = {"vs": "FP64 dense Classic oracle", "n": err["n"],
                         **{k2: err[k2] for k2 in err if k2.startswith("p")}}
         out["cpu_baseline"]["calibration_rate_gseg_s"] = rate / 1e9
+        if "comparators" in out and "sparse_velinterp_nv81" in out["comparators"]:
+            e81 = run_ladder(torch, np, [("sparse MIP 0, n_v=81", scene81, {}, {"mode": "level0"})],
+                             dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin), {},
+                             dirs, probes[k], d, ref, nb_lam)
+            out["comparators"]["sparse_velinterp_nv81"]["error_vs_fp64_classic"] = e81["sparse MIP 0, n_v=81"]
+        if args.ladder:
+            out["accuracy_ladder"] = accuracy_ladder(args, rt, torch, np, sc, scene, dirs, probes[k], d, ref, nb_lam,
+                                                     level_dist)
     print(json.dumps(out), flush=True)
+
+
+def accuracy_ladder(args, rt, torch, np, sc, scene, dirs, probe_vox, d, ref, nb_lam, level_dist):
+    """cfg2: error against the FP64 oracle of other settings on the same sampled rays."""
+    base = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, iod_frame=args.iod_frame)
+    scene81 = rt.Scene.from_dict(sc, emission=args.emission, n_v=81)
+    ld4 = [v * 4 for v in rt.CASCADE_LEVEL_DIST]
+    settings = [("as benchmarked", scene, {}, {}),
+                ("sparse MIP 0 (no merging)", scene, {}, {"mode": "level0"}),
+                ("levels <= 1", scene, {}, {"max_level": 1}),
+                ("levels <= 2", scene, {}, {"max_level": 2}),
+                ("plain VLM (no distance grading)", scene, {}, {"level_dist": None}),
+                ("no thin bypass", scene, {"tau_thin": 0.0}, {}),
+                ("core-closest level test", scene, {"iod_frame": "core"}, {}),
+                ("core-closest level test, T=1e-3", scene, {"iod_frame": "core", "iod_threshold": 1e-3}, {}),
+                ("n_v=81", scene81, {}, {}),
+                ("n_v=81, sparse MIP 0", scene81, {}, {"mode": "level0"}),
+                ("n_v=81, levels <= 1", scene81, {}, {"max_level": 1}),
+                ("n_v=81, levels <= 2", scene81, {}, {"max_level": 2}),
+                ("n_v=81, grading x4", scene81, {}, {"level_dist": ld4}),
+                ("n_v=81, core-closest, levels <= 2", scene81, {"iod_frame": "core"}, {"max_level": 2}),
+                ("n_v=81, core-closest, grading x4", scene81, {"iod_frame": "core"}, {"level_dist": ld4})]
+    return run_ladder(torch, np, settings, base, dict(mode="vlm", level_dist=level_dist), dirs, probe_vox, d, ref,
+                      nb_lam)
+
+
+def run_ladder(torch, np, settings, base_build, base_trace, dirs, probe_vox, d, ref, nb_lam):
+    """Each setting is traced only from the sampled probes (all directions); the sampled direction is picked."""
+    dev = dirs.device
+    pk = torch.from_numpy(np.ascontiguousarray(probe_vox)).to(dev)
+    dd = torch.from_numpy(d).long().to(dev)
+    ar = torch.arange(len(d), device=dev)
+    res = {}
+    for name, scn, bkw, tkw in settings:
+        got = np.zeros((len(d), nb_lam * 8))
+        for b in range(nb_lam):
+            scn.build(8 * b, 8 * b + 8, **dict(base_build, **bkw))
+            I = scn.trace(dirs, probes=pk, **dict(base_trace, **tkw))
+            got[:, 8 * b:8 * b + 8] = I[dd, :, ar].cpu().numpy()
+        res[name] = {k2: v for k2, v in _err(got, ref).items() if k2 in ("p100", "p99.9", "p99", "p50")}
+        log("ladder %-40s p99.9 %.3e" % (name, res[name]["p99.9"]))
+    return res
 
 
 # ----------------------------------------------------------------------------- shared helpers
@@ -425,7 +496,22 @@ def bench_cfg3(args):
     ref, cpu_seglam, cpu_s = _oracle_classic(sc, probe_vox, k, d, list(range(nb * 8)), nthreads)
     log("cfg3 oracle: %d pairs x %d lambda in %.1fs" % (k.size, nb * 8, cpu_s))
     dense_seglam = dense_cells * 8 * nb
-    out_line = {"workload": "cfg3", "config": {
+    ladder = None
+    if args.ladder:
+        base = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin)
+        settings = [("as benchmarked (f32)", scene, {}, {}),
+                    ("sparse MIP 0 (no merging)", scene, {}, {"mode": "level0"}),
+                    ("levels <= 1", scene, {}, {"max_level": 1}),
+                    ("levels <= 2", scene, {}, {"max_level": 2}),
+                    ("plain VLM (no distance grading)", scene, {}, {"level_dist": None}),
+                    ("no thin bypass", scene, {"tau_thin": 0.0}, {}),
+                    ("no thin bypass, log means", scene, {"tau_thin": 0.0, "avg_mode": "log"}, {}),
+                    ("log means", scene, {"avg_mode": "log"}, {}),
+                    ("no thin bypass, T=1e-3", scene, {"tau_thin": 0.0, "iod_threshold": 1e-3}, {}),
+                    ("no thin bypass, levels <= 2", scene, {"tau_thin": 0.0}, {"max_level": 2})]
+        ladder = run_ladder(torch, np, settings, base, dict(mode="vlm", level_dist=level_dist), dirs, probe_vox[k], d,
+                            ref, nb)
+    out_line = {"workload": "cfg3", "accuracy_ladder": ladder, "config": {
         "workload": "3D 256^3, 8^3 bricks, %d active (25%%), slab + %d loops, 2 Voigt lines (Core and Voigt) + "
                     "grey continuum, |v| <= 30 km/s, 4-level VLM T=%g, %s, 32 Fibonacci directions, %d lambda "
                     "(%d batches of 8), all %d probes" % (
@@ -612,7 +698,8 @@ def bench_cfg5(args):
     rows_b = n_dir * 8 * ptr
     raw = torch.zeros((nb * rows_b, 12), dtype=torch.float32, device=dev)
     tgt = torch.zeros(nb * rows_b, dtype=torch.float32, device=dev)
-    nn = rt.Nrc(max_batch=2 ** 14, freq_max=sc["n"][0] / 2.0, seed=5)
+    freq = args.nrc_freq if args.nrc_freq > 0 else sc["n"][0] / 2.0
+    nn = rt.Nrc(max_batch=2 ** 14, freq_max=freq, seed=5)
     torch.cuda.synchronize()
     ta = time.perf_counter()
     for b in range(nb):
@@ -624,12 +711,12 @@ def bench_cfg5(args):
     q_frac_train = float(raw[:, 11].mean().item())
     log("cfg5 generation: %d rows in %.2fs (query fraction %.3f)" % (raw.shape[0], gen_s, q_frac_train))
     ta = time.perf_counter()
-    nn.train(raw, tgt, steps=1, batch=2 ** 14, lr=1e-3)
+    nn.train(raw, tgt, steps=1, batch=2 ** 14, lr=args.nrc_lr)
     loss0 = nn.loss()
     done = 1
     while done < args.nrc_steps:
         n = min(500, args.nrc_steps - done)
-        nn.train(raw, tgt, steps=n, batch=2 ** 14, lr=1e-3)
+        nn.train(raw, tgt, steps=n, batch=2 ** 14, lr=args.nrc_lr)
         done += n
         log("cfg5 training: %d steps, loss %.3e" % (done, nn.loss()))
     torch.cuda.synchronize()
@@ -718,8 +805,9 @@ def bench_cfg5(args):
     out_line = {"workload": "cfg5", "config": {
         "workload": "radiance cache on the 3D 256^3 Core-and-Voigt scene (%d active bricks), BF16 storage, "
                     "truncation at path %g, %d lambda, 32 directions, all %d probes; %d training rows, %d held-out "
-                    "probes per batch; MLP 256-4x64 SiLU-1 BF16 MFMA, Adam lr 1e-3 batch 16384, %d steps" % (
-                        int(sc["block_active"].sum()), T_TRUNC, nb * 8, n_probes, raw.shape[0], phd, args.nrc_steps)},
+                    "probes per batch; MLP 256-4x64 SiLU-1 BF16 MFMA, frequencies up to %g, Adam lr %g batch 16384, "
+                    "%d steps" % (int(sc["block_active"].sum()), T_TRUNC, nb * 8, n_probes, raw.shape[0], phd, freq,
+                                  args.nrc_lr, args.nrc_steps)},
         "timing_ms_per_solve": {"plain_f32": ms_f32, "plain_bf16": ms_bf16, "cache": ms_nrc,
                                 "cache_trace_per_batch": tr_ms, "cache_compose_per_batch": comp_ms},
         "speedup_cache_vs_plain_f32": ms_f32 / ms_nrc, "speedup_cache_vs_plain_bf16": ms_bf16 / ms_nrc,

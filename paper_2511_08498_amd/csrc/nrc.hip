@@ -181,6 +181,11 @@ __global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
         float r[11], w, tgt;
         bool valid;
         row_raw(a, row_a, r, w, tgt, valid);
+        if (a.mode == 1 && !__any(valid && w > 0.f)) {
+            // no query in these 16 rows (rays that left the grid or fell back): copy I_near
+            if (g == 0 && valid) a.I_out[row_a] = a.I_near[row_a];
+            continue;
+        }
         // ---- layer 1: 256 -> 64
         f32x4 acc[4];
         for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
