@@ -573,12 +573,15 @@ def bench_cfg4(args):
                 it["scene"].build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
                                    storage="bf16", stream=stream)
 
-    def sequential(stats=None):
+    def sequential(stats=None, tag="sequential"):
         for b in range(waves):
             build_wave(b)
             for it in items:
                 if it["nb"] > b:
                     it["scene"].trace(it["dirs"], mode="vlm", level_dist=level_dist, out=it["out"], stats=stats)
+            if b % 8 == 7:
+                torch.cuda.synchronize()
+                log("cfg4 %s: wave %d/%d" % (tag, b + 1, waves))
 
     def jobs(part):
         return [{"scene": items[i]["scene"], "dirs": items[i]["dirs"], "out": items[i]["out"],
@@ -597,7 +600,7 @@ def bench_cfg4(args):
 
     run_ev = []
 
-    def batched(record=False, st=None):
+    def batched(record=False, st=None, tag="batched"):
         for b in range(waves):
             build_wave(b, stream=st)
             if record:
@@ -607,6 +610,9 @@ def bench_cfg4(args):
             if record:
                 e1.record(stream)
                 run_ev.append((e0, e1))
+            if st is None and b % 8 == 7:
+                torch.cuda.synchronize()
+                log("cfg4 %s: wave %d/%d" % (tag, b + 1, waves))
 
     # correctness: wave 0 batched == sequential, bit for bit
     build_wave(0)
@@ -619,15 +625,17 @@ def bench_cfg4(args):
     torch.cuda.synchronize()
     identical = all(torch.equal(r, it["out"]) for r, it in zip(ref0, items))
     del ref0
-    # timing
-    sequential()
+    log("cfg4 wave 0: batched == sequential bit for bit: %s" % identical)
+    # timing (each phase: one untimed pass, then --steps timed passes)
+    sequential(tag="sequential warm-up")
     torch.cuda.synchronize()
     ta = time.perf_counter()
     for _ in range(args.steps):
         sequential()
     torch.cuda.synchronize()
     ms_seq = (time.perf_counter() - ta) * 1e3 / args.steps
-    batched()
+    log("cfg4 sequential: %.1f ms per solve" % ms_seq)
+    batched(tag="batched warm-up")
     torch.cuda.synchronize()
     ta = time.perf_counter()
     for _ in range(args.steps):
@@ -635,6 +643,7 @@ def bench_cfg4(args):
     torch.cuda.synchronize()
     ms_bat = (time.perf_counter() - ta) * 1e3 / args.steps
     run_ms = [a.elapsed_time(b) for a, b in run_ev]
+    log("cfg4 batched: %.1f ms per solve" % ms_bat)
     side = torch.cuda.Stream()
     side.wait_stream(stream)
     with torch.cuda.stream(side):
@@ -642,14 +651,17 @@ def bench_cfg4(args):
             batched(st=side)
         g.replay()
         side.synchronize()
+        log("cfg4 graph captured and replayed once")
         ta = time.perf_counter()
         for _ in range(args.steps):
             g.replay()
-        side.synchronize()
+            side.synchronize()
+            log("cfg4 graph replay done")
         ms_graph = (time.perf_counter() - ta) * 1e3 / args.steps
     torch.cuda.synchronize()
+    log("cfg4 graph: %.1f ms per solve" % ms_graph)
     stats = torch.zeros(5, dtype=torch.int64, device=dev)
-    sequential(stats=stats)
+    sequential(stats=stats, tag="counting")
     torch.cuda.synchronize()
     seglam = int(stats[0].item()) * 8
     n2 = sum(1 for it in items if it["spec"]["dim"] == 2)

@@ -34,10 +34,10 @@ __device__ __forceinline__ int block_level(const uint64_t* sts, long long b, int
 
 // Fine cell (multiple of nvs inside [c0, c0 + vs)) containing x_a(t*) with
 // t* = d2s / (2 |w_s|); on a plane, the cell the ray moves into.
-__device__ __noinline__ int fine_cell(int p2a, double wa, double aws, int d2s, int c0, int vs, int nvs, int sta)
+__device__ __noinline__ int fine_cell(int p2a, double wa, double aws, double d2s, int c0, int vs, int nvs, int sta)
 {
-    const double rhs = (double)d2s * wa;  // exact
-    double xa = 0.5 * (double)p2a - ((double)d2s * 0.5 / aws) * wa;
+    const double rhs = d2s * wa;  // exact
+    double xa = 0.5 * (double)p2a - (d2s * 0.5 / aws) * wa;
     int j = ((int)floor(xa)) & ~(nvs - 1);
     if (j < c0) j = c0;
     if (j > c0 + vs - nvs) j = c0 + vs - nvs;
@@ -54,11 +54,11 @@ struct Counters {
 
 // Distance-graded cap at a block entered at t = d2 / (2 |w_s|): the largest m
 // with level_dist[1..m] <= t, decided exactly as d2/2 >= level_dist[m] |w_s|.
-__device__ __forceinline__ int graded_cap(const float* ld, int nlev, int d2, double aws)
+__device__ __forceinline__ int graded_cap(const float* ld, int nlev, double d2, double aws)
 {
     int cap = 0;
     for (int m = 1; m < nlev; ++m) {
-        if (!((double)d2 * 0.5 >= (double)ld[m] * aws)) break;
+        if (!(d2 * 0.5 >= (double)ld[m] * aws)) break;
         cap = m;
     }
     return cap;
@@ -76,7 +76,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
                                     Counters& cnt)
 {
     int p2[3], st[3], c[3], k[3], bc[3];
-    double aw[3], iw[3], ws[3];
+    double aw[3], iw[3], ws[3], dd[3];  // dd: |p2 - 2 k| (twice the distance to the next plane), exact
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         p2[a] = 1;
@@ -87,13 +87,14 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         aw[a] = 0.0;
         iw[a] = 0.0;
         ws[a] = 0.0;
+        dd[a] = 1.0;
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         p2[a] = 2 * pv[a] + 1;
         ws[a] = (double)wf[a];
         aw[a] = fabs(ws[a]);
-        iw[a] = aw[a] > 0.0 ? 1.0 / aw[a] : 0.0;
+        iw[a] = aw[a] > 0.0 ? 0.5 / aw[a] : 0.0;  // half the reciprocal: t = dd iw
         st[a] = wf[a] > 0.f ? -1 : (wf[a] < 0.f ? 1 : 0);
         bc[a] = pv[a] >> g.log2B;
     }
@@ -113,32 +114,44 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
     for (int a = 0; a < D; ++a) {
         c[a] = pv[a] & ~(vs - 1);
         k[a] = c[a] + (st[a] > 0 ? vs : 0);
+        dd[a] = (double)abs(p2[a] - 2 * k[a]);
     }
     double t = 0.0;
     for (int step = 0; step < step_cap; ++step) {
-        int s0 = -1, d2s0 = 0;
-        unsigned tie = 0;
+        int s0;
+        unsigned tie;
+        double tn;
+        if constexpr (D == 2) {
+            // axis a crosses first iff dd_a |w_b| < dd_b |w_a|; an axis with w_a = 0 has a zero
+            // product on the right and never wins, so no special case is needed
+            const double lhs = dd[0] * aw[1], rhs = dd[1] * aw[0];
+            const bool x0 = lhs <= rhs, x1 = rhs <= lhs;
+            tie = (x0 ? 1u : 0u) | (x1 ? 2u : 0u);
+            s0 = x0 ? 0 : 1;
+            tn = x0 ? dd[0] * iw[0] : dd[1] * iw[1];
+        } else {
+            s0 = -1;
+            tie = 0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            if (st[a] == 0) continue;
-            int d2 = abs(p2[a] - 2 * k[a]);
-            if (s0 < 0) {
-                s0 = a;
-                d2s0 = d2;
-                tie = 1u << a;
-            } else {
-                double lhs = (double)d2 * aw[s0];
-                double rhs = (double)d2s0 * aw[a];
-                if (lhs < rhs) {
+            for (int a = 0; a < D; ++a) {
+                if (st[a] == 0) continue;
+                if (s0 < 0) {
                     s0 = a;
-                    d2s0 = d2;
                     tie = 1u << a;
-                } else if (lhs == rhs) {
-                    tie |= 1u << a;
+                } else {
+                    double lhs = dd[a] * aw[s0];
+                    double rhs = dd[s0] * aw[a];
+                    if (lhs < rhs) {
+                        s0 = a;
+                        tie = 1u << a;
+                    } else if (lhs == rhs) {
+                        tie |= 1u << a;
+                    }
                 }
             }
+            tn = dd[s0] * iw[s0];
         }
-        const double tn = (double)d2s0 * 0.5 * iw[s0];
+        const double d2s0 = dd[s0];
         if (lvl >= 0) {
             if (vis.seg(c, lvl, blk, t, tn)) return 2;
             ++cnt.segs;
@@ -146,20 +159,19 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             ++cnt.empty;
         }
         t = tn;
-        int kc[3] = {0, 0, 0};
+        // advance the crossing axes (branch-free: the other axes add 0 and keep their block)
         bool out = false, bchg = false;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-            if (!((tie >> a) & 1u)) continue;
-            kc[a] = k[a];
-            c[a] += st[a] * vs;
-            k[a] += st[a] * vs;
-            if (c[a] < 0 || c[a] >= g.n[a]) out = true;
-            int nbc = c[a] >> g.log2B;
-            if (nbc != bc[a]) {
-                bchg = true;
-                bc[a] = nbc;
-            }
+            const bool sa = (tie >> a) & 1u;
+            const int sv = sa ? st[a] * vs : 0;
+            c[a] += sv;
+            k[a] += sv;
+            dd[a] += sa ? (double)(2 * vs) : 0.0;
+            out = out || (unsigned)c[a] >= (unsigned)g.n[a];
+            const int nbc = c[a] >> g.log2B;
+            bchg = bchg || nbc != bc[a];
+            bc[a] = nbc;
         }
         if (out) return 0;
         if (bchg) {
@@ -175,11 +187,13 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
                 int nvs = nl < 0 ? g.B : (1 << nl);
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    if ((tie >> a) & 1u) c[a] = (st[a] > 0 ? kc[a] : kc[a] - 1) & ~(nvs - 1);
+                    // a crossing axis re-locates from the plane just crossed, k - st vs
+                    if ((tie >> a) & 1u) c[a] = (st[a] > 0 ? k[a] - vs : k[a] + vs - 1) & ~(nvs - 1);
                     else if (st[a] == 0) c[a] = pv[a] & ~(nvs - 1);
                     else if (nvs >= vs) c[a] &= ~(nvs - 1);
                     else c[a] = fine_cell(p2[a], ws[a], aw[s0], d2s0, c[a], vs, nvs, st[a]);
                     k[a] = c[a] + (st[a] > 0 ? nvs : 0);
+                    dd[a] = (double)abs(p2[a] - 2 * k[a]);
                 }
                 lvl = nl;
                 vs = nvs;
@@ -211,7 +225,8 @@ __device__ __forceinline__ void rte_step(float& I, float& Tr, float eta, float c
     const float a = chi * k.dtl;
     const float e = __builtin_amdgcn_exp2f(-a);
     const float hs = fmaf(a, fmaf(a, k.q2, k.q1), k.dt);
-    const float hd = (1.0f - e) * __builtin_amdgcn_rcpf(chi);
+    const float r = __builtin_amdgcn_rcpf(chi);
+    const float hd = fmaf(-e, r, r);  // (1 - e) / chi in one rounding
     const float h = a < 0.045084220027780106f ? hs : hd;  // tau < 1/32
     I = fmaf(Tr * eta, h, I);
     Tr *= e;
