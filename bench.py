@@ -83,9 +83,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5"],
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "matrix"],
                     help="cfg2: 2D velocity interpolation (default, the headline line); cfg3: 3D Core and Voigt "
-                         "per storage dtype; cfg4: 48-scene batched vs sequential; cfg5: radiance cache on cfg3")
+                         "per storage dtype; cfg4: 48-scene batched vs sequential; cfg5: radiance cache on cfg3; "
+                         "matrix: the paper's method matrix on a prominence-like 2D scene")
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=21)
     ap.add_argument("--iod", type=float, default=1e-2)
@@ -124,6 +125,8 @@ def main():
         return bench_cfg4(args)
     if args.workload == "cfg5":
         return bench_cfg5(args)
+    if args.workload == "matrix":
+        return bench_matrix(args)
     return bench_cfg2(args)
 
 
@@ -278,6 +281,24 @@ def bench_cfg2(args):
                                           "ms_per_batch": (tb - ta) * 1e3 / nbc}
         vlm_ms_batch = ms_step / nb_lam
         cmp["speedup_vs_dense_classic"] = cmp["dense_classic"]["ms_per_batch"] / vlm_ms_batch
+        # angle-integrated output (mean intensity J + diagonal operator) instead of I per direction
+        jbuf = torch.empty((8, n_probes), dtype=torch.float32, device=dev)
+        pbuf = torch.empty_like(jbuf)
+        for b in range(nbc):
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
+            scene.trace_j(dirs, mode="vlm", level_dist=level_dist, J=jbuf, psi=pbuf)
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for b in range(nbc):
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
+            scene.trace_j(dirs, mode="vlm", level_dist=level_dist, J=jbuf, psi=pbuf)
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        cmp["vlm_j_output"] = {"ms_per_batch": (tb - ta) * 1e3 / nbc,
+                               "speedup_vs_i_output": vlm_ms_batch / ((tb - ta) * 1e3 / nbc),
+                               "note": "same march; J and psi [8][probes] instead of I [64 dirs][8][probes]"}
         if args.emission == "velinterp":
             # the accuracy-preserving setting: no merging, 81 velocity nodes (error filled in below)
             scene81 = rt.Scene.from_dict(sc, emission="velinterp", n_v=81)
@@ -843,6 +864,83 @@ def bench_cfg5(args):
                              kk_np.size, nb * 8, cpu_s)}}
     print(json.dumps(out_line), flush=True)
 
+
+# ----------------------------------------------------------------------------- method matrix
+def bench_matrix(args):
+    """{Dense, Sparse} x {Classic, VelInterp, CaV} x {-, Mips} on the prominence-like 2D scene (512 x 768,
+    16^2 bricks, ~58 % active, two Voigt lines, shear flow): time per full solve (16 wavelength batches),
+    updates applied, and error against the FP64 dense Classic oracle on the same sampled rays.  Classic is
+    the exact per-voxel line evaluation, which is what Core and Voigt computes at MIP 0, so Classic and CaV
+    at MIP 0 are one method here; dense methods trace the same (active-voxel) probes."""
+    np, torch, rt, dev = _env()
+    from synth import make_prominence
+    sc = make_prominence()
+    nb = sc["lam"].size // 8
+    if args.batches:
+        nb = min(nb, args.batches)
+    dirs = torch.from_numpy(sc["dirs"]).to(dev)
+    n_dir = dirs.shape[0]
+    level_dist = None if args.no_grading else [v * args.grade_scale for v in rt.CASCADE_LEVEL_DIST]
+    sparse_cav = rt.Scene.from_dict(sc, emission="cav")
+    probe_vox = sparse_cav.probe_voxels()
+    pv = torch.from_numpy(probe_vox).to(dev)
+    n_probes = probe_vox.size
+    rng = np.random.default_rng(77)
+    k = rng.choice(n_probes, min(args.pairs, n_probes), replace=False)
+    d = rng.integers(0, n_dir, k.size).astype(np.int32)
+    kk, dd = torch.from_numpy(k).long().to(dev), torch.from_numpy(d).long().to(dev)
+    scenes = {"dense_cav": rt.Scene.from_dict(sc, emission="cav", dense=True), "sparse_cav": sparse_cav,
+              "sparse_velinterp": rt.Scene.from_dict(sc, emission="velinterp", n_v=args.n_v)}
+    methods = [("DenseClassic", "dense_cav", "level0"), ("SparseClassic", "sparse_cav", "level0"),
+               ("SparseVelInterp", "sparse_velinterp", "level0"), ("DenseCavMips", "dense_cav", "vlm"),
+               ("SparseCavMips", "sparse_cav", "vlm"), ("SparseVelInterpMips", "sparse_velinterp", "vlm")]
+    out = torch.empty((n_dir, 8, n_probes), dtype=torch.float32, device=dev)
+    bkw = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin)
+    res = {}
+    for name, key, mode in methods:
+        scn = scenes[key]
+        probes = None if key.startswith("sparse") else pv
+
+        def solve(stats=None, gather=None):
+            for b in range(nb):
+                scn.build(8 * b, 8 * b + 8, **bkw)
+                scn.trace(dirs, probes=probes, mode=mode, level_dist=level_dist if mode == "vlm" else None, out=out,
+                          stats=stats)
+                if gather is not None:
+                    gather[:, 8 * b:8 * b + 8] = out[dd, :, kk]
+
+        solve()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for _ in range(args.steps):
+            solve()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - ta) * 1e3 / args.steps
+        stats = torch.zeros(5, dtype=torch.int64, device=dev)
+        got = torch.empty((k.size, nb * 8), dtype=torch.float32, device=dev)
+        solve(stats=stats, gather=got)
+        torch.cuda.synchronize()
+        res[name] = {"ms_per_solve": ms, "seg_lam_per_solve": int(stats[0].item()) * 8, "got": got.cpu().numpy()}
+        log("matrix %-20s %.1f ms per solve" % (name, ms))
+    nthreads = min(os.cpu_count() or 1, 16)
+    ref, cpu_seglam, cpu_s = _oracle_classic(sc, probe_vox, k, d, list(range(nb * 8)), nthreads)
+    base = res["DenseClassic"]["ms_per_solve"]
+    table = {}
+    for name, r in res.items():
+        table[name] = {"ms_per_solve": r["ms_per_solve"], "speedup_vs_dense_classic": base / r["ms_per_solve"],
+                       "raw_gseg_s": r["seg_lam_per_solve"] / (r["ms_per_solve"] / 1e3) / 1e9,
+                       "error_vs_fp64_classic": _err(r["got"], ref)}
+    line = {"workload": "matrix", "config": {
+        "workload": "2D 512 x 768 prominence-like sheet, 16^2 bricks, %d of %d active, 2 Voigt lines + grey "
+                    "continuum, shear flow |v| <= 30 km/s, %d directions, %d lambda (%d batches), VLM T=%g, %s; "
+                    "velocity interpolation n_v=%d; all %d active-voxel probes" % (
+                        int(sc["block_active"].sum()), sc["block_active"].size, n_dir, nb * 8, nb, args.iod,
+                        "plain VLM" if args.no_grading else "cascade-graded levels", args.n_v, n_probes)},
+        "methods": table,
+        "cpu_baseline": {"value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
+                         "kind": "oracle", "sample": "%d pairs x %d wavelengths, FP64 dense Classic, %.1f s" % (
+                             k.size, nb * 8, cpu_s)}}
+    print(json.dumps(line), flush=True)
 
 if __name__ == "__main__":
     main()

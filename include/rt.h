@@ -334,7 +334,10 @@ typedef struct rt_batch_job {
  *   wgs_per_cu     resident workgroups per compute unit (default 2);
  *   tiles_per_pop  64-probe tiles claimed per atomic pop (default 1);
  *   order          0 (default): costliest job first (cost ~ n_dir x n_probes x
- *                  sum of grid sides); 1: the given job order;
+ *                  sum of grid sides); 1: the given job order.  Either way 2D jobs
+ *                  come before 3D jobs: each dimension present gets one persistent
+ *                  launch of its own (compiled for that dimension and, when all its
+ *                  jobs share it, that storage dtype), both launches on `stream`;
  *   d_claims       optional device uint32 [total tiles], incremented once per
  *                  processed tile (lets tests check that every tile is taken
  *                  exactly once).
@@ -352,7 +355,7 @@ typedef struct rt_batch rt_batch;
 /* Validates the jobs, uploads the job table (synchronises `stream`) and sizes
  * the queue.  The scenes must have a built batch; their storage is read at
  * every rt_batch_run, so rebuilding a scene for another batch of the same
- * size is picked up by the next run.  Errors: RT_E_ARG, RT_E_STATE, RT_E_UNSUPPORTED
+ * size and storage dtype is picked up by the next run.  Errors: RT_E_ARG, RT_E_STATE, RT_E_UNSUPPORTED
  * (non-static emission), RT_E_HIP. */
 rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_batch_params* params, void* stream,
                           rt_batch** out);
@@ -387,6 +390,27 @@ rt_status rt_graph_begin(void* stream);
 rt_status rt_graph_end(void* stream, rt_graph** out);
 rt_status rt_graph_launch(const rt_graph* graph, void* stream);
 void rt_graph_destroy(rt_graph* graph);
+
+/*
+ * rt_trace_j -- angle-integrated formal solution for the current wavelength
+ * batch: the mean intensity J[l][p] = sum_d w_d I_d[l][p] over the n_dir
+ * directions with quadrature weights d_weights [n_dir] (device float, e.g.
+ * 1/n_dir), and optionally psi[l][p] = sum_d w_d (1 - exp(-tau_1,d)) with
+ * tau_1,d the optical depth of the first segment (the probe's own cell to its
+ * boundary), the diagonal of the approximate operator used by accelerated
+ * lambda iteration.  The march is rt_trace's (same params, same cells); I is
+ * never written.  Directions are split into chunks marched by separate waves;
+ * with d_work (device, work_bytes, nullable) the chunk partials are summed in a
+ * fixed order (deterministic), without it every wave takes all directions.
+ * rt_trace_j_workspace_bytes gives the work size for full parallelism (0 when
+ * one chunk already fills the device).  d_J, d_psi: [batch][n_probes].
+ * Errors as rt_trace.  Asynchronous; allocates nothing.
+ */
+rt_status rt_trace_j(const rt_scene* scene, const rt_trace_params* params, const float* d_dirs,
+                     const float* d_weights, int32_t n_dir, const int32_t* d_probes, int64_t n_probes, float* d_J,
+                     float* d_psi, float* d_work, size_t work_bytes, void* stream);
+rt_status rt_trace_j_workspace_bytes(const rt_scene* scene, int32_t n_dir, int64_t n_probes, int32_t with_psi,
+                                     size_t* h_bytes);
 
 /*
  * ------------------------------------------------- neural radiance cache

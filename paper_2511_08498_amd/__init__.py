@@ -35,6 +35,7 @@ EXPORTS = (
     "rt_graph_destroy", "rt_trace_truncated", "rt_nrc_num_params", "rt_nrc_create", "rt_nrc_destroy",
     "rt_nrc_get_weights", "rt_nrc_set_weights", "rt_nrc_pack", "rt_nrc_train", "rt_nrc_loss", "rt_nrc_gradients",
     "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate", "rt_scene_workspace_bytes", "rt_nrc_workspace_bytes",
+    "rt_trace_j", "rt_trace_j_workspace_bytes",
 )
 _VOID = ("rt_scene_destroy", "rt_last_error", "rt_version", "rt_batch_destroy", "rt_graph_destroy", "rt_nrc_destroy")
 
@@ -140,6 +141,8 @@ def lib():
     L.rt_graph_destroy.restype = None
     L.rt_trace_truncated.argtypes = [_P, _P, ctypes.c_float, i32, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P, _P]
     L.rt_scene_workspace_bytes.argtypes = [_P, i64, ctypes.POINTER(ctypes.c_size_t)]
+    L.rt_trace_j.argtypes = [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, ctypes.c_size_t, _P]
+    L.rt_trace_j_workspace_bytes.argtypes = [_P, i32, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.rt_nrc_workspace_bytes.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
     L.rt_nrc_num_params.argtypes = [_P]
     L.rt_nrc_create.argtypes = [_P, _P, ctypes.POINTER(_P)]
@@ -377,6 +380,45 @@ class Scene:
                                         out["fstat"].data_ptr(), _stream(stream)))
         out["dirs"], out["n_probes"], out["probes"] = td, n_probes, tp
         return out
+
+    def trace_j(self, dirs, weights=None, probes=None, mode="vlm", I0=0.0, max_level=-1, step_cap=0,
+                level_dist=None, with_psi=True, chunked=True, J=None, psi=None, stream=None):
+        """Angle-integrated trace (rt_trace_j): J[batch][n_probes] = sum_d w_d I_d and, with_psi,
+        psi = sum_d w_d (1 - exp(-tau of the first segment)).  weights default to 1/n_dir."""
+        torch = self.torch
+        td = dirs if isinstance(dirs, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(dirs, np.float32))
+        td = td.to(device=self.device, dtype=torch.float32).contiguous()
+        nd = int(td.shape[0])
+        if weights is None:
+            tw = torch.full((nd,), 1.0 / nd, dtype=torch.float32, device=self.device)
+        else:
+            tw = weights if isinstance(weights, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(weights, np.float32))
+            tw = tw.to(device=self.device, dtype=torch.float32).contiguous()
+        if probes is None:
+            n_probes, tp = self.info["n_probes"], None
+        else:
+            tp = probes if isinstance(probes, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(probes, np.int32))
+            tp = tp.to(device=self.device, dtype=torch.int32).contiguous()
+            n_probes = tp.numel()
+        nl = self.batch[1] - self.batch[0]
+        if J is None:
+            J = torch.empty((nl, n_probes), dtype=torch.float32, device=self.device)
+        if with_psi and psi is None:
+            psi = torch.empty((nl, n_probes), dtype=torch.float32, device=self.device)
+        work, wb = None, 0
+        if chunked:
+            v = ctypes.c_size_t(0)
+            _check(lib().rt_trace_j_workspace_bytes(self.h, nd, int(n_probes), 1 if with_psi else 0, ctypes.byref(v)))
+            wb = v.value
+            if wb:
+                work = torch.empty(wb // 4, dtype=torch.float32, device=self.device)
+        p = self._tparams(mode, max_level, I0, step_cap, None, level_dist)
+        _check(lib().rt_trace_j(self.h, ctypes.byref(p), td.data_ptr(), tw.data_ptr(), nd,
+                                tp.data_ptr() if tp is not None else None, int(n_probes), J.data_ptr(),
+                                psi.data_ptr() if with_psi else None, work.data_ptr() if work is not None else None,
+                                int(wb), _stream(stream)))
+        self._last_j = (td, tw, tp, work)
+        return J, (psi if with_psi else None)
 
     def active_blocks(self):
         out = np.zeros(self.info["n_active"], np.int32)

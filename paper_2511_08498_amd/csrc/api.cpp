@@ -408,6 +408,86 @@ rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_
     return RT_OK;
 }
 
+}  // extern "C"
+
+// Direction chunks of an angle-integrated trace: ~2^18 waves, as many as a
+// per-direction trace of a mid-size scene launches (latency hiding needs them),
+// never more chunks than directions.
+static long long j_target_chunks(int n_dir, long long n_probes)
+{
+    const long long tiles = (n_probes + 63) / 64;
+    long long c = ((1ll << 18) + tiles - 1) / tiles;
+    if (c < 1) c = 1;
+    if (c > n_dir) c = n_dir;
+    return c;
+}
+
+extern "C" {
+
+rt_status rt_trace_j_workspace_bytes(const rt_scene* sc, int32_t n_dir, int64_t n_probes, int32_t with_psi,
+                                     size_t* h_bytes)
+{
+    g_err.clear();
+    if (!sc || !h_bytes) return fail(RT_E_ARG, "null argument");
+    if (n_dir < 1 || n_probes < 0) return fail(RT_E_ARG, "n_dir must be >= 1 and n_probes >= 0");
+    const long long c = j_target_chunks(n_dir, n_probes);
+    *h_bytes = c <= 1 ? 0 : (size_t)c * kLam * (size_t)n_probes * sizeof(float) * (with_psi ? 2 : 1);
+    return RT_OK;
+}
+
+rt_status rt_trace_j(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, const float* d_weights,
+                     int32_t n_dir, const int32_t* d_probes, int64_t n_probes, float* d_J, float* d_psi, float* d_work,
+                     size_t work_bytes, void* stream)
+{
+    g_err.clear();
+    if (!sc || !p || !d_dirs || !d_weights || !d_J) return fail(RT_E_ARG, "null argument");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace_j before rt_scene_build");
+    if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
+    if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
+    for (int m = 1; m < RT_MAX_LEVELS; ++m)
+        if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
+    const long long all = (long long)sc->n_active * sc->g.bvox;
+    if (!d_probes && n_probes != all)
+        return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
+    if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
+    if (n_probes == 0) return RT_OK;
+    const int nl = sc->batch_end - sc->batch_begin;
+    const long long per_chunk = (long long)nl * n_probes * (d_psi ? 2 : 1);
+    long long chunks = j_target_chunks(n_dir, n_probes);
+    if (d_work) {
+        const long long fit = (long long)(work_bytes / sizeof(float)) / per_chunk;
+        if (chunks > fit) chunks = fit;
+    } else {
+        chunks = 1;
+    }
+    if (chunks < 1) chunks = 1;
+    const int dpc = (int)((n_dir + chunks - 1) / chunks);
+    chunks = (n_dir + dpc - 1) / dpc;
+    if (((n_probes + 63) / 64) * chunks > (long long)0x7fffffff * 4) return fail(RT_E_ARG, "launch too large");
+    TraceLaunch t = make_trace(sc, p);
+    t.dirs = d_dirs;
+    t.n_dir = n_dir;
+    t.probes = d_probes;
+    t.n_probes = n_probes;
+    t.jmode = 1;
+    t.dirs_per_chunk = dpc;
+    t.weights = d_weights;
+    hipStream_t s = (hipStream_t)stream;
+    if (chunks == 1) {
+        t.part_J = d_J;
+        t.part_psi = d_psi;
+        RT_HIP(launch_trace(t, s));
+        return RT_OK;
+    }
+    const long long n = (long long)nl * n_probes;
+    t.part_J = d_work;
+    t.part_psi = d_psi ? d_work + chunks * n : nullptr;
+    RT_HIP(launch_trace(t, s));
+    RT_HIP(launch_reduce_chunks(t.part_J, (int)chunks, n, d_J, s));
+    if (d_psi) RT_HIP(launch_reduce_chunks(t.part_psi, (int)chunks, n, d_psi, s));
+    return RT_OK;
+}
+
 rt_status rt_trace_truncated(const rt_scene* sc, const rt_trace_params* p, float t_trunc, int32_t gen,
                              const uint8_t* d_fallback, const float* d_dirs, int32_t n_dir, const int32_t* d_probes,
                              int64_t n_probes, float* d_I_near, float* d_T_near, float* d_I_far, float* d_feat,
@@ -577,6 +657,7 @@ struct rt_batch {
     unsigned* claims = nullptr;
     unsigned total_tiles = 0;
     int wg_waves = 4, n_wgs = 0, tiles_per_pop = 1;
+    std::vector<BatchSeg> segs;  // one persistent launch per dimension present
     ~rt_batch()
     {
         if (d_jobs) (void)hipFree(d_jobs);
@@ -653,8 +734,11 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
     }
     std::vector<int> order((size_t)n_jobs);
     for (int j = 0; j < n_jobs; ++j) order[(size_t)j] = j;
-    if (bp.order == 0)
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[(size_t)a] > cost[(size_t)b]; });
+    // 2D jobs first, then 3D (one launch each); within a dimension costliest first unless order = 1
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (bj[(size_t)a].g.dim != bj[(size_t)b].g.dim) return bj[(size_t)a].g.dim < bj[(size_t)b].g.dim;
+        return bp.order == 0 && cost[(size_t)a] > cost[(size_t)b];
+    });
     rt_batch* bt = new (std::nothrow) rt_batch();
     if (!bt) return fail(RT_E_ARG, "out of host memory");
     unsigned long long tile = 0;
@@ -669,6 +753,15 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
         return fail(RT_E_ARG, "too many tiles in one batch (%llu)", tile);
     }
     bt->total_tiles = (unsigned)tile;
+    for (int j = 0; j < (int)bt->jobs.size(); ++j) {
+        const BatchJob& b = bt->jobs[(size_t)j];
+        if (bt->segs.empty() || bt->segs.back().dim != b.g.dim)
+            bt->segs.push_back(BatchSeg{b.g.dim, b.storage, j, j, b.tile0, b.tile0});
+        BatchSeg& g = bt->segs.back();
+        if (g.storage != b.storage) g.storage = -1;
+        g.j1 = j + 1;
+        g.tile_end = b.tile0 + (unsigned)b.tiles * (unsigned)b.n_dir;
+    }
     bt->wg_waves = wg_waves;
     bt->tiles_per_pop = tpp;
     bt->n_wgs = device_cus() * wgs_per_cu;
@@ -693,7 +786,7 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
 rt_status rt_batch_run(const rt_batch* bt, void* stream)
 {
     if (!bt) return fail(RT_E_ARG, "null batch");
-    RT_HIP(launch_batched(bt->d_jobs, (int)bt->jobs.size(), bt->total_tiles, bt->wg_waves, bt->n_wgs,
+    RT_HIP(launch_batched(bt->d_jobs, bt->segs.data(), (int)bt->segs.size(), bt->wg_waves, bt->n_wgs,
                           bt->tiles_per_pop, bt->counter, bt->claims, bt->err, (hipStream_t)stream));
     return RT_OK;
 }

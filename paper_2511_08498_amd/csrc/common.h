@@ -168,8 +168,15 @@ struct TraceLaunch {
     float* I_far;
     float4* feat;              // [n_dir][n_probes]
     float4* fstat_out;         // [n_dir][nl][n_probes]
+    // angle-integrated output (mean intensity J and the diagonal operator)
+    int jmode;
+    int dirs_per_chunk;
+    const float* weights;      // [n_dir] quadrature weights
+    float* part_J;             // [n_chunks][nl][n_probes]
+    float* part_psi;           // [n_chunks][nl][n_probes], nullable
 };
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s);
+hipError_t launch_reduce_chunks(const float* part, int n_chunks, long long n, float* out, hipStream_t s);
 
 // One job of the batched persistent trace (static emission).
 struct BatchJob {
@@ -194,7 +201,14 @@ struct BatchJob {
     float ds0;
     float level_dist[kMaxLevels];
 };
-hipError_t launch_batched(const BatchJob* d_jobs, int n_jobs, unsigned total_tiles, int wg_waves, int n_wgs,
+// A run of jobs of one dimension: one persistent launch each (at most 2: 2D, 3D).
+struct BatchSeg {
+    int dim;
+    int storage;        // dtype shared by the segment's jobs, -1 for a mix
+    int j0, j1;         // jobs [j0, j1)
+    unsigned tile_begin, tile_end;
+};
+hipError_t launch_batched(const BatchJob* d_jobs, const BatchSeg* segs, int n_segs, int wg_waves, int n_wgs,
                           int tiles_per_pop, unsigned* counter, unsigned* claims, unsigned long long* err,
                           hipStream_t s);
 hipError_t launch_debug_visited(const TraceLaunch& t, int probe_vox, float wx, float wy, float wz, int cap,

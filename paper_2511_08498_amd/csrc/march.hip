@@ -220,7 +220,8 @@ struct SegK {
     }
 };
 
-__device__ __forceinline__ void rte_step(float& I, float& Tr, float eta, float chi, const SegK& k)
+// returns the segment's transmission exp(-tau)
+__device__ __forceinline__ float rte_step(float& I, float& Tr, float eta, float chi, const SegK& k)
 {
     const float a = chi * k.dtl;
     const float e = __builtin_amdgcn_exp2f(-a);
@@ -230,6 +231,7 @@ __device__ __forceinline__ void rte_step(float& I, float& Tr, float eta, float c
     const float h = a < 0.045084220027780106f ? hs : hd;  // tau < 1/32
     I = fmaf(Tr * eta, h, I);
     Tr *= e;
+    return e;
 }
 
 template <typename T>
@@ -325,6 +327,7 @@ __device__ __forceinline__ float4 load4<__half>(const __half* r, int i)
 // Plain: the whole ray, front to back.
 struct AccPlain {
     static constexpr bool kTrunc = false;
+    static constexpr bool kJ = false;
     float I[kLam], Tr[kLam];
     __device__ void init(const TraceLaunch*)
     {
@@ -354,6 +357,7 @@ struct AccPlain {
 template <bool Gen>
 struct AccTrunc {
     static constexpr bool kTrunc = true;
+    static constexpr bool kJ = false;
     static constexpr bool kGen = Gen;  // generation mode: also accumulate the far field
     float In[kLam], Tn[kLam];
     float If[Gen ? kLam : 1], Tf[Gen ? kLam : 1];
@@ -434,6 +438,38 @@ struct AccTrunc {
             far(e, x, tstar, t1, dsf);
             return false;
         }
+    }
+};
+
+// Angle integration: the plain march, plus 1 - exp(-tau) of the first segment
+// (the probe's own cell up to its boundary), whose weighted sum over directions
+// is the diagonal of the approximate operator.
+struct AccJ {
+    static constexpr bool kTrunc = false;
+    static constexpr bool kJ = true;
+    float I[kLam], Tr[kLam], psi[kLam];
+    int first;
+    __device__ void init(const TraceLaunch*)
+    {
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            I[l] = 0.f;
+            Tr[l] = 1.f;
+            psi[l] = 0.f;
+        }
+        first = 1;
+    }
+    __device__ __forceinline__ bool add(const float* e, const float* x, const int*, int, long long, double t0,
+                                        double t1, float dsf)
+    {
+        const SegK k((float)(t1 - t0) * dsf);
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            const float tr = rte_step(I[l], Tr[l], e[l], x[l], k);
+            if (first) psi[l] = 1.0f - tr;
+        }
+        first = 0;
+        return false;
     }
 };
 
@@ -722,15 +758,113 @@ __global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
     }
 }
 
+// Angle-integrated trace: a wave takes 64 probes and a chunk of directions,
+// marches them one direction after another (the direction stays uniform across
+// the wave) and accumulates J = sum_d w_d I_d and psi = sum_d w_d (1 - exp(-tau_1,d))
+// in registers; one partial per chunk is written (the caller's chunks are summed
+// in a fixed order afterwards).
+template <int D, class Vis>
+__global__ void __launch_bounds__(256) k_trace_j(TraceLaunch t)
+{
+    extern __shared__ uint64_t sts[];
+    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
+    __syncthreads();
+    const unsigned G = gridDim.x, wg = blockIdx.x;
+    const unsigned q = G / 8u, r = G % 8u, xcd = wg % 8u, i = wg / 8u;
+    const unsigned lwg = xcd < r ? xcd * (q + 1u) + i : r * (q + 1u) + (xcd - r) * q + i;
+    const long long tiles = (t.n_probes + 63) / 64;
+    const long long wave = (long long)lwg * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const long long chunk = wave / tiles;
+    const long long probe = (wave - chunk * tiles) * 64 + lane;
+    const long long d0 = chunk * t.dirs_per_chunk;
+    if (d0 >= t.n_dir) return;  // whole wave
+    const long long d1 = d0 + t.dirs_per_chunk < t.n_dir ? d0 + t.dirs_per_chunk : t.n_dir;
+    const bool live = probe < t.n_probes;
+    int pv[3] = {0, 0, 0};
+    if (live) {
+        if (t.probes) {
+            long long v = t.probes[probe];
+            pv[0] = (int)(v % t.g.n[0]);
+            pv[1] = (int)((v / t.g.n[0]) % t.g.n[1]);
+            pv[2] = (int)(v / ((long long)t.g.n[0] * t.g.n[1]));
+        } else {
+            long long slot = probe >> (D * t.g.log2B);
+            int local = (int)(probe & (t.g.bvox - 1));
+            int blk = t.active_list[slot];
+            int bcx = blk % t.g.nb[0], bcy = (blk / t.g.nb[0]) % t.g.nb[1], bcz = blk / (t.g.nb[0] * t.g.nb[1]);
+            pv[0] = bcx * t.g.B + (local & (t.g.B - 1));
+            pv[1] = bcy * t.g.B + ((local >> t.g.log2B) & (t.g.B - 1));
+            if (D > 2) pv[2] = bcz * t.g.B + (local >> (2 * t.g.log2B));
+        }
+    }
+    float J[kLam], P[kLam];
+#pragma unroll
+    for (int l = 0; l < kLam; ++l) J[l] = P[l] = 0.f;
+    for (long long dir = d0; dir < d1; ++dir) {
+        if (!live) continue;
+        float wf[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < D; ++a) wf[a] = t.dirs[dir * D + a];
+        Vis vis;
+        vis.init(&t, wf);
+        Counters cnt = {0, 0, 0};
+        const int rc = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+        if (rc == 1) {
+            atomicAdd(&t.err[0], 1ull);
+            atomicMin(&t.err[1], (unsigned long long)(dir * t.n_probes + probe));
+        }
+        const float w = t.weights[dir];
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            J[l] = fmaf(w, fmaf(vis.acc.Tr[l], t.I0, vis.acc.I[l]), J[l]);
+            P[l] = fmaf(w, vis.acc.psi[l], P[l]);
+        }
+    }
+    if (!live) return;
+    const int nl = t.lb.nl;
+#pragma unroll
+    for (int l = 0; l < kLam; ++l) {
+        if (l >= nl) continue;
+        const long long o = (chunk * nl + l) * t.n_probes + probe;
+        t.part_J[o] = J[l];
+        if (t.part_psi) t.part_psi[o] = P[l];
+    }
+}
+
+// out[i] = sum over chunks c (in order) of part[c n + i]
+__global__ void k_reduce_chunks(const float* part, int n_chunks, long long n, float* out)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int c = 0; c < n_chunks; ++c) s += part[(long long)c * n + i];
+    out[i] = s;
+}
+
+hipError_t launch_reduce_chunks(const float* part, int n_chunks, long long n, float* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, part, n_chunks, n, out);
+    return hipGetLastError();
+}
+
 template <int D, class Vis>
 static hipError_t launch_one(const TraceLaunch& t, hipStream_t s)
 {
     long long tiles = (t.n_probes + 63) / 64;
-    long long waves = tiles * t.n_dir;
-    long long wgs = (waves + 3) / 4;
-    if (wgs <= 0) return hipSuccess;
     size_t shm = sizeof(uint64_t) * (size_t)t.g.n_state_words;
-    hipLaunchKernelGGL((k_trace<D, Vis>), dim3((unsigned)wgs), dim3(256), shm, s, t);
+    if constexpr (Vis::AccT::kJ) {
+        const long long n_chunks = (t.n_dir + t.dirs_per_chunk - 1) / t.dirs_per_chunk;
+        const long long wgs = (tiles * n_chunks + 3) / 4;
+        if (wgs <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_trace_j<D, Vis>), dim3((unsigned)wgs), dim3(256), shm, s, t);
+    } else {
+        long long waves = tiles * t.n_dir;
+        long long wgs = (waves + 3) / 4;
+        if (wgs <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_trace<D, Vis>), dim3((unsigned)wgs), dim3(256), shm, s, t);
+    }
     return hipGetLastError();
 }
 
@@ -763,6 +897,7 @@ static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
 
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)
 {
+    if (t.jmode) return launch_trace_acc<AccJ>(t, s);
     if (t.trunc) return t.gen ? launch_trace_acc<AccTrunc<true>>(t, s) : launch_trace_acc<AccTrunc<false>>(t, s);
     return launch_trace_acc<AccPlain>(t, s);
 }
@@ -850,51 +985,96 @@ __device__ __forceinline__ void batched_ray(const BatchJob& J, long long dir, lo
     }
 }
 
-__global__ void k_reset_queue(unsigned* counter) { *counter = 0u; }
+// Queue counters of the launch segments start at their first tile.
+__global__ void k_reset_queue(unsigned* counter, unsigned t0, unsigned t1)
+{
+    counter[0] = t0;
+    counter[1] = t1;
+}
 
-__global__ void __launch_bounds__(512) k_batched(const BatchJob* __restrict__ jobs, int n_jobs, unsigned total_tiles, int tiles_per_pop,
-                          unsigned* counter, unsigned* claims, unsigned long long* err)
+// Tiles of one job of the queue: binary search over the jobs' first tiles
+// (uniform across the wave).
+__device__ __forceinline__ int job_of_tile(const BatchJob* __restrict__ jobs, int j0, int j1, unsigned tile)
+{
+    int lo = j0, hi = j1 - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile0 <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One persistent launch over the jobs [j0, j1) of one dimension, whose tiles are
+// [tile_begin, tile_end).  AnyT: the storage dtype is dispatched per job (a mix);
+// otherwise every job stores T.
+template <int D, typename T, bool AnyT>
+__global__ void __launch_bounds__(512) k_batched(const BatchJob* __restrict__ jobs, int j0, int j1, unsigned tile_end,
+                                                 int tiles_per_pop, unsigned* counter, unsigned* claims,
+                                                 unsigned long long* err)
 {
     const int lane = threadIdx.x & 63;
     for (;;) {
         unsigned base = 0;
         if (lane == 0) base = atomicAdd(counter, (unsigned)tiles_per_pop);
-        base = __shfl(base, 0, 64);
-        if (base >= total_tiles) break;
+        // wave-uniform from here: the job lookup and its fields stay in scalar registers
+        base = (unsigned)__builtin_amdgcn_readfirstlane((int)base);
+        if (base >= tile_end) break;
         for (int q = 0; q < tiles_per_pop; ++q) {
             const unsigned tile = base + (unsigned)q;
-            if (tile >= total_tiles) break;
-            int j = 0;
-            while (j + 1 < n_jobs && jobs[j + 1].tile0 <= tile) ++j;
-            const BatchJob& J = jobs[j];
+            if (tile >= tile_end) break;
+            const BatchJob& J = jobs[job_of_tile(jobs, j0, j1, tile)];
             const long long lt = (long long)(tile - J.tile0);
             const long long dir = lt / J.tiles;
             const long long probe = (lt - dir * J.tiles) * 64 + lane;
             if (claims && lane == 0) atomicAdd(&claims[tile], 1u);
             if (probe >= J.n_probes) continue;
-            if (J.g.dim == 2) {
-                if (J.storage == RT_F32) batched_ray<2, float>(J, dir, probe, err);
-                else if (J.storage == RT_BF16) batched_ray<2, __hip_bfloat16>(J, dir, probe, err);
-                else batched_ray<2, __half>(J, dir, probe, err);
+            if constexpr (!AnyT) {
+                batched_ray<D, T>(J, dir, probe, err);
             } else {
-                if (J.storage == RT_F32) batched_ray<3, float>(J, dir, probe, err);
-                else if (J.storage == RT_BF16) batched_ray<3, __hip_bfloat16>(J, dir, probe, err);
-                else batched_ray<3, __half>(J, dir, probe, err);
+                if (J.storage == RT_F32) batched_ray<D, float>(J, dir, probe, err);
+                else if (J.storage == RT_BF16) batched_ray<D, __hip_bfloat16>(J, dir, probe, err);
+                else batched_ray<D, __half>(J, dir, probe, err);
             }
         }
     }
 }
 
-hipError_t launch_batched(const BatchJob* d_jobs, int n_jobs, unsigned total_tiles, int wg_waves, int n_wgs,
+template <int D>
+static void launch_batched_dim(const BatchSeg& g, const BatchJob* d_jobs, int wg_waves, int n_wgs, int tiles_per_pop,
+                               unsigned* counter, unsigned* claims, unsigned long long* err, hipStream_t s)
+{
+    const dim3 grid((unsigned)n_wgs), block((unsigned)(64 * wg_waves));
+    if (g.storage == RT_F32)
+        hipLaunchKernelGGL((k_batched<D, float, false>), grid, block, 0, s, d_jobs, g.j0, g.j1, g.tile_end,
+                           tiles_per_pop, counter, claims, err);
+    else if (g.storage == RT_BF16)
+        hipLaunchKernelGGL((k_batched<D, __hip_bfloat16, false>), grid, block, 0, s, d_jobs, g.j0, g.j1, g.tile_end,
+                           tiles_per_pop, counter, claims, err);
+    else if (g.storage == RT_F16)
+        hipLaunchKernelGGL((k_batched<D, __half, false>), grid, block, 0, s, d_jobs, g.j0, g.j1, g.tile_end,
+                           tiles_per_pop, counter, claims, err);
+    else
+        hipLaunchKernelGGL((k_batched<D, float, true>), grid, block, 0, s, d_jobs, g.j0, g.j1, g.tile_end,
+                           tiles_per_pop, counter, claims, err);
+}
+
+hipError_t launch_batched(const BatchJob* d_jobs, const BatchSeg* segs, int n_segs, int wg_waves, int n_wgs,
                           int tiles_per_pop, unsigned* counter, unsigned* claims, unsigned long long* err,
                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL(k_reset_queue, dim3(1), dim3(1), 0, s, counter, n_segs > 0 ? segs[0].tile_begin : 0u,
+                       n_segs > 1 ? segs[1].tile_begin : 0u);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_batched, dim3((unsigned)n_wgs), dim3((unsigned)(64 * wg_waves)), 0, s, d_jobs, n_jobs,
-                       total_tiles, tiles_per_pop, counter, claims, err);
-    return hipGetLastError();
+    for (int i = 0; i < n_segs; ++i) {
+        if (segs[i].dim == 2)
+            launch_batched_dim<2>(segs[i], d_jobs, wg_waves, n_wgs, tiles_per_pop, counter + i, claims, err, s);
+        else
+            launch_batched_dim<3>(segs[i], d_jobs, wg_waves, n_wgs, tiles_per_pop, counter + i, claims, err, s);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace rt

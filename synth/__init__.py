@@ -14,6 +14,7 @@ from .scenes import (  # noqa: F401
     make_cfg2,
     make_cfg3,
     make_cfg4_scene,
+    make_prominence,
     cfg4_specs,
     sample_pairs,
     probe_voxels,

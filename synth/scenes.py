@@ -255,6 +255,65 @@ def make_cfg2(seed: int = 2, n: int = 1024, B: int = 16, active_frac: float = 0.
     )
 
 
+def make_prominence(seed: int = 6, nx: int = 512, ny: int = 768, B: int = 16, n_lam_per_line: int = 64,
+                    n_dir: int = 16, half_width: float = 128.0):
+    """2D prominence-like scene for the method matrix: a cool dense sheet (x within
+    256 +- half_width, its edges displaced by a Kelvin-Helmholtz-like wave of
+    amplitude 24 and wavelength 128 plus a GRF(0, 8, 16) wobble) in a hot corona
+    treated as empty (bricks without sheet material have eta = chi = 0, about half
+    of them).  Inside: density exp(GRF(0, 0.7, 12)), T = 0.5 + 0.5 Phi(GRF(l=24));
+    a thin transition layer (4 voxels) at T = 1.5 and density 0.05.  Two Voigt lines
+    (500.0, 500.2 nm; centre opacity 20 n and 1 n per voxel at the reference
+    Doppler width 8 km/s; v_D = 8 sqrt(T); damping 10^(-3 + 2 Phi(g))), grey
+    continuum 1e-3 n.  Velocity: shear flow v_y = +-20 km/s across the sheet's
+    centre line plus a vortical GRF perturbation, rescaled to max |v| = 30 km/s.
+    """
+    dim = 2
+    shp = (ny, nx)
+    ss = np.random.SeedSequence(seed)
+    rs = [np.random.default_rng(s) for s in ss.spawn(8)]
+    yy, xx = np.meshgrid(np.arange(ny) + 0.5, np.arange(nx) + 0.5, indexing="ij")
+    wob = 8.0 * grf(rs[0], (ny,), 16.0)
+    phase = rs[1].uniform(0, 2 * np.pi)
+    edge = half_width + 24.0 * np.sin(2 * np.pi * yy[:, :1] / 128.0 + phase) + wob[:, None]
+    dist = np.abs(xx - nx / 2.0) - edge  # < 0 inside the sheet
+    inside = dist < 0
+    layer = (dist >= 0) & (dist < 4)
+    dens = np.where(inside, np.exp(0.7 * grf(rs[2], shp, 12.0)), np.where(layer, 0.05, 0.0))
+    T = np.where(inside, 0.5 + 0.5 * ndtr(grf(rs[3], shp, 24.0)), 1.5)
+    nbx, nby = nx // B, ny // B
+    occ = (dens > 0).reshape(nby, B, nbx, B).any(axis=(1, 3))
+    block_active = occ.reshape(-1).astype(np.uint8)  # (by, bx) C order -> bx fastest
+    bmask = _mask_from_blocks((nx, ny, 1), dim, B, block_active)
+    dens = np.where(bmask & (dens <= 0), 1e-4, dens)
+    T = np.where(bmask, T, 1.5)
+    S = np.where(bmask, np.exp(-1.0 / T), 0.0)
+    vy = 20.0 * np.tanh((xx - nx / 2.0) / 16.0)
+    vx = 6.0 * grf(rs[4], shp, 32.0)
+    vy = vy + 6.0 * grf(rs[5], shp, 32.0)
+    sp = np.sqrt(vx * vx + vy * vy)
+    scale = 30.0 / sp[bmask].max()
+    vel = np.stack([vx * scale, vy * scale]) * bmask
+    lam0 = np.array([500.0, 500.2])
+    vD = 8.0 * np.sqrt(T)
+    a0 = 10.0 ** (-3.0 + 2.0 * ndtr(grf(rs[6], shp, 16.0)))
+    chi_star = np.stack([np.where(bmask, c * dens * math.sqrt(math.pi) * l0 * 8.0 / C_KMS, 0.0)
+                         for c, l0 in ((20.0, lam0[0]), (1.0, lam0[1]))])
+    inv_dld = np.stack([np.where(bmask, C_KMS / (l0 * vD), 0.0) for l0 in lam0])
+    damp = np.stack([np.where(bmask, a0, 0.0)] * 2)
+    chi_bg = np.where(bmask, 1e-3 * dens, 0.0)
+    dv = np.linspace(-80.0, 80.0, n_lam_per_line)
+    lam = np.concatenate([l0 * (1.0 + dv / C_KMS) for l0 in lam0])
+    f32 = lambda a, k: a.astype(np.float32).reshape(k, -1)  # noqa: E731
+    return dict(
+        name="prominence", dim=dim, n=(nx, ny, 1), brick=B, n_levels=4, model="lines", profile="voigt",
+        lam=lam, lam0=lam0, eta_star=f32(chi_star * S, 2), chi_star=f32(chi_star, 2), damp=f32(damp, 2),
+        inv_dld=f32(inv_dld, 2), eta_bg=(chi_bg * S).astype(np.float32).reshape(-1),
+        chi_bg=chi_bg.astype(np.float32).reshape(-1), vel=f32(vel, 2), dirs=directions_2d(n_dir),
+        block_active=block_active, ds0=1.0, I0=0.0, iod_threshold=1e-2, tau_thin=0.25, lam_batch=8,
+    )
+
+
 def _loops_density(rng, n, z_top, target_blocks, B, max_loops=400, first=12):
     """Semicircular loop tubes standing on the slab top (z = z_top)."""
     nx = ny = nz = n
