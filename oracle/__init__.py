@@ -78,6 +78,9 @@ def lib():
         L.orc_levels.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, _P, _P]
         L.orc_march.restype = ctypes.c_int
         L.orc_march.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_int32, _P]
+        L.orc_march_interval.restype = ctypes.c_int
+        L.orc_march_interval.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, _P, _P, ctypes.c_double,
+                                         ctypes.c_double, _P, _P, ctypes.c_int32]
         _LIB = L
     return _LIB
 
@@ -252,6 +255,32 @@ def march(scene: Scene, emis: int, levels, ray_vox, ray_dir, n_threads: int = 0,
                          _ptr(out), int(n_threads), _ptr(nseg))
     assert rc == 0, "oracle march: segment buffer overflow"
     return (out, nseg) if want_nseg else out
+
+
+def march_interval(scene: Scene, emis: int, levels, ray_vox, ray_dir, t1, t2, n_threads: int = 0):
+    """(I, T)[ray][lam] in FP64 over the path interval [t1, t2] of each ray (radiance interval):
+    I starts from 0 at the far end unless the ray leaves the grid inside the interval (then from I0);
+    T is the interval's transmittance."""
+    dirs = _c(scene.sc["dirs"], np.float32)
+    rv = _c(ray_vox, np.int32)
+    rd = _c(ray_dir, np.int32)
+    nl = scene.s.n_lam
+    I = np.zeros((rv.size, nl))
+    T = np.zeros((rv.size, nl))
+    lev = None if levels is None else _c(levels, np.int8)
+    rc = lib().orc_march_interval(scene.ref, int(emis), _ptr(lev), _ptr(dirs), rv.size, _ptr(rv), _ptr(rd),
+                                  float(t1), float(t2), _ptr(I), _ptr(T), int(n_threads))
+    assert rc != -2, "oracle interval march: need 0 <= t1 <= t2"
+    assert rc == 0, "oracle interval march: segment buffer overflow"
+    return I, T
+
+
+def cap_levels(levels, max_level):
+    """Block levels with a per-call MIP cap (empty blocks stay -1)."""
+    lv = np.asarray(levels, np.int8).copy()
+    if max_level >= 0:
+        lv[lv > max_level] = max_level
+    return lv
 
 
 def voigt_h(a, x):

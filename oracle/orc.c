@@ -31,6 +31,13 @@
  *                     with emissivity/opacity per cell from stored values
  *                     (static), the exact line model (Classic), velocity
  *                     interpolation (Sect. 3.1) or Core and Voigt (Sect. 3.2).
+ *   orc_march_interval  the same over a radiance interval t in [t1, t2]
+ *                     (Sect. 2.3, Eq. Ray and the HDDA procedure of Alg. 1
+ *                     take [t1, t2]; Sect. 4.1 radiance cascades): the
+ *                     ray's pieces clipped to the interval, the recurrence
+ *                     started from 0 (or from I0 when the ray leaves the
+ *                     grid inside the interval), plus the interval's
+ *                     transmittance T = prod exp(-tau).
  *   orc_voigt_h       H(a,x) = Re w(x + i a) by Weideman's rational series
  *                     with N = 64 terms in FP64 (an independent method from
  *                     the single-precision profile of the GPU path).
@@ -703,14 +710,20 @@ static void cell_cav(const orc_scene* s, const int32_t c[3], int size, const dou
 /* ------------------------------------------------------------------ */
 /*
  * For each ray r (probe voxel ray_vox[r], direction dirs[ray_dir[r]]) and each
- * wavelength il: I_out[r * n_lam + il].  emis selects where a cell's eta, chi
- * come from (ORC_STATIC: st_eta/st_chi level grids; ORC_CLASSIC: line model
- * at the voxel, level 0 only; ORC_VELINTERP; ORC_CAV).  nseg_out (nullable)
- * receives the number of segments of each ray.
+ * wavelength il: I_out[r * n_lam + il] over the path interval [t1, t2] of the
+ * ray (t1 = 0, t2 = infinity: the whole ray).  emis selects where a cell's
+ * eta, chi come from (ORC_STATIC: st_eta/st_chi level grids; ORC_CLASSIC: line
+ * model at the voxel, level 0 only; ORC_VELINTERP; ORC_CAV).  Each piece of the
+ * ray's cell list is clipped to [t1, t2]; pieces left with no length are
+ * dropped.  The recurrence starts at the far end of the interval from I0 if
+ * the ray leaves the grid inside the interval (t1 < t_exit <= t2), else from 0
+ * (the far field is another interval's).  T_out (nullable) receives the
+ * transmittance of the interval, the product of exp(-tau) over its pieces.
+ * nseg_out (nullable) receives the number of segments of each ray.
  */
-int orc_march(const orc_scene* s, int32_t emis, const int8_t* levels, const float* dirs, int64_t n_rays,
-              const int32_t* ray_vox, const int32_t* ray_dir, double* I_out, int32_t n_threads,
-              int32_t* nseg_out)
+static int march_rays(const orc_scene* s, int32_t emis, const int8_t* levels, const float* dirs, int64_t n_rays,
+                      const int32_t* ray_vox, const int32_t* ray_dir, double t1, double t2, double* I_out,
+                      double* T_out, int32_t n_threads, int32_t* nseg_out)
 {
     const int D = s->dim;
     int cap = 0;
@@ -743,9 +756,15 @@ int orc_march(const orc_scene* s, int32_t emis, const int8_t* levels, const floa
             const float* w = dirs + (int64_t)ray_dir[r] * D;
             float w3[3] = {0, 0, 0};
             double wd[3] = {0, 0, 0};
+            double texit = INFINITY;
             for (int a = 0; a < D; ++a) {
                 w3[a] = w[a];
                 wd[a] = (double)w[a];
+                /* the ray leaves the box through the first boundary plane it reaches */
+                double te = INFINITY;
+                if (wd[a] > 0) te = (pv[a] + 0.5) / wd[a];
+                else if (wd[a] < 0) te = (pv[a] + 0.5 - s->n[a]) / wd[a];
+                if (te < texit) texit = te;
             }
             int ns = orc_ray_segments(s, levels, pv, w3, cap, cell, lv, ti, to, sc, sti, sto, cap);
             if (ns < 0) {
@@ -753,6 +772,20 @@ int orc_march(const orc_scene* s, int32_t emis, const int8_t* levels, const floa
                 err = 1;
                 continue;
             }
+            /* clip to [t1, t2] */
+            int nc = 0;
+            for (int i = 0; i < ns; ++i) {
+                double a0 = ti[i] > t1 ? ti[i] : t1;
+                double b0 = to[i] < t2 ? to[i] : t2;
+                if (!(b0 > a0)) continue;
+                for (int a = 0; a < 3; ++a) cell[3 * nc + a] = cell[3 * i + a];
+                lv[nc] = lv[i];
+                ti[nc] = a0;
+                to[nc] = b0;
+                ++nc;
+            }
+            ns = nc;
+            const int exits = t1 < texit && texit <= t2;
             if (nseg_out) nseg_out[r] = ns;
             for (int il = 0; il < s->n_lam; ++il) {
                 for (int i = 0; i < ns; ++i) {
@@ -776,8 +809,8 @@ int orc_march(const orc_scene* s, int32_t emis, const int8_t* levels, const floa
                     se[i] = e;
                     sx[i] = x;
                 }
-                /* upwind boundary -> probe */
-                double I = s->I0;
+                /* far end of the interval -> near end */
+                double I = exits ? s->I0 : 0.0, T = 1.0;
                 for (int i = ns - 1; i >= 0; --i) {
                     double len = (to[i] - ti[i]) * s->ds0;
                     if (sx[i] == 0.0) {
@@ -785,9 +818,11 @@ int orc_march(const orc_scene* s, int32_t emis, const int8_t* levels, const floa
                     } else {
                         double tau = sx[i] * len;
                         I = I * exp(-tau) + (se[i] / sx[i]) * (-expm1(-tau));
+                        T *= exp(-tau);
                     }
                 }
                 I_out[r * s->n_lam + il] = I;
+                if (T_out) T_out[r * s->n_lam + il] = T;
             }
         }
         free(sc);
@@ -801,6 +836,22 @@ int orc_march(const orc_scene* s, int32_t emis, const int8_t* levels, const floa
         free(sx);
     }
     return err ? -1 : 0;
+}
+
+int orc_march(const orc_scene* s, int32_t emis, const int8_t* levels, const float* dirs, int64_t n_rays,
+              const int32_t* ray_vox, const int32_t* ray_dir, double* I_out, int32_t n_threads,
+              int32_t* nseg_out)
+{
+    return march_rays(s, emis, levels, dirs, n_rays, ray_vox, ray_dir, 0.0, INFINITY, I_out, NULL, n_threads,
+                      nseg_out);
+}
+
+int orc_march_interval(const orc_scene* s, int32_t emis, const int8_t* levels, const float* dirs, int64_t n_rays,
+                       const int32_t* ray_vox, const int32_t* ray_dir, double t1, double t2, double* I_out,
+                       double* T_out, int32_t n_threads)
+{
+    if (!(t1 >= 0.0) || !(t2 >= t1)) return -2;
+    return march_rays(s, emis, levels, dirs, n_rays, ray_vox, ray_dir, t1, t2, I_out, T_out, n_threads, NULL);
 }
 
 /* vectorised H(a, x) for tests */
