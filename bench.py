@@ -89,7 +89,7 @@ def main():
                          "matrix: the paper's method matrix on a prominence-like 2D scene")
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=21)
-    ap.add_argument("--iod", type=float, default=1e-2)
+    ap.add_argument("--iod", type=float, default=None, help="IoD threshold T (default 1 for matrix, else 1e-2)")
     ap.add_argument("--avg", default="linear", choices=["log", "linear"], help="stored level values: arithmetic "
                     "(box filter, default) or geometric mean of the children")
     ap.add_argument("--tau-thin", type=float, default=0.25, help="thin bypass threshold on a cell's optical side")
@@ -116,9 +116,12 @@ def main():
     ap.add_argument("--scenes", type=int, default=0, help="cfg4: first N scenes only (0 = all 48)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus %d requested); the path shards by "
-              "wavelength batch with no exchange, see the design notes." % args.gpus)
+        print("bench.py measures one GPU (--gpus %d requested): rays are independent given the scene, and the "
+              "path would shard by wavelength batch with no exchange." % args.gpus)
         sys.exit(2)
+    if args.iod is None:
+        # the method matrix mirrors the deployment of Sect. 4.1 (IoD threshold 1); elsewhere 1e-2
+        args.iod = 1.0 if args.workload == "matrix" else 1e-2
     if args.workload == "cfg3":
         return bench_cfg3(args)
     if args.workload == "cfg4":
@@ -299,6 +302,40 @@ def bench_cfg2(args):
         cmp["vlm_j_output"] = {"ms_per_batch": (tb - ta) * 1e3 / nbc,
                                "speedup_vs_i_output": vlm_ms_batch / ((tb - ta) * 1e3 / nbc),
                                "note": "same march; J and psi [8][probes] instead of I [64 dirs][8][probes]"}
+        # radiance intervals: the same rays split at the cascade interval ends 1.5 * 4^c, each interval
+        # with its cascade's maximum MIP level, I and T written per interval (what a merge consumes)
+        ends, caps = [0.0, 1.5, 6.0, 24.0, 96.0, float("inf")], [0, 0, 1, 2, 3]
+        ibufs = [(torch.empty_like(tmp), torch.empty_like(tmp)) for _ in caps]
+        iv_stats = torch.zeros(5, dtype=torch.int64, device=dev)
+
+        def intervals(stats=None):
+            for c in range(len(caps)):
+                scene.trace_interval(dirs, ends[c], ends[c + 1], mode="vlm", max_level=caps[c], out=ibufs[c][0],
+                                     out_T=ibufs[c][1], stats=stats)
+        for b in range(nbc):
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
+            intervals()
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        for b in range(nbc):
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
+            intervals()
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for b in range(nbc):
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        iod_frame=args.iod_frame)
+            intervals(stats=iv_stats)
+        torch.cuda.synchronize()
+        cmp["cascade_intervals"] = {"ms_per_batch": (tb - ta) * 1e3 / nbc,
+                                    "raw_gseg_s": int(iv_stats[0].item()) * 8 / (tb - ta) / 1e9,
+                                    "vs_whole_ray_vlm": vlm_ms_batch / ((tb - ta) * 1e3 / nbc),
+                                    "intervals": [[ends[c], ends[c + 1], caps[c]] for c in range(len(caps))],
+                                    "note": "same rays split at 1.5 * 4^c, per-cascade MIP caps, I and T of "
+                                            "every interval written"}
+        del ibufs
         if args.emission == "velinterp":
             # the accuracy-preserving setting: no merging, 81 velocity nodes (error filled in below)
             scene81 = rt.Scene.from_dict(sc, emission="velinterp", n_v=81)

@@ -48,7 +48,7 @@ extern "C" {
 typedef enum rt_status {
     RT_OK = 0,
     RT_E_ARG = 1,         /* invalid argument (shape, enum, null pointer, size) */
-    RT_E_UNSUPPORTED = 2, /* valid but not supported by this build */
+    RT_E_UNSUPPORTED = 2, /* valid but not supported by the library */
     RT_E_STATE = 3,       /* call order (e.g. trace before build) */
     RT_E_HIP = 4,         /* a HIP runtime call failed */
     RT_E_DEVICE = 5       /* a device-side anomaly was recorded */
@@ -272,6 +272,30 @@ rt_status rt_scene_build(rt_scene* scene, const rt_build_params* params, int32_t
  */
 rt_status rt_trace(const rt_scene* scene, const rt_trace_params* params, const float* d_dirs, int32_t n_dir,
                    const int32_t* d_probes, int64_t n_probes, float* d_I, void* stream);
+
+/*
+ * rt_trace_interval -- rt_trace over the path interval t in [t1, t2] of every
+ * ray x(t) = p - t w (a radiance interval: Eq. Ray and the HDDA procedure of
+ * Alg. 1 traverse [t1, t2]; Sect. 4.1 gives each cascade its own interval and
+ * maximum MIP level, params->max_level).  The interval starts in the cell
+ * holding x(t1) (on a cell face, the cell the ray moves into) at its block's
+ * level, and its last segment ends at t2; a face crossed exactly at t2 belongs
+ * to this interval.  With a distance-graded cap (params->level_dist) a block's
+ * cap is still set by the path length at which the ray entered it, so
+ * consecutive intervals visit the cells of the whole ray.
+ *   t1, t2     0 <= t1 <= t2; t2 may be +infinity (to the grid boundary).
+ *   d_I        device float [n_dir][nl][n_probes]: the interval's emission seen
+ *              at p, starting from 0 at the interval's far end, or from
+ *              params->I0 when the ray leaves the grid within the interval.
+ *   d_T        device float [n_dir][nl][n_probes] transmittance of the
+ *              interval (1 when it holds no non-empty cell), or NULL.
+ * Intervals [0, t1], [t1, t2], ... compose as I = I_a + T_a I_b, T = T_a T_b.
+ * Other arguments as for rt_trace.  Asynchronous.
+ * Errors: RT_E_ARG (also t1 negative or not finite, t2 < t1), RT_E_STATE.
+ */
+rt_status rt_trace_interval(const rt_scene* scene, const rt_trace_params* params, const float* d_dirs,
+                            int32_t n_dir, const int32_t* d_probes, int64_t n_probes, double t1, double t2,
+                            float* d_I, float* d_T, void* stream);
 
 /* Scene facts (host only, no device work). */
 rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* h_info);

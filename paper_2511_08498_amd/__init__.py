@@ -35,7 +35,7 @@ EXPORTS = (
     "rt_graph_destroy", "rt_trace_truncated", "rt_nrc_num_params", "rt_nrc_create", "rt_nrc_destroy",
     "rt_nrc_get_weights", "rt_nrc_set_weights", "rt_nrc_pack", "rt_nrc_train", "rt_nrc_loss", "rt_nrc_gradients",
     "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate", "rt_scene_workspace_bytes", "rt_nrc_workspace_bytes",
-    "rt_trace_j", "rt_trace_j_workspace_bytes",
+    "rt_trace_j", "rt_trace_j_workspace_bytes", "rt_trace_interval",
 )
 _VOID = ("rt_scene_destroy", "rt_last_error", "rt_version", "rt_batch_destroy", "rt_graph_destroy", "rt_nrc_destroy")
 
@@ -117,6 +117,7 @@ def lib():
     L.rt_scene_create.argtypes = [_P, _P, _P, ctypes.POINTER(_P)]
     L.rt_scene_build.argtypes = [_P, _P, i32, i32, _P]
     L.rt_trace.argtypes = [_P, _P, _P, i32, _P, i64, _P, _P]
+    L.rt_trace_interval.argtypes = [_P, _P, _P, i32, _P, i64, ctypes.c_double, ctypes.c_double, _P, _P, _P]
     L.rt_scene_get_info.argtypes = [_P, _P]
     L.rt_scene_active_blocks.argtypes = [_P, _P]
     L.rt_scene_levels.argtypes = [_P, _P]
@@ -347,6 +348,34 @@ class Scene:
                               _stream(stream)))
         self._last = (td, tp)
         return out
+
+    def trace_interval(self, dirs, t1, t2, probes=None, mode="vlm", I0=0.0, max_level=-1, step_cap=0,
+                       level_dist=None, want_T=True, out=None, out_T=None, stats=None, stream=None):
+        """Radiance interval [t1, t2] of every ray (rt_trace_interval): (I, T) [n_dir][batch][n_probes]
+        (T is None when want_T is false)."""
+        torch = self.torch
+        td = dirs if isinstance(dirs, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(dirs, np.float32))
+        td = td.to(device=self.device, dtype=torch.float32).contiguous()
+        if probes is None:
+            n_probes, tp = self.info["n_probes"], None
+        else:
+            tp = probes if isinstance(probes, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(probes, np.int32))
+            tp = tp.to(device=self.device, dtype=torch.int32).contiguous()
+            n_probes = tp.numel()
+        nd, nl = int(td.shape[0]), self.batch[1] - self.batch[0]
+        if out is None:
+            out = torch.empty((nd, nl, n_probes), dtype=torch.float32, device=self.device)
+        if want_T and out_T is None:
+            out_T = torch.empty((nd, nl, n_probes), dtype=torch.float32, device=self.device)
+        if not want_T:
+            out_T = None
+        p = self._tparams(mode, max_level, I0, step_cap, stats, level_dist)
+        _check(lib().rt_trace_interval(self.h, ctypes.byref(p), td.data_ptr(), nd,
+                                       tp.data_ptr() if tp is not None else None, int(n_probes), float(t1),
+                                       float(t2), out.data_ptr(), out_T.data_ptr() if out_T is not None else None,
+                                       _stream(stream)))
+        self._last = (td, tp)
+        return out, out_T
 
     def trace_truncated(self, dirs, t_trunc, gen=True, fallback=None, probes=None, mode="vlm", I0=0.0,
                         max_level=-1, step_cap=0, level_dist=None, stream=None):

@@ -293,6 +293,13 @@ static LamBatch make_batch(const rt_scene* sc, int lam_begin, int lam_end)
         lb.lam[l] = sc->lam.empty() ? 0.0 : sc->lam[(size_t)il];
     }
     for (int k = 0; k < kMaxLines; ++k) lb.lam0[k] = k < lb.n_lines ? sc->lam0[(size_t)k] : 1.0;
+    for (int k = 0; k < kMaxLines; ++k) {
+        lb.k0[k] = (float)(lb.lam0[k] / kCkms);
+        for (int l = 0; l < kLam; ++l) {
+            lb.dl[l][k] = (float)(lb.lam[l] - lb.lam0[k]);
+            lb.rr[l][k] = (float)(lb.lam[l] / lb.lam0[k]);
+        }
+    }
     return lb;
 }
 
@@ -404,6 +411,40 @@ rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_
     t.probes = d_probes;
     t.n_probes = n_probes;
     t.I = d_I;
+    RT_HIP(launch_trace(t, (hipStream_t)stream));
+    return RT_OK;
+}
+
+rt_status rt_trace_interval(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, int32_t n_dir,
+                            const int32_t* d_probes, int64_t n_probes, double t1, double t2, float* d_I, float* d_T,
+                            void* stream)
+{
+    g_err.clear();
+    if (!sc || !p || !d_dirs || !d_I) return fail(RT_E_ARG, "null argument");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace_interval before rt_scene_build");
+    if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
+    if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
+    if (!(t1 >= 0.0) || !(t1 < INFINITY)) return fail(RT_E_ARG, "t1 must be finite and >= 0 (got %g)", t1);
+    if (!(t2 >= t1)) return fail(RT_E_ARG, "t2 must be >= t1 (got t1 = %g, t2 = %g)", t1, t2);
+    for (int m = 1; m < RT_MAX_LEVELS; ++m)
+        if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
+    const long long all = (long long)sc->n_active * sc->g.bvox;
+    if (!d_probes && n_probes != all)
+        return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
+    if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
+    if (n_probes == 0) return RT_OK;
+    if ((long long)n_dir * ((n_probes + 63) / 64) > (long long)0x7fffffff * 4)
+        return fail(RT_E_ARG, "launch too large");
+    TraceLaunch t = make_trace(sc, p);
+    t.dirs = d_dirs;
+    t.n_dir = n_dir;
+    t.probes = d_probes;
+    t.n_probes = n_probes;
+    t.I = d_I;
+    t.interval = 1;
+    t.t_lo = t1;
+    t.t_hi = t2;
+    t.T_out = d_T;
     RT_HIP(launch_trace(t, (hipStream_t)stream));
     return RT_OK;
 }

@@ -42,6 +42,10 @@ struct LamBatch {
     int pad_;
     double lam[kLam];
     double lam0[kMaxLines];
+    // FP32 per-batch constants of the line evaluation (read as kernel arguments):
+    float dl[kLam][kMaxLines];  // lam - lam0
+    float rr[kLam][kMaxLines];  // lam / lam0
+    float k0[kMaxLines];        // lam0 / c
 };
 
 // Device buffers owned by a scene.
@@ -174,6 +178,11 @@ struct TraceLaunch {
     const float* weights;      // [n_dir] quadrature weights
     float* part_J;             // [n_chunks][nl][n_probes]
     float* part_psi;           // [n_chunks][nl][n_probes], nullable
+    // radiance interval [t_lo, t_hi] of each ray
+    int interval;
+    double t_lo;
+    double t_hi;
+    float* T_out;              // [n_dir][nl][n_probes] interval transmittance, nullable
 };
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s);
 hipError_t launch_reduce_chunks(const float* part, int n_chunks, long long n, float* out, hipStream_t s);

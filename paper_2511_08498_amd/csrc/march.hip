@@ -70,10 +70,15 @@ __device__ __forceinline__ int graded_cap(const float* ld, int nlev, double d2, 
 // 2 when the visitor asked to stop (truncated march).
 // With `graded`, a block's level is also capped by the path length at which
 // the ray enters it (ld: level_dist).
-template <int D, class Vis>
+// With Iv, only the path interval [t_lo, t_hi] is traversed (a radiance
+// interval): the start cell is the one holding x(t_lo) (on a plane, the one the
+// ray moves into), the last segment ends at t_hi, and a plane crossed exactly
+// at t_hi belongs to this interval.  Returns 3 when t_hi was reached inside the
+// grid and 4 when the ray had left the grid by t_lo (no segment).
+template <int D, bool Iv = false, class Vis>
 __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode, int maxl, int graded,
                                     const float* ld, const int* pv, const float* wf, int step_cap, Vis& vis,
-                                    Counters& cnt)
+                                    Counters& cnt, double t_lo = 0.0, double t_hi = 0.0)
 {
     int p2[3], st[3], c[3], k[3], bc[3];
     double aw[3], iw[3], ws[3], dd[3];  // dd: |p2 - 2 k| (twice the distance to the next plane), exact
@@ -98,25 +103,66 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         st[a] = wf[a] > 0.f ? -1 : (wf[a] < 0.f ? 1 : 0);
         bc[a] = pv[a] >> g.log2B;
     }
+    int c0[3] = {pv[0], pv[1], pv[2]};
+    double t = 0.0;
+    if constexpr (Iv) {
+        // MIP-0 cell at t_lo: plane j >= 1 of axis a lies at doubled distance 2j - 1 from the
+        // centre and is crossed by t_lo iff 2j - 1 <= 2 t_lo |w_a|.  An fma rounds once, so its
+        // sign is that of the exact difference; floor(t_lo |w_a| + 1/2) is at most one too high.
+        const double tw = 2.0 * t_lo;
+        bool gone = false;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            if (st[a] == 0) continue;
+            const double e = floor(fma(t_lo, aw[a], 0.5));
+            if (!(e <= (double)g.n[a] + 2.0)) {
+                gone = true;
+                continue;
+            }
+            int nj = (int)e;
+            if (nj > 0 && fma(-tw, aw[a], (double)(2 * nj - 1)) > 0.0) --nj;
+            c0[a] = pv[a] + st[a] * nj;
+            gone = gone || (unsigned)c0[a] >= (unsigned)g.n[a];
+            bc[a] = c0[a] >> g.log2B;
+        }
+        if (gone) return 4;
+        t = t_lo;
+    }
     long long blk = bc[0] + (long long)g.nb[0] * (bc[1] + (long long)g.nb[1] * bc[2]);
     int cap0 = maxl;
     if (graded) {
-        int c0 = 0;
-        for (int m = 1; m < g.n_levels; ++m) {
-            if (!(ld[m] <= 0.f)) break;
-            c0 = m;
+        int cg = 0;
+        if constexpr (Iv) {
+            // the start block was entered when the ray crossed the last of its entry faces
+            // (time dn / (2 an); 0 in the probe's own block)
+            double dn = 0.0, an = 1.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                if (st[a] == 0 || bc[a] == (pv[a] >> g.log2B)) continue;
+                const int kf = (st[a] > 0 ? bc[a] : bc[a] + 1) << g.log2B;
+                const double df = (double)abs(p2[a] - 2 * kf);
+                if (df * an > dn * aw[a]) {
+                    dn = df;
+                    an = aw[a];
+                }
+            }
+            cg = graded_cap(ld, g.n_levels, dn, an);
+        } else {
+            for (int m = 1; m < g.n_levels; ++m) {
+                if (!(ld[m] <= 0.f)) break;
+                cg = m;
+            }
         }
-        cap0 = c0 < maxl ? c0 : maxl;
+        cap0 = cg < maxl ? cg : maxl;
     }
     int lvl = block_level(sts, blk, mode, cap0);
     int vs = lvl < 0 ? g.B : (1 << lvl);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        c[a] = pv[a] & ~(vs - 1);
+        c[a] = c0[a] & ~(vs - 1);
         k[a] = c[a] + (st[a] > 0 ? vs : 0);
         dd[a] = (double)abs(p2[a] - 2 * k[a]);
     }
-    double t = 0.0;
     for (int step = 0; step < step_cap; ++step) {
         int s0;
         unsigned tie;
@@ -152,6 +198,18 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             tn = dd[s0] * iw[s0];
         }
         const double d2s0 = dd[s0];
+        if constexpr (Iv) {
+            // next crossing beyond t_hi (exact sign): the interval ends inside this cell
+            if (fma(-2.0 * t_hi, aw[s0], d2s0) > 0.0) {
+                if (lvl >= 0) {
+                    if (t_hi > t && vis.seg(c, lvl, blk, t, t_hi)) return 2;
+                    ++cnt.segs;
+                } else {
+                    ++cnt.empty;
+                }
+                return 3;
+            }
+        }
         if (lvl >= 0) {
             if (vis.seg(c, lvl, blk, t, tn)) return 2;
             ++cnt.segs;
@@ -328,6 +386,7 @@ __device__ __forceinline__ float4 load4<__half>(const __half* r, int i)
 struct AccPlain {
     static constexpr bool kTrunc = false;
     static constexpr bool kJ = false;
+    static constexpr bool kIv = false;
     float I[kLam], Tr[kLam];
     __device__ void init(const TraceLaunch*)
     {
@@ -347,6 +406,12 @@ struct AccPlain {
     }
 };
 
+// Radiance interval [t_lo, t_hi]: the plain accumulator over the interval's
+// segments; the caller also receives the interval's transmittance.
+struct AccIv : AccPlain {
+    static constexpr bool kIv = true;
+};
+
 // Truncated: the near field t < t_trunc and the far field t >= t_trunc are
 // accumulated separately (the cell that straddles t_trunc is split there,
 // exactly, since eta and chi are constant in it).  Generation mode keeps
@@ -358,6 +423,7 @@ template <bool Gen>
 struct AccTrunc {
     static constexpr bool kTrunc = true;
     static constexpr bool kJ = false;
+    static constexpr bool kIv = false;
     static constexpr bool kGen = Gen;  // generation mode: also accumulate the far field
     float In[kLam], Tn[kLam];
     float If[Gen ? kLam : 1], Tf[Gen ? kLam : 1];
@@ -447,6 +513,7 @@ struct AccTrunc {
 struct AccJ {
     static constexpr bool kTrunc = false;
     static constexpr bool kJ = true;
+    static constexpr bool kIv = false;
     float I[kLam], Tr[kLam], psi[kLam];
     int first;
     __device__ void init(const TraceLaunch*)
@@ -477,6 +544,7 @@ struct AccJ {
 template <int D, typename T, class Acc = AccPlain>
 struct VisStatic {
     using AccT = Acc;
+    static constexpr int kMinWaves = 1;
     const Geo* g;
     const int32_t* slot;
     const T* vals;
@@ -514,6 +582,7 @@ struct VisStatic {
 template <int D, class Acc = AccPlain>
 struct VisVelinterp {
     using AccT = Acc;
+    static constexpr int kMinWaves = 1;
     const TraceLaunch* tl;
     long long cur_blk;
     long long base;
@@ -566,14 +635,13 @@ struct VisVelinterp {
 template <int D, typename T = float, class Acc = AccPlain>
 struct VisCav {
     using AccT = Acc;
+    // the plain 3D march needs a few registers more than three waves per SIMD allow
+    static constexpr int kMinWaves = (D == 3 && !Acc::kTrunc && !Acc::kJ) ? 3 : 1;
     const TraceLaunch* tl;
     long long cur_blk;
     long long base;
     float dsf;
     float w[3];
-    float dl[kLam][kMaxLines];  // lam - lam0
-    float k0[kMaxLines];        // lam0 / c
-    float rr[kLam][kMaxLines];  // lam / lam0
     Acc acc;
     __device__ void init(const TraceLaunch* t, const float* wf)
     {
@@ -584,15 +652,6 @@ struct VisCav {
         w[0] = wf[0];
         w[1] = wf[1];
         w[2] = D > 2 ? wf[2] : 0.f;
-#pragma unroll
-        for (int k = 0; k < kMaxLines; ++k) {
-            k0[k] = (float)(t->lb.lam0[k] / kCkms);
-#pragma unroll
-            for (int l = 0; l < kLam; ++l) {
-                dl[l][k] = (float)(t->lb.lam[l] - t->lb.lam0[k]);
-                rr[l][k] = (float)(t->lb.lam[l] / t->lb.lam0[k]);
-            }
-        }
         acc.init(t);
     }
     __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
@@ -627,12 +686,13 @@ struct VisCav {
 #pragma unroll
             for (int k = 0; k < kMaxLines; ++k) {
                 if (k < nln) {
-                    float x = fmaf(k0[k], u, dl[l][k]) * ls[k][3];
+                    // per-batch constants lam - lam0, lam / lam0, lam0 / c: scalar kernel arguments
+                    float x = fmaf(tl->lb.k0[k], u, tl->lb.dl[l][k]) * ls[k][3];
                     float phi;
                     if (!voigt) {
                         phi = __expf(-x * x);
                     } else {
-                        float r2 = rr[l][k];
+                        float r2 = tl->lb.rr[l][k];
                         phi = voigt_h(ls[k][2] * r2 * r2, x) * ls[k][3] * (0.56418958354775628f / r2);
                     }
                     ee = fmaf(ls[k][0], phi, ee);
@@ -673,10 +733,22 @@ __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* 
 
     Vis vis;
     vis.init(&t, wf);
-    int rc = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+    constexpr bool kIv = Vis::AccT::kIv;
+    int rc = hdda<D, kIv>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt,
+                          t.t_lo, t.t_hi);
     int capped = rc == 1;
     const int nl = t.lb.nl;
-    if constexpr (!Vis::AccT::kTrunc) {
+    if constexpr (kIv) {
+        // I0 enters only through the interval in which the ray leaves the grid
+        const float I0 = rc == 0 ? t.I0 : 0.f;
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            if (l >= nl) continue;
+            const long long q = ((long long)dir * nl + l) * t.n_probes + probe;
+            t.I[q] = fmaf(vis.acc.Tr[l], I0, vis.acc.I[l]);
+            if (t.T_out) t.T_out[q] = vis.acc.Tr[l];
+        }
+    } else if constexpr (!Vis::AccT::kTrunc) {
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
             if (l < nl) t.I[((long long)dir * nl + l) * t.n_probes + probe] = fmaf(vis.acc.Tr[l], t.I0, vis.acc.I[l]);
@@ -723,7 +795,8 @@ __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* 
 }
 
 template <int D, class Vis>
-__global__ void __launch_bounds__(256) k_trace(TraceLaunch t)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Vis::kMinWaves)))
+k_trace(TraceLaunch t)
 {
     extern __shared__ uint64_t sts[];
     for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
@@ -898,6 +971,7 @@ static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)
 {
     if (t.jmode) return launch_trace_acc<AccJ>(t, s);
+    if (t.interval) return launch_trace_acc<AccIv>(t, s);
     if (t.trunc) return t.gen ? launch_trace_acc<AccTrunc<true>>(t, s) : launch_trace_acc<AccTrunc<false>>(t, s);
     return launch_trace_acc<AccPlain>(t, s);
 }
