@@ -97,6 +97,9 @@ def main():
     ap.add_argument("--iod-frame", default="rest", choices=["rest", "core"],
                     help="velocity interpolation: level test with lines at rest (the paper) or core-closest")
     ap.add_argument("--no-grading", action="store_true", help="plain VLM (no distance-graded cap)")
+    ap.add_argument("--grade", default="path", choices=["entry", "path"],
+                    help="distance-graded cap taken along the path (the cascade intervals' caps) or at each "
+                         "block's entry")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--compare-batches", type=int, default=4)
@@ -178,7 +181,7 @@ def bench_cfg2(args):
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-            scene.trace(dirs, mode="vlm", level_dist=level_dist, out=I_all[b], stats=stats)
+            scene.trace(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, out=I_all[b], stats=stats)
             if record:
                 e1.record(stream)
                 ev.append((e0, e1))
@@ -243,7 +246,7 @@ def bench_cfg2(args):
                "2D 1024^2, 16^2 bricks, 40%% active, 2 Gaussian lines + continuum, |v| <= 30 km/s, %s (n_v=%d), "
                "4-level VLM T=%g, %s means, thin %g, level test %s frame, %s, 64 dirs, 256 lambda (32 batches of 8), "
                "all %d probes" % (args.emission, args.n_v, args.iod, args.avg, args.tau_thin, args.iod_frame,
-                                  "plain VLM" if args.no_grading else "cascade-graded levels x%g" % args.grade_scale,
+                                  _grading(args),
                                   n_probes)),
                       "value_kind": "dense-equivalent segment-wavelength updates per second"},
            "raw_gseg_s": raw, "seg_lam_per_step": seglam_step, "dense_seg_lam_per_step": dense_seglam_step,
@@ -290,13 +293,13 @@ def bench_cfg2(args):
         for b in range(nbc):
             scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
                         iod_frame=args.iod_frame)
-            scene.trace_j(dirs, mode="vlm", level_dist=level_dist, J=jbuf, psi=pbuf)
+            scene.trace_j(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, J=jbuf, psi=pbuf)
         torch.cuda.synchronize()
         ta = time.perf_counter()
         for b in range(nbc):
             scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
                         iod_frame=args.iod_frame)
-            scene.trace_j(dirs, mode="vlm", level_dist=level_dist, J=jbuf, psi=pbuf)
+            scene.trace_j(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, J=jbuf, psi=pbuf)
         torch.cuda.synchronize()
         tb = time.perf_counter()
         cmp["vlm_j_output"] = {"ms_per_batch": (tb - ta) * 1e3 / nbc,
@@ -420,7 +423,8 @@ def accuracy_ladder(args, rt, torch, np, sc, scene, dirs, probe_vox, d, ref, nb_
                 ("n_v=81, grading x4", scene81, {}, {"level_dist": ld4}),
                 ("n_v=81, core-closest, levels <= 2", scene81, {"iod_frame": "core"}, {"max_level": 2}),
                 ("n_v=81, core-closest, grading x4", scene81, {"iod_frame": "core"}, {"level_dist": ld4})]
-    return run_ladder(torch, np, settings, base, dict(mode="vlm", level_dist=level_dist), dirs, probe_vox, d, ref,
+    return run_ladder(torch, np, settings, base, dict(mode="vlm", level_dist=level_dist, grade=args.grade), dirs,
+                      probe_vox, d, ref,
                       nb_lam)
 
 
@@ -461,6 +465,15 @@ def _oracle_classic(sc, probe_vox, k, d, lam_idx, n_threads):
     ta = time.perf_counter()
     ref, nseg = orc.march(s, orc.CLASSIC, None, probe_vox[k], d, n_threads=n_threads, want_nseg=True)
     return ref, int(nseg.sum()) * len(lam_idx), time.perf_counter() - ta
+
+
+def _grading(args):
+    """workload text for the level cap along the ray"""
+    if args.no_grading:
+        return "plain VLM"
+    scale = "" if args.grade_scale == 1.0 else " x%g" % args.grade_scale
+    return "cascade-graded levels (cap taken %s)%s" % (
+        "along the path" if args.grade == "path" else "at block entry", scale)
 
 
 def _err(got, ref):
@@ -508,7 +521,7 @@ def bench_cfg3(args):
                 if record:
                     e0, e1 = _events(torch)
                     e0.record(stream)
-                scene.trace(dirs, mode="vlm", level_dist=level_dist, out=out)
+                scene.trace(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, out=out)
                 if record:
                     e1.record(stream)
                     evs.append((e0, e1))
@@ -532,7 +545,7 @@ def bench_cfg3(args):
     stats = torch.zeros(5, dtype=torch.int64, device=dev)
     for b in range(nb):
         scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin)
-        scene.trace(dirs, mode="vlm", level_dist=level_dist, out=out, stats=stats)
+        scene.trace(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, out=out, stats=stats)
     torch.cuda.synchronize()
     seglam = int(stats[0].item()) * 8
     # dense comparator: Core and Voigt at MIP 0 on the full grid (every brick stored), one batch
@@ -567,14 +580,15 @@ def bench_cfg3(args):
                     ("log means", scene, {"avg_mode": "log"}, {}),
                     ("no thin bypass, T=1e-3", scene, {"tau_thin": 0.0, "iod_threshold": 1e-3}, {}),
                     ("no thin bypass, levels <= 2", scene, {"tau_thin": 0.0}, {"max_level": 2})]
-        ladder = run_ladder(torch, np, settings, base, dict(mode="vlm", level_dist=level_dist), dirs, probe_vox[k], d,
+        ladder = run_ladder(torch, np, settings, base, dict(mode="vlm", level_dist=level_dist, grade=args.grade),
+                            dirs, probe_vox[k], d,
                             ref, nb)
     out_line = {"workload": "cfg3", "accuracy_ladder": ladder, "config": {
         "workload": "3D 256^3, 8^3 bricks, %d active (25%%), slab + %d loops, 2 Voigt lines (Core and Voigt) + "
                     "grey continuum, |v| <= 30 km/s, 4-level VLM T=%g, %s, 32 Fibonacci directions, %d lambda "
                     "(%d batches of 8), all %d probes" % (
                         int(sc["block_active"].sum()), int(sc["n_loops"]), args.iod,
-                        "plain VLM" if args.no_grading else "cascade-graded levels", nb * 8, nb, n_probes)},
+                        _grading(args), nb * 8, nb, n_probes)},
         "seg_lam_per_solve": seglam, "dense_seg_lam_per_solve": dense_seglam,
         "dense_classic_gpu": {"ms_per_batch": dense_ms_batch, "ms_per_solve_extrapolated": dense_ms_batch * nb},
         "cpu_baseline": {"value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
@@ -636,14 +650,15 @@ def bench_cfg4(args):
             build_wave(b)
             for it in items:
                 if it["nb"] > b:
-                    it["scene"].trace(it["dirs"], mode="vlm", level_dist=level_dist, out=it["out"], stats=stats)
+                    it["scene"].trace(it["dirs"], mode="vlm", level_dist=level_dist, grade=args.grade, out=it["out"],
+                                      stats=stats)
             if b % 8 == 7:
                 torch.cuda.synchronize()
                 log("cfg4 %s: wave %d/%d" % (tag, b + 1, waves))
 
     def jobs(part):
         return [{"scene": items[i]["scene"], "dirs": items[i]["dirs"], "out": items[i]["out"],
-                 "level_dist": level_dist} for i in part]
+                 "level_dist": level_dist, "grade": args.grade} for i in part]
 
     parts = sorted({tuple(i for i, it in enumerate(items) if it["nb"] > b) for b in range(waves)}, key=len,
                    reverse=True)
@@ -675,7 +690,7 @@ def bench_cfg4(args):
     # correctness: wave 0 batched == sequential, bit for bit
     build_wave(0)
     for it in items:
-        it["scene"].trace(it["dirs"], mode="vlm", level_dist=level_dist, out=it["out"])
+        it["scene"].trace(it["dirs"], mode="vlm", level_dist=level_dist, grade=args.grade, out=it["out"])
     ref0 = [it["out"].clone() for it in items]
     for it in items:
         it["out"].fill_(-1.0)
@@ -727,7 +742,7 @@ def bench_cfg4(args):
         "workload": "%d scenes (%d 2D 64^2-1024^2 with 16^2 bricks, %d 3D 64^3-192^3 with 8^3 bricks), 2-5 level "
                     "VLM T=%g, %s, static Gaussian line + continuum, 16-64 directions, 64-256 wavelengths, BF16 "
                     "storage, all probes" % (len(items), n2, len(items) - n2, args.iod,
-                                             "plain VLM" if args.no_grading else "cascade-graded levels")},
+                                             _grading(args))},
         "waves": waves, "seg_lam_per_solve": seglam, "batched_equals_sequential": identical,
         "autotuned": best, "autotune_ms": tune_ms,
         "sequential": {"ms_per_solve": ms_seq, "raw_gseg_s": seglam / ms_seq / 1e6},
@@ -774,7 +789,8 @@ def bench_cfg5(args):
     ta = time.perf_counter()
     for b in range(nb):
         scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage="bf16")
-        tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=tr_probes[b], level_dist=level_dist)
+        tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=tr_probes[b], level_dist=level_dist,
+                                   grade=args.grade)
         nn.pack(scene, tr, raw, tgt, b * rows_b)
     torch.cuda.synchronize()
     gen_s = time.perf_counter() - ta
@@ -797,7 +813,8 @@ def bench_cfg5(args):
     held_err = []
     for b in range(nb):
         scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage="bf16")
-        tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=hd_probes[b], level_dist=level_dist)
+        tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=hd_probes[b], level_dist=level_dist,
+                                   grade=args.grade)
         _, err = nn.validate(scene, tr, THRESH, fb)
         q = (tr["feat"][..., 3] > 0)[:, None, :].expand_as(err)
         held_err.append(err[q].cpu().numpy())
@@ -817,7 +834,7 @@ def bench_cfg5(args):
     def plain(dt, gather=None):
         for b in range(nb):
             scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage=dt)
-            scene.trace(dirs, mode="vlm", level_dist=level_dist, out=out)
+            scene.trace(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, out=out)
             if gather is not None:
                 gather[:, 8 * b:8 * b + 8] = out[dd, :, kk]
 
@@ -830,7 +847,8 @@ def bench_cfg5(args):
             if record:
                 e0, e1 = _events(torch)
                 e0.record(stream)
-            tr = scene.trace_truncated(dirs, T_TRUNC, gen=False, fallback=fallback, level_dist=level_dist)
+            tr = scene.trace_truncated(dirs, T_TRUNC, gen=False, fallback=fallback, level_dist=level_dist,
+                                       grade=args.grade)
             if record:
                 e1.record(stream)
             nn.compose(scene, tr, out=outc)
@@ -941,7 +959,8 @@ def bench_matrix(args):
         def solve(stats=None, gather=None):
             for b in range(nb):
                 scn.build(8 * b, 8 * b + 8, **bkw)
-                scn.trace(dirs, probes=probes, mode=mode, level_dist=level_dist if mode == "vlm" else None, out=out,
+                scn.trace(dirs, probes=probes, mode=mode, level_dist=level_dist if mode == "vlm" else None,
+                          grade=args.grade, out=out,
                           stats=stats)
                 if gather is not None:
                     gather[:, 8 * b:8 * b + 8] = out[dd, :, kk]
@@ -972,7 +991,7 @@ def bench_matrix(args):
                     "continuum, shear flow |v| <= 30 km/s, %d directions, %d lambda (%d batches), VLM T=%g, %s; "
                     "velocity interpolation n_v=%d; all %d active-voxel probes" % (
                         int(sc["block_active"].sum()), sc["block_active"].size, n_dir, nb * 8, nb, args.iod,
-                        "plain VLM" if args.no_grading else "cascade-graded levels", args.n_v, n_probes)},
+                        _grading(args), args.n_v, n_probes)},
         "methods": table,
         "cpu_baseline": {"value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
                          "kind": "oracle", "sample": "%d pairs x %d wavelengths, FP64 dense Classic, %.1f s" % (

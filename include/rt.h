@@ -199,7 +199,19 @@ typedef struct rt_build_params {
  *              over radiance intervals ending at 1.5 x 4^i voxels (Sect. 4.1)
  *              correspond to level_dist = {0, 6, 24, 96, 384}.  Values are
  *              compared exactly (use small dyadic numbers).
+ *   grade_mode rt_grade_mode: where the level_dist cap is taken.
+ *              RT_GRADE_BLOCK_ENTRY: at the path length at which the ray
+ *              enters each block, for the whole block (level changes stay on
+ *              block faces).  RT_GRADE_PATH: at every point of the ray, so the
+ *              cap rises exactly at t = level_dist[m], inside a cell if need
+ *              be (the cell is split there and the ray re-located at the new
+ *              level, with the same exact predicates as an interval start);
+ *              this is the cascade intervals' caps of Sect. 4.1 along one
+ *              ray, equal to the composition of rt_trace_interval calls over
+ *              [level_dist[m], level_dist[m+1]] with max_level = m.
  */
+typedef enum rt_grade_mode { RT_GRADE_BLOCK_ENTRY = 0, RT_GRADE_PATH = 1 } rt_grade_mode;
+
 typedef struct rt_trace_params {
     int32_t mode;
     int32_t max_level;
@@ -207,7 +219,7 @@ typedef struct rt_trace_params {
     int32_t step_cap;
     unsigned long long* d_stats;
     float level_dist[RT_MAX_LEVELS];
-    int32_t reserved_;
+    int32_t grade_mode;
 } rt_trace_params;
 
 typedef struct rt_scene_info {

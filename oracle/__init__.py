@@ -43,7 +43,7 @@ class OrcScene(ctypes.Structure):
         ("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("brick", ctypes.c_int32),
         ("n_levels", ctypes.c_int32), ("n_lam", ctypes.c_int32), ("profile", ctypes.c_int32),
         ("n_lines", ctypes.c_int32), ("n_v", ctypes.c_int32), ("avg_mode", ctypes.c_int32),
-        ("pad_", ctypes.c_int32), ("ds0", ctypes.c_double), ("I0", ctypes.c_double),
+        ("grade_mode", ctypes.c_int32), ("ds0", ctypes.c_double), ("I0", ctypes.c_double),
         ("st_eta", _P), ("st_chi", _P), ("lam", _P), ("lam0", _P), ("eta_star", _P),
         ("chi_star", _P), ("damp", _P), ("inv_dld", _P), ("eta_bg", _P), ("chi_bg", _P),
         ("vel", _P), ("level_dist", _P),
@@ -134,9 +134,11 @@ class Scene:
         self.s = s
         self.level_total = int(lib().orc_level_total(self.dim, _ptr(np.array(self.n, np.int32)), s.n_levels))
 
-    def set_level_dist(self, level_dist):
-        """Distance-graded level cap: level m only in blocks the ray enters at
-        path length >= level_dist[m]; None disables the grading."""
+    def set_level_dist(self, level_dist, mode="entry"):
+        """Distance-graded level cap: level m only where the path length is >= level_dist[m],
+        taken at the ray's entry into each block (mode "entry") or at every point of the ray
+        (mode "path"); None disables the grading."""
+        self.s.grade_mode = {"entry": 0, "path": 1}[mode]
         if level_dist is None:
             self.s.level_dist = None
             return

@@ -43,12 +43,23 @@ def ray_cells_exact(dim, n, pv, w):
     return cells, tin, tout
 
 
-def adapted_cells_exact(dim, n, B, levels, pv, w, level_dist=None):
+def adapted_cells_exact(dim, n, B, levels, pv, w, level_dist=None, grade="entry"):
     """Adapted-grid cells (coarse coords, level, t_in, t_out) from the exact dense list.
 
-    level_dist: level m only in blocks entered at t >= level_dist[m] (exact compare)."""
+    level_dist: level m only where t >= level_dist[m] (exact compare), t being the path
+    length at which the ray entered the block (grade "entry") or that of each point of
+    the ray (grade "path": a voxel piece straddling level_dist[m] is split there)."""
     cells, tin, tout = ray_cells_exact(dim, n, pv, w)
     nb = [int(n[a]) // B for a in range(dim)] + [1] * (3 - dim)
+
+    def cap_at(t):
+        cap = 0
+        for m in range(1, len(level_dist)):
+            if not Fraction(level_dist[m]) <= t:
+                break
+            cap = m
+        return cap
+
     out = []
     cur_blk, cur_cap = None, 127
     for c, a, b in zip(cells, tin, tout):
@@ -56,18 +67,21 @@ def adapted_cells_exact(dim, n, B, levels, pv, w, level_dist=None):
         if blk != cur_blk:
             cur_blk = blk
             if level_dist is not None:
-                cur_cap = 0
-                for m in range(1, len(level_dist)):
-                    if not Fraction(level_dist[m]) <= a:
-                        break
-                    cur_cap = m
-        L = int(levels[blk]) if levels is not None else 0
-        if L < 0:
+                cur_cap = cap_at(a)
+        Lb = int(levels[blk]) if levels is not None else 0
+        if Lb < 0:
             continue
-        L = min(L, cur_cap)
-        cc = [x & ~((1 << L) - 1) for x in c]
-        if out and out[-1][0] == cc and out[-1][1] == L:
-            out[-1][3] = b
-            continue
-        out.append([cc, L, a, b])
+        pieces = [(a, b)]
+        if level_dist is not None and grade == "path":
+            cuts = sorted(set(Fraction(x) for x in level_dist[1:] if a < Fraction(x) < b))
+            ends = [a] + cuts + [b]
+            pieces = list(zip(ends[:-1], ends[1:]))
+        for p0, p1 in pieces:
+            cap = cap_at(p0) if (level_dist is not None and grade == "path") else cur_cap
+            L = min(Lb, cap)
+            cc = [x & ~((1 << L) - 1) for x in c]
+            if out and out[-1][0] == cc and out[-1][1] == L:
+                out[-1][3] = p1
+                continue
+            out.append([cc, L, p0, p1])
     return out

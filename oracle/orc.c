@@ -59,6 +59,7 @@
 enum { ORC_STATIC = 0, ORC_CLASSIC = 1, ORC_VELINTERP = 2, ORC_CAV = 3 };
 enum { ORC_GAUSS = 0, ORC_VOIGT = 1 };
 enum { ORC_AVG_LOG = 0, ORC_AVG_LINEAR = 1 };
+enum { ORC_GRADE_ENTRY = 0, ORC_GRADE_PATH = 1 };
 
 typedef struct orc_scene {
     int32_t dim;
@@ -70,7 +71,7 @@ typedef struct orc_scene {
     int32_t n_lines;
     int32_t n_v;        /* velocity nodes (velocity interpolation) */
     int32_t avg_mode;   /* ORC_AVG_LOG / ORC_AVG_LINEAR for stored level values */
-    int32_t pad_;
+    int32_t grade_mode; /* ORC_GRADE_ENTRY / ORC_GRADE_PATH (distance-graded level cap) */
     double ds0;         /* physical side of a MIP-0 voxel */
     double I0;          /* intensity entering at the upwind boundary */
     /* static: [n_lam][level_total] FP64 values of every level (level 0 first) */
@@ -190,10 +191,16 @@ int orc_ray_cells(int32_t dim, const int32_t n[3], const int32_t pv[3], const fl
 /*
  * Distance-graded level cap (near field at full resolution): level_dist[m]
  * (m = 1 .. n_levels-1, nullable) is the path length from the probe beyond
- * which level m may be used.  A block's level is capped by the largest m with
- * level_dist[m] <= t_entry, t_entry the path length at which the ray enters
- * the block (0 for the probe's own block), following the per-cascade MIP caps
- * of Sect. 4.1 (full resolution near the probe, coarser proxies further out).
+ * which level m may be used, following the per-cascade MIP caps of Sect. 4.1
+ * (full resolution near the probe, coarser proxies further out).  The cap is
+ * the largest m with level_dist[1..m] <= t, taken
+ *   ORC_GRADE_ENTRY: at t = t_entry, the path length at which the ray enters
+ *                    the block (0 for the probe's own block), for the whole
+ *                    block;
+ *   ORC_GRADE_PATH:  at every point of the ray, so the cap rises exactly at
+ *                    t = level_dist[m] (the cascade intervals of Sect. 4.1,
+ *                    whose caps hold along the interval's path length); a
+ *                    voxel piece that straddles level_dist[m] is split there.
  */
 static int graded_cap(const orc_scene* s, const double* level_dist, double t_entry)
 {
@@ -215,35 +222,57 @@ int orc_ray_segments_graded(const orc_scene* s, const int8_t* levels, const doub
     int B = s->brick;
     int32_t nb[3] = {1, 1, 1};
     for (int a = 0; a < s->dim; ++a) nb[a] = s->n[a] / B;
+    const int by_path = levels && level_dist && s->grade_mode == ORC_GRADE_PATH;
     int cnt = 0;
     int64_t cur_b = -1;
     int cur_cap = 127;
     for (int i = 0; i < nd; ++i) {
         const int32_t* c = scratch_cell + 3 * i;
-        int L = 0;
+        int Lb = 0;
         if (levels) {
             int64_t b = c[0] / B + (int64_t)nb[0] * (c[1] / B + (int64_t)nb[1] * (c[2] / B));
             if (b != cur_b) {
                 cur_b = b;
                 cur_cap = graded_cap(s, level_dist, scratch_tin[i]);
             }
-            L = levels[b];
-            if (L < 0) continue;
-            if (L > cur_cap) L = cur_cap;
+            Lb = levels[b];
+            if (Lb < 0) continue;
         }
-        int32_t cc[3];
-        for (int a = 0; a < 3; ++a) cc[a] = c[a] & ~((1 << L) - 1);
-        if (cnt > 0 && lvl[cnt - 1] == L && cell[3 * (cnt - 1)] == cc[0] && cell[3 * (cnt - 1) + 1] == cc[1] &&
-            cell[3 * (cnt - 1) + 2] == cc[2]) {
-            tout[cnt - 1] = scratch_tout[i];
-            continue;
+        /* sub-pieces: the voxel piece, split at the path-graded boundaries inside it */
+        double cut[8];
+        int nc = 0;
+        cut[nc++] = scratch_tin[i];
+        if (by_path)
+            for (int m = 1; m < s->n_levels && nc < 7; ++m)
+                if (level_dist[m] > scratch_tin[i] && level_dist[m] < scratch_tout[i]) cut[nc++] = level_dist[m];
+        for (int x = 1; x < nc; ++x) /* sort the cuts (level_dist need not increase) */
+            for (int y = x; y > 1 && cut[y] < cut[y - 1]; --y) {
+                double tmp = cut[y];
+                cut[y] = cut[y - 1];
+                cut[y - 1] = tmp;
+            }
+        cut[nc] = scratch_tout[i];
+        for (int q = 0; q < nc; ++q) {
+            if (!(cut[q + 1] > cut[q])) continue;
+            int L = Lb;
+            if (levels) {
+                const int cp = by_path ? graded_cap(s, level_dist, cut[q]) : cur_cap;
+                if (L > cp) L = cp;
+            }
+            int32_t cc[3];
+            for (int a = 0; a < 3; ++a) cc[a] = c[a] & ~((1 << L) - 1);
+            if (cnt > 0 && lvl[cnt - 1] == L && cell[3 * (cnt - 1)] == cc[0] && cell[3 * (cnt - 1) + 1] == cc[1] &&
+                cell[3 * (cnt - 1) + 2] == cc[2]) {
+                tout[cnt - 1] = cut[q + 1];
+                continue;
+            }
+            if (cnt >= cap) return -1;
+            for (int a = 0; a < 3; ++a) cell[3 * cnt + a] = cc[a];
+            lvl[cnt] = L;
+            tin[cnt] = cut[q];
+            tout[cnt] = cut[q + 1];
+            ++cnt;
         }
-        if (cnt >= cap) return -1;
-        for (int a = 0; a < 3; ++a) cell[3 * cnt + a] = cc[a];
-        lvl[cnt] = L;
-        tin[cnt] = scratch_tin[i];
-        tout[cnt] = scratch_tout[i];
-        ++cnt;
     }
     return cnt;
 }

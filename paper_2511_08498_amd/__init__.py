@@ -63,7 +63,10 @@ class RtBuildParams(ctypes.Structure):
 class RtTraceParams(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("max_level", ctypes.c_int32), ("I0", ctypes.c_float),
                 ("step_cap", ctypes.c_int32), ("d_stats", _P), ("level_dist", ctypes.c_float * 5),
-                ("reserved_", ctypes.c_int32)]
+                ("grade_mode", ctypes.c_int32)]
+
+
+GRADE = {"entry": 0, "path": 1}
 
 
 # Level m only beyond 1.5 x 4^m voxels: the paper's cascade caps [0,0,1,2,3,4]
@@ -313,8 +316,9 @@ class Scene:
         _check(lib().rt_scene_build(self.h, ctypes.byref(p), int(lam_begin), int(lam_end), _stream(stream)))
         self.batch = (int(lam_begin), int(lam_end))
 
-    def _tparams(self, mode, max_level, I0, step_cap, stats, level_dist=None):
+    def _tparams(self, mode, max_level, I0, step_cap, stats, level_dist=None, grade="entry"):
         p = RtTraceParams()
+        p.grade_mode = GRADE[grade]
         p.mode = MODE[mode]
         p.max_level = int(max_level)
         p.I0 = float(I0)
@@ -327,7 +331,7 @@ class Scene:
         return p
 
     def trace(self, dirs, probes=None, mode="vlm", I0=0.0, max_level=-1, step_cap=0, out=None, stats=None,
-              level_dist=None, stream=None):
+              level_dist=None, grade="entry", stream=None):
         """I[n_dir][batch wavelengths][n_probes] (float32, device)."""
         torch = self.torch
         td = dirs if isinstance(dirs, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(dirs, np.float32))
@@ -342,7 +346,7 @@ class Scene:
         nl = self.batch[1] - self.batch[0]
         if out is None:
             out = torch.empty((td.shape[0], nl, n_probes), dtype=torch.float32, device=self.device)
-        p = self._tparams(mode, max_level, I0, step_cap, stats, level_dist)
+        p = self._tparams(mode, max_level, I0, step_cap, stats, level_dist, grade)
         _check(lib().rt_trace(self.h, ctypes.byref(p), td.data_ptr(), int(td.shape[0]),
                               tp.data_ptr() if tp is not None else None, int(n_probes), out.data_ptr(),
                               _stream(stream)))
@@ -350,7 +354,7 @@ class Scene:
         return out
 
     def trace_interval(self, dirs, t1, t2, probes=None, mode="vlm", I0=0.0, max_level=-1, step_cap=0,
-                       level_dist=None, want_T=True, out=None, out_T=None, stats=None, stream=None):
+                       level_dist=None, grade="entry", want_T=True, out=None, out_T=None, stats=None, stream=None):
         """Radiance interval [t1, t2] of every ray (rt_trace_interval): (I, T) [n_dir][batch][n_probes]
         (T is None when want_T is false)."""
         torch = self.torch
@@ -369,7 +373,7 @@ class Scene:
             out_T = torch.empty((nd, nl, n_probes), dtype=torch.float32, device=self.device)
         if not want_T:
             out_T = None
-        p = self._tparams(mode, max_level, I0, step_cap, stats, level_dist)
+        p = self._tparams(mode, max_level, I0, step_cap, stats, level_dist, grade)
         _check(lib().rt_trace_interval(self.h, ctypes.byref(p), td.data_ptr(), nd,
                                        tp.data_ptr() if tp is not None else None, int(n_probes), float(t1),
                                        float(t2), out.data_ptr(), out_T.data_ptr() if out_T is not None else None,
@@ -378,7 +382,7 @@ class Scene:
         return out, out_T
 
     def trace_truncated(self, dirs, t_trunc, gen=True, fallback=None, probes=None, mode="vlm", I0=0.0,
-                        max_level=-1, step_cap=0, level_dist=None, stream=None):
+                        max_level=-1, step_cap=0, level_dist=None, grade="entry", stream=None):
         """Truncated trace (rt_trace_truncated).  Returns a dict of device tensors:
         I_near, T_near, I_far (generation mode only) [n_dir][batch][n_probes],
         feat [n_dir][n_probes][4] (truncation point x, y, z, query flag) and
@@ -400,7 +404,7 @@ class Scene:
         fb = None
         if fallback is not None:
             fb = fallback.to(device=self.device, dtype=torch.uint8).contiguous()
-        p = self._tparams(mode, max_level, I0, step_cap, None, level_dist)
+        p = self._tparams(mode, max_level, I0, step_cap, None, level_dist, grade)
         _check(lib().rt_trace_truncated(self.h, ctypes.byref(p), float(t_trunc), 1 if gen else 0,
                                         fb.data_ptr() if fb is not None else None, td.data_ptr(), nd,
                                         tp.data_ptr() if tp is not None else None, int(n_probes),
@@ -411,7 +415,7 @@ class Scene:
         return out
 
     def trace_j(self, dirs, weights=None, probes=None, mode="vlm", I0=0.0, max_level=-1, step_cap=0,
-                level_dist=None, with_psi=True, chunked=True, J=None, psi=None, stream=None):
+                level_dist=None, grade="entry", with_psi=True, chunked=True, J=None, psi=None, stream=None):
         """Angle-integrated trace (rt_trace_j): J[batch][n_probes] = sum_d w_d I_d and, with_psi,
         psi = sum_d w_d (1 - exp(-tau of the first segment)).  weights default to 1/n_dir."""
         torch = self.torch
@@ -441,7 +445,7 @@ class Scene:
             wb = v.value
             if wb:
                 work = torch.empty(wb // 4, dtype=torch.float32, device=self.device)
-        p = self._tparams(mode, max_level, I0, step_cap, None, level_dist)
+        p = self._tparams(mode, max_level, I0, step_cap, None, level_dist, grade)
         _check(lib().rt_trace_j(self.h, ctypes.byref(p), td.data_ptr(), tw.data_ptr(), nd,
                                 tp.data_ptr() if tp is not None else None, int(n_probes), J.data_ptr(),
                                 psi.data_ptr() if with_psi else None, work.data_ptr() if work is not None else None,
@@ -484,14 +488,15 @@ class Scene:
         _check(lib().rt_scene_cell_values(self.h, c.shape[0], _np_ptr(c), _np_ptr(out)))
         return out
 
-    def visited(self, probe_vox, w, mode="vlm", max_level=-1, step_cap=0, cap=None, level_dist=None, stream=None):
+    def visited(self, probe_vox, w, mode="vlm", max_level=-1, step_cap=0, cap=None, level_dist=None, grade="entry",
+                stream=None):
         cap = cap or (sum(self.n) + 16)
         cells = np.zeros((cap, 4), np.int32)
         tt = np.zeros((cap, 2), np.float64)
         cnt = ctypes.c_int32(0)
         wd = np.zeros(3, np.float32)
         wd[: self.dim] = np.asarray(w, np.float32)[: self.dim]
-        p = self._tparams(mode, max_level, 0.0, step_cap, None, level_dist)
+        p = self._tparams(mode, max_level, 0.0, step_cap, None, level_dist, grade)
         _check(lib().rt_debug_visited(self.h, ctypes.byref(p), int(probe_vox), _np_ptr(wd), int(cap),
                                       _np_ptr(cells), _np_ptr(tt), ctypes.byref(cnt), _stream(stream)))
         k = cnt.value
@@ -525,7 +530,7 @@ def _batch_jobs(jobs):
         arr[i].n_dir = int(d.shape[0])
         arr[i].d_I = o.data_ptr()
         arr[i].params = sc._tparams(j.get("mode", "vlm"), j.get("max_level", -1), j.get("I0", 0.0),
-                                    j.get("step_cap", 0), None, j.get("level_dist"))
+                                    j.get("step_cap", 0), None, j.get("level_dist"), j.get("grade", "entry"))
     return arr, keep
 
 

@@ -367,7 +367,7 @@ TraceLaunch rt::make_trace(const rt_scene* sc, const rt_trace_params* p)
     t.graded = 0;
     for (int m = 0; m < kMaxLevels; ++m) {
         t.level_dist[m] = m == 0 ? 0.f : p->level_dist[m];
-        if (m > 0 && p->level_dist[m] != 0.f) t.graded = 1;
+        if (m > 0 && p->level_dist[m] != 0.f) t.graded = p->grade_mode == RT_GRADE_PATH ? 2 : 1;
     }
     int cap = 16;
     for (int a = 0; a < g.dim; ++a) cap += 2 * g.n[a];
@@ -398,6 +398,8 @@ rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_
     if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
     for (int m = 1; m < RT_MAX_LEVELS; ++m)
         if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
+    if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
+        return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
     const long long all = (long long)sc->n_active * sc->g.bvox;
     if (!d_probes && n_probes != all)
         return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
@@ -428,6 +430,8 @@ rt_status rt_trace_interval(const rt_scene* sc, const rt_trace_params* p, const 
     if (!(t2 >= t1)) return fail(RT_E_ARG, "t2 must be >= t1 (got t1 = %g, t2 = %g)", t1, t2);
     for (int m = 1; m < RT_MAX_LEVELS; ++m)
         if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
+    if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
+        return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
     const long long all = (long long)sc->n_active * sc->g.bvox;
     if (!d_probes && n_probes != all)
         return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
@@ -487,6 +491,8 @@ rt_status rt_trace_j(const rt_scene* sc, const rt_trace_params* p, const float* 
     if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
     for (int m = 1; m < RT_MAX_LEVELS; ++m)
         if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
+    if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
+        return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
     const long long all = (long long)sc->n_active * sc->g.bvox;
     if (!d_probes && n_probes != all)
         return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
@@ -541,6 +547,8 @@ rt_status rt_trace_truncated(const rt_scene* sc, const rt_trace_params* p, float
     if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace_truncated before rt_scene_build");
     if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
     if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
+    if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
+        return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
     if (sc->g.nblocks >= (1ll << 24)) return fail(RT_E_UNSUPPORTED, "truncated march needs fewer than 2^24 blocks");
     const long long all = (long long)sc->n_active * sc->g.bvox;
     if (!d_probes && n_probes != all) return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld", all);
@@ -639,6 +647,8 @@ rt_status rt_debug_visited(const rt_scene* sc, const rt_trace_params* p, int32_t
     if (!sc || !p || !h_dir || !h_cells || !h_t || !h_count || cap < 1) return fail(RT_E_ARG, "bad argument");
     if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
     if (probe_vox < 0 || probe_vox >= sc->in.nvox) return fail(RT_E_ARG, "probe outside the grid");
+    if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
+        return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
     hipStream_t s = (hipStream_t)stream;
     TraceLaunch t = make_trace(sc, p);
     int32_t* dc = nullptr;
@@ -747,6 +757,8 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
         if (J.n_dir < 1) return fail(RT_E_ARG, "job %d: n_dir must be >= 1", j);
         const rt_trace_params& tp = J.params;
         if (tp.mode != RT_TRACE_LEVEL0 && tp.mode != RT_TRACE_VLM) return fail(RT_E_ARG, "job %d: bad mode", j);
+        if (tp.grade_mode != RT_GRADE_BLOCK_ENTRY && tp.grade_mode != RT_GRADE_PATH)
+            return fail(RT_E_ARG, "job %d: bad grade_mode", j);
         TraceLaunch t = make_trace(sc, &tp);
         BatchJob& b = bj[(size_t)j];
         std::memset(&b, 0, sizeof(b));

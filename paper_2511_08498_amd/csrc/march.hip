@@ -64,12 +64,45 @@ __device__ __forceinline__ int graded_cap(const float* ld, int nlev, double d2, 
     return cap;
 }
 
+// Path-graded cap at path length t: the largest m with ld[1..m] <= t.
+__device__ __forceinline__ int path_cap(const float* ld, int nlev, double t)
+{
+    int cap = 0;
+    for (int m = 1; m < nlev; ++m) {
+        if (!((double)ld[m] <= t)) break;
+        cap = m;
+    }
+    return cap;
+}
+
+// MIP-0 coordinate on axis a (step sign st, |w_a| = aw) of the point x(t) of the
+// ray from the voxel centre pv, in the cell the ray moves into when x(t) lies on
+// a face.  Plane j >= 1 lies at doubled distance 2j - 1 from the centre and is
+// crossed by t iff 2j - 1 <= 2 t |w_a|; an fma rounds once, so its sign is that
+// of the exact difference, and floor(t |w_a| + 1/2) is at most one too high.
+// Returns false when the point is past the grid on this axis.
+__device__ __forceinline__ bool mip0_coord(int pva, int st, double aw, double t, int na, int& ca)
+{
+    if (st == 0) {
+        ca = pva;
+        return true;
+    }
+    const double e = floor(fma(t, aw, 0.5));
+    if (!(e <= (double)na + 2.0)) return false;
+    int nj = (int)e;
+    if (nj > 0 && fma(-2.0 * t, aw, (double)(2 * nj - 1)) > 0.0) --nj;
+    ca = pva + st * nj;
+    return (unsigned)ca < (unsigned)na;
+}
+
 // Traverses the adapted grid from voxel centre pv upwind along -w.  Calls
 // vis.seg(c, level, block, t0, t1) for every non-empty cell in order of
 // increasing t.  Returns 0 when the ray left the grid, 1 at the step cap and
 // 2 when the visitor asked to stop (truncated march).
-// With `graded`, a block's level is also capped by the path length at which
-// the ray enters it (ld: level_dist).
+// graded = 1: a block's level is also capped by the path length at which the
+// ray enters it (ld: level_dist); graded = 2: capped by the path length of each
+// point, so the cap rises at t = ld[m] inside a cell, where the cell is split
+// and the ray re-located at the new level.
 // With Iv, only the path interval [t_lo, t_hi] is traversed (a radiance
 // interval): the start cell is the one holding x(t_lo) (on a plane, the one the
 // ray moves into), the last segment ends at t_hi, and a plane crossed exactly
@@ -80,57 +113,51 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
                                     const float* ld, const int* pv, const float* wf, int step_cap, Vis& vis,
                                     Counters& cnt, double t_lo = 0.0, double t_hi = 0.0)
 {
-    int p2[3], st[3], c[3], k[3], bc[3];
-    double aw[3], iw[3], ws[3], dd[3];  // dd: |p2 - 2 k| (twice the distance to the next plane), exact
+    // Per axis: the doubled centre p2 = 2 p (odd), the step sign st, the cell c at the current
+    // level (size vs); the next plane is k = c + (st > 0 ? vs : 0), and dd = |p2 - 2 k| (twice the
+    // distance to it) is kept exactly.  |w_a| is kept in FP32 (exact when widened to FP64).
+    int p2[3], st[3], c[3];
+    float af[3];
+    double iw[3], dd[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         p2[a] = 1;
         st[a] = 0;
         c[a] = 0;
-        k[a] = 0;
-        bc[a] = 0;
-        aw[a] = 0.0;
+        af[a] = 0.f;
         iw[a] = 0.0;
-        ws[a] = 0.0;
         dd[a] = 1.0;
     }
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         p2[a] = 2 * pv[a] + 1;
-        ws[a] = (double)wf[a];
-        aw[a] = fabs(ws[a]);
-        iw[a] = aw[a] > 0.0 ? 0.5 / aw[a] : 0.0;  // half the reciprocal: t = dd iw
+        af[a] = fabsf(wf[a]);
+        iw[a] = af[a] > 0.f ? 0.5 / (double)af[a] : 0.0;  // half the reciprocal: t = dd iw
         st[a] = wf[a] > 0.f ? -1 : (wf[a] < 0.f ? 1 : 0);
-        bc[a] = pv[a] >> g.log2B;
     }
     int c0[3] = {pv[0], pv[1], pv[2]};
     double t = 0.0;
     if constexpr (Iv) {
-        // MIP-0 cell at t_lo: plane j >= 1 of axis a lies at doubled distance 2j - 1 from the
-        // centre and is crossed by t_lo iff 2j - 1 <= 2 t_lo |w_a|.  An fma rounds once, so its
-        // sign is that of the exact difference; floor(t_lo |w_a| + 1/2) is at most one too high.
-        const double tw = 2.0 * t_lo;
-        bool gone = false;
+        // MIP-0 cell at t_lo
+        bool in = true;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-            if (st[a] == 0) continue;
-            const double e = floor(fma(t_lo, aw[a], 0.5));
-            if (!(e <= (double)g.n[a] + 2.0)) {
-                gone = true;
-                continue;
-            }
-            int nj = (int)e;
-            if (nj > 0 && fma(-tw, aw[a], (double)(2 * nj - 1)) > 0.0) --nj;
-            c0[a] = pv[a] + st[a] * nj;
-            gone = gone || (unsigned)c0[a] >= (unsigned)g.n[a];
-            bc[a] = c0[a] >> g.log2B;
-        }
-        if (gone) return 4;
+        for (int a = 0; a < D; ++a) in = mip0_coord(pv[a], st[a], (double)af[a], t_lo, g.n[a], c0[a]) && in;
+        if (!in) return 4;
         t = t_lo;
     }
-    long long blk = bc[0] + (long long)g.nb[0] * (bc[1] + (long long)g.nb[1] * bc[2]);
+    // path-graded cap and the path length at which it next rises
+    int capp = 127;
+    float tb = INFINITY;  // a level_dist value (FP32, exact in FP64)
+    if (graded == 2) {
+        capp = path_cap(ld, g.n_levels, t);
+        tb = capp + 1 < g.n_levels ? ld[capp + 1] : INFINITY;
+    }
+    long long blk = (c0[0] >> g.log2B) +
+                    (long long)g.nb[0] * ((c0[1] >> g.log2B) + (long long)g.nb[1] * (c0[2] >> g.log2B));
     int cap0 = maxl;
-    if (graded) {
+    if (graded == 2) {
+        cap0 = capp < maxl ? capp : maxl;
+    } else if (graded) {
         int cg = 0;
         if constexpr (Iv) {
             // the start block was entered when the ray crossed the last of its entry faces
@@ -138,12 +165,13 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             double dn = 0.0, an = 1.0;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                if (st[a] == 0 || bc[a] == (pv[a] >> g.log2B)) continue;
-                const int kf = (st[a] > 0 ? bc[a] : bc[a] + 1) << g.log2B;
+                const int ba = c0[a] >> g.log2B;
+                if (st[a] == 0 || ba == (pv[a] >> g.log2B)) continue;
+                const int kf = (st[a] > 0 ? ba : ba + 1) << g.log2B;
                 const double df = (double)abs(p2[a] - 2 * kf);
-                if (df * an > dn * aw[a]) {
+                if (df * an > dn * (double)af[a]) {
                     dn = df;
-                    an = aw[a];
+                    an = (double)af[a];
                 }
             }
             cg = graded_cap(ld, g.n_levels, dn, an);
@@ -155,13 +183,15 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         }
         cap0 = cg < maxl ? cg : maxl;
     }
-    int lvl = block_level(sts, blk, mode, cap0);
+    // path grading: lraw is the block's level before the path cap; the cap binds only where
+    // lraw > capp, and only there can its rise at tb change the level
+    int lraw = graded == 2 ? block_level(sts, blk, mode, maxl) : 0;
+    int lvl = graded == 2 ? (lraw < capp ? lraw : capp) : block_level(sts, blk, mode, cap0);
     int vs = lvl < 0 ? g.B : (1 << lvl);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
         c[a] = c0[a] & ~(vs - 1);
-        k[a] = c[a] + (st[a] > 0 ? vs : 0);
-        dd[a] = (double)abs(p2[a] - 2 * k[a]);
+        dd[a] = (double)abs(p2[a] - 2 * (c[a] + (st[a] > 0 ? vs : 0)));
     }
     for (int step = 0; step < step_cap; ++step) {
         int s0;
@@ -170,7 +200,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         if constexpr (D == 2) {
             // axis a crosses first iff dd_a |w_b| < dd_b |w_a|; an axis with w_a = 0 has a zero
             // product on the right and never wins, so no special case is needed
-            const double lhs = dd[0] * aw[1], rhs = dd[1] * aw[0];
+            const double lhs = dd[0] * (double)af[1], rhs = dd[1] * (double)af[0];
             const bool x0 = lhs <= rhs, x1 = rhs <= lhs;
             tie = (x0 ? 1u : 0u) | (x1 ? 2u : 0u);
             s0 = x0 ? 0 : 1;
@@ -185,8 +215,8 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
                     s0 = a;
                     tie = 1u << a;
                 } else {
-                    double lhs = dd[a] * aw[s0];
-                    double rhs = dd[s0] * aw[a];
+                    double lhs = dd[a] * (double)af[s0];
+                    double rhs = dd[s0] * (double)af[a];
                     if (lhs < rhs) {
                         s0 = a;
                         tie = 1u << a;
@@ -198,23 +228,46 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             tn = dd[s0] * iw[s0];
         }
         const double d2s0 = dd[s0];
-        if constexpr (Iv) {
-            // next crossing beyond t_hi (exact sign): the interval ends inside this cell
-            if (fma(-2.0 * t_hi, aw[s0], d2s0) > 0.0) {
-                if (lvl >= 0) {
-                    if (t_hi > t && vis.seg(c, lvl, blk, t, t_hi)) return 2;
-                    ++cnt.segs;
-                } else {
-                    ++cnt.empty;
-                }
-                return 3;
-            }
+        const double aws = (double)af[s0];
+        // the segment ends at the next crossing, unless the path-graded cap rises first (ev 1:
+        // the cell is split at tb) or the interval ends first (ev 2); both tests are exact in sign
+        int ev = 0;
+        double te = tn;
+        if (graded == 2 && lraw > capp && (!Iv || (double)tb < t_hi) && fma(-2.0 * (double)tb, aws, d2s0) > 0.0) {
+            ev = 1;
+            te = (double)tb;
+        } else if (Iv && fma(-2.0 * t_hi, aws, d2s0) > 0.0) {
+            ev = 2;
+            te = t_hi;
         }
         if (lvl >= 0) {
-            if (vis.seg(c, lvl, blk, t, tn)) return 2;
-            ++cnt.segs;
+            if (ev == 0 || te > t) {
+                if (vis.seg(c, lvl, blk, t, te)) return 2;
+                ++cnt.segs;
+            }
         } else {
             ++cnt.empty;
+        }
+        if (ev != 0) {
+            if (ev == 2) return 3;
+            // the cap rises at t = tb and binds here, so the level rises: re-locate from x(t),
+            // which lies in the current cell
+            t = te;
+            capp = path_cap(ld, g.n_levels, t);
+            tb = capp + 1 < g.n_levels ? ld[capp + 1] : INFINITY;
+            const int nl = lraw < capp ? lraw : capp;
+            ++cnt.lvlchg;
+            const int nvs = 1 << nl;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                int ca = c[a];
+                mip0_coord(pv[a], st[a], (double)af[a], t, g.n[a], ca);
+                c[a] = ca & ~(nvs - 1);
+                dd[a] = (double)abs(p2[a] - 2 * (c[a] + (st[a] > 0 ? nvs : 0)));
+            }
+            lvl = nl;
+            vs = nvs;
+            continue;
         }
         t = tn;
         // advance the crossing axes (branch-free: the other axes add 0 and keep their block)
@@ -223,35 +276,42 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         for (int a = 0; a < D; ++a) {
             const bool sa = (tie >> a) & 1u;
             const int sv = sa ? st[a] * vs : 0;
+            const int cold = c[a];
             c[a] += sv;
-            k[a] += sv;
             dd[a] += sa ? (double)(2 * vs) : 0.0;
             out = out || (unsigned)c[a] >= (unsigned)g.n[a];
-            const int nbc = c[a] >> g.log2B;
-            bchg = bchg || nbc != bc[a];
-            bc[a] = nbc;
+            bchg = bchg || (c[a] >> g.log2B) != (cold >> g.log2B);
         }
         if (out) return 0;
         if (bchg) {
-            blk = bc[0] + (long long)g.nb[0] * (bc[1] + (long long)g.nb[1] * bc[2]);
-            int capb = maxl;
-            if (graded) {
-                int cg = graded_cap(ld, g.n_levels, d2s0, aw[s0]);
-                capb = cg < maxl ? cg : maxl;
+            blk = (c[0] >> g.log2B) +
+                  (long long)g.nb[0] * ((c[1] >> g.log2B) + (long long)g.nb[1] * (c[2] >> g.log2B));
+            int nl;
+            if (graded == 2) {
+                // the path cap at the crossing (exact), and the new block's level under it
+                capp = graded_cap(ld, g.n_levels, d2s0, aws);
+                tb = capp + 1 < g.n_levels ? ld[capp + 1] : INFINITY;
+                lraw = block_level(sts, blk, mode, maxl);
+                nl = lraw < capp ? lraw : capp;
+            } else {
+                int capb = maxl;
+                if (graded) {
+                    int cg = graded_cap(ld, g.n_levels, d2s0, aws);
+                    capb = cg < maxl ? cg : maxl;
+                }
+                nl = block_level(sts, blk, mode, capb);
             }
-            int nl = block_level(sts, blk, mode, capb);
             if (nl != lvl) {
                 ++cnt.lvlchg;
                 int nvs = nl < 0 ? g.B : (1 << nl);
 #pragma unroll
                 for (int a = 0; a < D; ++a) {
-                    // a crossing axis re-locates from the plane just crossed, k - st vs
-                    if ((tie >> a) & 1u) c[a] = (st[a] > 0 ? k[a] - vs : k[a] + vs - 1) & ~(nvs - 1);
+                    // a crossing axis re-locates from the voxel next to the plane just crossed
+                    if ((tie >> a) & 1u) c[a] = (st[a] > 0 ? c[a] : c[a] + vs - 1) & ~(nvs - 1);
                     else if (st[a] == 0) c[a] = pv[a] & ~(nvs - 1);
                     else if (nvs >= vs) c[a] &= ~(nvs - 1);
-                    else c[a] = fine_cell(p2[a], ws[a], aw[s0], d2s0, c[a], vs, nvs, st[a]);
-                    k[a] = c[a] + (st[a] > 0 ? nvs : 0);
-                    dd[a] = (double)abs(p2[a] - 2 * k[a]);
+                    else c[a] = fine_cell(p2[a], (double)wf[a], aws, d2s0, c[a], vs, nvs, st[a]);
+                    dd[a] = (double)abs(p2[a] - 2 * (c[a] + (st[a] > 0 ? nvs : 0)));
                 }
                 lvl = nl;
                 vs = nvs;
@@ -544,7 +604,7 @@ struct AccJ {
 template <int D, typename T, class Acc = AccPlain>
 struct VisStatic {
     using AccT = Acc;
-    static constexpr int kMinWaves = 1;
+    static constexpr int kMinWaves = (!Acc::kTrunc && !Acc::kJ) ? 4 : 1;
     const Geo* g;
     const int32_t* slot;
     const T* vals;
@@ -582,7 +642,7 @@ struct VisStatic {
 template <int D, class Acc = AccPlain>
 struct VisVelinterp {
     using AccT = Acc;
-    static constexpr int kMinWaves = 1;
+    static constexpr int kMinWaves = (D == 2 && !Acc::kTrunc && !Acc::kJ) ? 4 : 1;
     const TraceLaunch* tl;
     long long cur_blk;
     long long base;
@@ -632,11 +692,13 @@ struct VisVelinterp {
     }
 };
 
-template <int D, typename T = float, class Acc = AccPlain>
+// NL: lines the kernel is compiled for (2 or kMaxLines); scenes with up to two
+// lines use NL = 2, which halves the per-segment line state and code.
+template <int D, typename T = float, class Acc = AccPlain, int NL = kMaxLines>
 struct VisCav {
     using AccT = Acc;
     // the plain 3D march needs a few registers more than three waves per SIMD allow
-    static constexpr int kMinWaves = (D == 3 && !Acc::kTrunc && !Acc::kJ) ? 3 : 1;
+    static constexpr int kMinWaves = (Acc::kTrunc || Acc::kJ) ? 1 : (D == 2 && NL == 2) ? 4 : (D == 3 ? 3 : 1);
     const TraceLaunch* tl;
     long long cur_blk;
     long long base;
@@ -663,9 +725,9 @@ struct VisCav {
         long long cell = base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D);
         const T* r = (const T*)(sizeof(T) == 4 ? (const void*)tl->cav : tl->cav_lp) + cell * tl->cav_rec;
         const int nln = tl->lb.n_lines;
-        float ls[kMaxLines][4];
+        float ls[NL][4];
 #pragma unroll
-        for (int k = 0; k < kMaxLines; ++k) {
+        for (int k = 0; k < NL; ++k) {
             if (k < nln) {
                 float4 q = load4<T>(r, k);
                 ls[k][0] = q.x;
@@ -684,7 +746,7 @@ struct VisCav {
         for (int l = 0; l < kLam; ++l) {
             float ee = bgv.x, xx = bgv.y;
 #pragma unroll
-            for (int k = 0; k < kMaxLines; ++k) {
+            for (int k = 0; k < NL; ++k) {
                 if (k < nln) {
                     // per-batch constants lam - lam0, lam / lam0, lam0 / c: scalar kernel arguments
                     float x = fmaf(tl->lb.k0[k], u, tl->lb.dl[l][k]) * ls[k][3];
@@ -941,6 +1003,21 @@ static hipError_t launch_one(const TraceLaunch& t, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int D, class Acc, int NL>
+static hipError_t launch_cav_nl(const TraceLaunch& t, hipStream_t s)
+{
+    if (t.storage == RT_F32) return launch_one<D, VisCav<D, float, Acc, NL>>(t, s);
+    if (t.storage == RT_BF16) return launch_one<D, VisCav<D, __hip_bfloat16, Acc, NL>>(t, s);
+    return launch_one<D, VisCav<D, __half, Acc, NL>>(t, s);
+}
+
+template <int D, class Acc>
+static hipError_t launch_cav(const TraceLaunch& t, hipStream_t s)
+{
+    if (t.lb.n_lines <= 2) return launch_cav_nl<D, Acc, 2>(t, s);
+    return launch_cav_nl<D, Acc, kMaxLines>(t, s);
+}
+
 template <class Acc>
 static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
 {
@@ -959,13 +1036,9 @@ static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
         return launch_one<3, VisVelinterp<3, Acc>>(t, s);
     }
     if (t.g.dim == 2) {
-        if (t.storage == RT_F32) return launch_one<2, VisCav<2, float, Acc>>(t, s);
-        if (t.storage == RT_BF16) return launch_one<2, VisCav<2, __hip_bfloat16, Acc>>(t, s);
-        return launch_one<2, VisCav<2, __half, Acc>>(t, s);
+        return launch_cav<2, Acc>(t, s);
     }
-    if (t.storage == RT_F32) return launch_one<3, VisCav<3, float, Acc>>(t, s);
-    if (t.storage == RT_BF16) return launch_one<3, VisCav<3, __hip_bfloat16, Acc>>(t, s);
-    return launch_one<3, VisCav<3, __half, Acc>>(t, s);
+    return launch_cav<3, Acc>(t, s);
 }
 
 hipError_t launch_trace(const TraceLaunch& t, hipStream_t s)

@@ -170,3 +170,97 @@ def test_cascade_intervals_lines(rt, emission):
         st = orc.rel_err_stats(I[ok], Ir[ok])
         assert st["n_ref_zero_mismatch"] == 0 and _p100(st) < bound, (c, st)
         _check_T(Tt[ok], Tr[ok], bound, c)
+
+
+def test_path_graded_visited_cells_bit_exact(rt, cfg1):
+    """Path grading: the level cap rises at t = level_dist[m] inside a cell; visited cells and levels equal the
+    oracle's bit for bit, segment ends to 1e-13 (the split points are the schedule's values)."""
+    import math
+    scene = rt.Scene.from_dict(cfg1)
+    scene.build(0, 8, iod_threshold=1.0)
+    s, lv, _, _ = oracle_batch(cfg1, 0, 8, 1.0)
+    assert np.array_equal(scene.levels(), lv)
+    rng = np.random.default_rng(8)
+    probes = scene.probe_voxels()
+    dirs = list(cfg1["dirs"]) + [np.array(v, np.float32) for v in ([1, 0], [0, -1], [math.sqrt(.5), math.sqrt(.5)],
+                                                                  [-0.6, 0.8])]
+    nchk = nsplit = 0
+    for sched in ((0, 6, 24, 96), (0, 2.5, 7, 30), (0, 0, 5, 5)):
+        s.set_level_dist(sched, mode="path")
+        for w in dirs:
+            for pv in rng.choice(probes, 25, replace=False):
+                cells, tt = scene.visited(int(pv), w, mode="vlm", level_dist=sched, grade="path")
+                oc, ol, oti, oto = orc.ray_segments(s, lv, (int(pv) % 64, int(pv) // 64), w)
+                assert len(cells) == len(oc), (sched, pv, w)
+                assert np.array_equal(cells[:, :3], oc) and np.array_equal(cells[:, 3], ol)
+                np.testing.assert_allclose(tt[:, 0], oti, rtol=1e-13, atol=1e-13)
+                np.testing.assert_allclose(tt[:, 1], oto, rtol=1e-13, atol=1e-13)
+                nsplit += int(np.isin(oti, np.array(sched[1:], np.float64)).sum())
+                nchk += 1
+    s.set_level_dist(None)
+    assert nchk > 700 and nsplit > 50
+
+
+def test_path_graded_intensities_and_cascades(rt, cfg1):
+    """Path-graded whole-ray march against the oracle on the same cells, and against the composition of the
+    capped cascade intervals on the GPU (FP32 rounding only)."""
+    import torch
+    dirs = torch.from_numpy(cfg1["dirs"]).cuda()
+    scene = rt.Scene.from_dict(cfg1)
+    probes, vox, d = all_pairs(scene, 8)
+    scene.build(0, 8, iod_threshold=0.1)
+    s, lv, _, _ = oracle_batch(cfg1, 0, 8, 0.1)
+    LD = rt.CASCADE_LEVEL_DIST
+    s.set_level_dist(LD, mode="path")
+    I = scene.trace(dirs, mode="vlm", level_dist=LD, grade="path")
+    ref = _dir_lam_probe(orc.march(s, orc.STATIC, lv, vox, d), 8, probes.size, 8)
+    st = orc.rel_err_stats(I.cpu().numpy(), ref)
+    assert st["n_ref_zero_mismatch"] == 0 and _p100(st) < TOL_SAME_CELLS, st
+    acc = torch.zeros_like(I, dtype=torch.float64)
+    trans = torch.ones_like(acc)
+    for c in range(len(CAPS)):
+        Ic, Tc = scene.trace_interval(dirs, ENDS[c], ENDS[c + 1], mode="vlm", max_level=CAPS[c])
+        acc += trans * Ic.double()
+        trans *= Tc.double()
+    st = orc.rel_err_stats(acc.cpu().numpy(), I.double().cpu().numpy())
+    assert _p100(st) < 5e-5, st
+    # path grading coarsens no later than entry grading: never more segments
+    sp = torch.zeros(5, dtype=torch.int64, device="cuda")
+    se = torch.zeros(5, dtype=torch.int64, device="cuda")
+    scene.trace(dirs, mode="vlm", level_dist=LD, grade="path", stats=sp)
+    scene.trace(dirs, mode="vlm", level_dist=LD, stats=se)
+    assert sp[0].item() <= se[0].item()
+    # the same rule inside an interval: [6, 96] path-graded equals [6, 24] capped at 1 composed with [24, 96] at 2
+    I1, T1 = scene.trace_interval(dirs, 6.0, 96.0, mode="vlm", level_dist=LD, grade="path")
+    Ia, Ta = scene.trace_interval(dirs, 6.0, 24.0, mode="vlm", max_level=1)
+    Ib, Tb = scene.trace_interval(dirs, 24.0, 96.0, mode="vlm", max_level=2)
+    comp = (Ia.double() + Ta.double() * Ib.double()).cpu().numpy()
+    st = orc.rel_err_stats(comp, I1.double().cpu().numpy())
+    assert st["n_ref_zero_mismatch"] == 0 and _p100(st) < 5e-5, st
+    _check_T(T1.cpu().numpy(), (Ta.double() * Tb.double()).cpu().numpy(), 5e-5, "T [6, 96]")
+
+
+@pytest.mark.parametrize("emission", ["velinterp", "cav"])
+def test_path_graded_lines(rt, emission):
+    import torch
+    if emission == "velinterp":
+        sc = make_cfg2(seed=21, n=128, B=16, n_lam_per_line=8, n_dir=8)
+        T, kind, rule, kw = 1e-2, orc.VELINTERP, 0, dict(n_v=21)
+    else:
+        sc = cav_scene()
+        T, kind, rule, kw = 0.1, orc.CAV, 1, {}
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    scene = rt.Scene.from_dict(sc, emission=emission, **kw)
+    k, vox, d = sample_rays(scene, 8, 400, 6)
+    scene.build(0, 8, iod_threshold=T)
+    lv_gpu = scene.levels()
+    lv = oracle_levels(sc, list(range(8)), rule, T)
+    ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
+    assert ok.mean() > 0.8
+    s = orc.Scene(sc, lam_idx=list(range(8)), **kw)
+    s.set_level_dist(rt.CASCADE_LEVEL_DIST, mode="path")
+    I = scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST, grade="path").cpu().numpy()[d, :, k]
+    ref = orc.march(s, kind, lv, vox, d)
+    st = orc.rel_err_stats(I[ok], ref[ok])
+    bound = 1e-4 if emission == "velinterp" else 5e-3
+    assert st["n_ref_zero_mismatch"] == 0 and _p100(st) < bound, st

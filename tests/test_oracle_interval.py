@@ -206,3 +206,66 @@ def test_interval_boundary_intensity_once(orc):
         assert I[0, 0] == want and T[0, 0] == 1.0, (t1, t2)
     with pytest.raises(AssertionError):
         orc.march_interval(s, orc.STATIC, None, vox, d, 3.0, 2.0)
+
+
+@pytest.mark.parametrize("case", ["random2d", "random3d"])
+@pytest.mark.parametrize("sched", [(0, 6, 24, 96, 384), (0, 2.5, 7, 30), (0, 0, 5, 5)])
+def test_path_graded_cells_match_exact(orc, case, sched):
+    """Path grading: the level cap rises exactly at t = level_dist[m], splitting the voxel piece there."""
+    rng = np.random.default_rng({"random2d": 27, "random3d": 28}[case])
+    if case == "random2d":
+        n, B, nl = (64, 64), 16, 5
+        lv = rng.integers(-1, 5, size=16).astype(np.int8)
+    else:
+        n, B, nl = (16, 16, 16), 8, 4
+        lv = rng.integers(-1, 4, size=8).astype(np.int8)
+    dim = len(n)
+    sc = static_scene(n, B, np.zeros((1,) + n), np.zeros((1,) + n), n_levels=nl)
+    s = orc.Scene(sc)
+    s.set_level_dist(sched, mode="path")
+    nsplit = 0
+    for w in _rand_dirs(rng, dim, 8):
+        for _ in range(5):
+            pv = tuple(int(rng.integers(0, n[a])) for a in range(dim))
+            cells, lvl, ti, to = orc.ray_segments(s, lv, pv, w)
+            ex = adapted_cells_exact(dim, n, B, lv, pv, w, level_dist=sched, grade="path")
+            assert len(ex) == len(cells), (pv, w)
+            for i, (cc, L, a, b) in enumerate(ex):
+                assert list(cells[i]) == cc and lvl[i] == L
+                assert ti[i] == pytest.approx(float(a), rel=1e-14, abs=1e-14)
+                assert to[i] == pytest.approx(float(b), rel=1e-14, abs=1e-14)
+                nsplit += any(float(a) == x for x in sched[1:])
+            ent = adapted_cells_exact(dim, n, B, lv, pv, w, level_dist=sched, grade="entry")
+            # entry grading holds each block at the cap of its entry point: never coarser than path grading
+            assert sum(float(b - a) * (1 << L) for _, L, a, b in ent) <= sum(
+                float(b - a) * (1 << L) for _, L, a, b in ex) + 1e-9
+    assert nsplit > 0
+
+
+def test_path_graded_march_is_composed_cascades(orc):
+    """Whole-ray march with path grading {0, 6, 24, 96} = the cascade intervals [0,1.5], [1.5,6], [6,24],
+    [24,96], [96,inf) each capped at its cascade level, composed (I = I_a + T_a I_b)."""
+    sc, s, lv = _cfg1_static(orc)
+    rng = np.random.default_rng(29)
+    vox = rng.integers(0, 4096, size=500).astype(np.int32)
+    d = rng.integers(0, 8, size=500).astype(np.int32)
+    s.set_level_dist((0, 6, 24, 96), mode="path")
+    for I0 in (0.0, 0.4):
+        s.s.I0 = I0
+        I_path = orc.march(s, orc.STATIC, lv, vox, d)
+        s.set_level_dist(None)
+        ends = [0.0] + CASCADE_ENDS[:4] + [np.inf]
+        caps = [0, 0, 1, 2, 3]
+        I, T = np.zeros_like(I_path), np.ones_like(I_path)
+        for c in range(5):
+            Ic, Tc = orc.march_interval(s, orc.STATIC, orc.cap_levels(lv, caps[c]), vox, d, ends[c], ends[c + 1])
+            I += T * Ic
+            T *= Tc
+        np.testing.assert_allclose(I, I_path, rtol=1e-12, atol=1e-300)
+        s.set_level_dist((0, 6, 24, 96), mode="path")
+        # entry grading is a different (coarser-later) rule: it differs on some rays
+        s.set_level_dist((0, 6, 24, 96), mode="entry")
+        I_entry = orc.march(s, orc.STATIC, lv, vox, d)
+        assert np.any(np.abs(I_entry - I_path) > 1e-9 * np.abs(I_path))
+        s.set_level_dist((0, 6, 24, 96), mode="path")
+    s.s.I0 = 0.0
