@@ -386,14 +386,11 @@ TraceLaunch rt::make_trace(const rt_scene* sc, const rt_trace_params* p)
     return t;
 }
 
-extern "C" {
-
-rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, int32_t n_dir,
-                   const int32_t* d_probes, int64_t n_probes, float* d_I, void* stream)
+// Checks shared by the per-direction trace entry points (pointers checked by the caller).
+static rt_status check_trace(const rt_scene* sc, const rt_trace_params* p, int32_t n_dir, const int32_t* d_probes,
+                             int64_t n_probes, const char* who)
 {
-    g_err.clear();
-    if (!sc || !p || !d_dirs || !d_I) return fail(RT_E_ARG, "null argument");
-    if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace before rt_scene_build");
+    if (sc->batch_begin < 0) return fail(RT_E_STATE, "%s before rt_scene_build", who);
     if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
     if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
     for (int m = 1; m < RT_MAX_LEVELS; ++m)
@@ -404,9 +401,20 @@ rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_
     if (!d_probes && n_probes != all)
         return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
     if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
-    if (n_probes == 0) return RT_OK;
     if ((long long)n_dir * ((n_probes + 63) / 64) > (long long)0x7fffffff * 4)
         return fail(RT_E_ARG, "launch too large");
+    return RT_OK;
+}
+
+extern "C" {
+
+rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, int32_t n_dir,
+                   const int32_t* d_probes, int64_t n_probes, float* d_I, void* stream)
+{
+    g_err.clear();
+    if (!sc || !p || !d_dirs || !d_I) return fail(RT_E_ARG, "null argument");
+    rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace");
+    if (st != RT_OK || n_probes == 0) return st;
     TraceLaunch t = make_trace(sc, p);
     t.dirs = d_dirs;
     t.n_dir = n_dir;
@@ -423,22 +431,10 @@ rt_status rt_trace_interval(const rt_scene* sc, const rt_trace_params* p, const 
 {
     g_err.clear();
     if (!sc || !p || !d_dirs || !d_I) return fail(RT_E_ARG, "null argument");
-    if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace_interval before rt_scene_build");
-    if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
-    if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
     if (!(t1 >= 0.0) || !(t1 < INFINITY)) return fail(RT_E_ARG, "t1 must be finite and >= 0 (got %g)", t1);
     if (!(t2 >= t1)) return fail(RT_E_ARG, "t2 must be >= t1 (got t1 = %g, t2 = %g)", t1, t2);
-    for (int m = 1; m < RT_MAX_LEVELS; ++m)
-        if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
-    if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
-        return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
-    const long long all = (long long)sc->n_active * sc->g.bvox;
-    if (!d_probes && n_probes != all)
-        return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
-    if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
-    if (n_probes == 0) return RT_OK;
-    if ((long long)n_dir * ((n_probes + 63) / 64) > (long long)0x7fffffff * 4)
-        return fail(RT_E_ARG, "launch too large");
+    rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace_interval");
+    if (st != RT_OK || n_probes == 0) return st;
     TraceLaunch t = make_trace(sc, p);
     t.dirs = d_dirs;
     t.n_dir = n_dir;
