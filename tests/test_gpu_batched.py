@@ -45,12 +45,13 @@ def scenes(rt):
     return out
 
 
-def eager(scenes, level_dist=None):
-    return [s.trace(d, mode="vlm", level_dist=level_dist).clone() for _, s, d in scenes]
+def eager(scenes, level_dist=None, grade="entry"):
+    return [s.trace(d, mode="vlm", level_dist=level_dist, grade=grade).clone() for _, s, d in scenes]
 
 
-def jobs_for(scenes, outs, level_dist=None):
-    return [dict(scene=s, dirs=d, out=o, mode="vlm", level_dist=level_dist) for (_, s, d), o in zip(scenes, outs)]
+def jobs_for(scenes, outs, level_dist=None, grade="entry"):
+    return [dict(scene=s, dirs=d, out=o, mode="vlm", level_dist=level_dist, grade=grade)
+            for (_, s, d), o in zip(scenes, outs)]
 
 
 def test_batched_equals_single_scene_launches(rt, scenes):
@@ -67,6 +68,22 @@ def test_batched_equals_single_scene_launches(rt, scenes):
     c = claims.cpu().numpy()
     assert c.size == sum(d.shape[0] * ((s.info["n_probes"] + 63) // 64) for _, s, d in scenes)
     assert np.all(c == 1)
+    assert b.device_error() == (0, -1)
+
+
+def test_batched_path_grading_equals_single_scene_launches(rt, scenes):
+    """The cap taken along the path (cascade intervals' rule) in the persistent kernel: the same bits as the
+    single-scene launches, and different from block-entry grading on these scenes."""
+    import torch
+    ref = eager(scenes, rt.CASCADE_LEVEL_DIST, "path")
+    outs = [torch.full_like(r, float("nan")) for r in ref]
+    b = rt.Batch(jobs_for(scenes, outs, rt.CASCADE_LEVEL_DIST, "path"))
+    b.run()
+    torch.cuda.synchronize()
+    for r, o in zip(ref, outs):
+        assert torch.equal(r, o)
+    entry = eager(scenes, rt.CASCADE_LEVEL_DIST, "entry")
+    assert any(not torch.equal(r, e) for r, e in zip(ref, entry))
     assert b.device_error() == (0, -1)
 
 
