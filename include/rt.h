@@ -280,6 +280,7 @@ rt_status rt_scene_build(rt_scene* scene, const rt_build_params* params, int32_t
  *              probes (then n_probes must equal rt_scene_info.n_probes).
  *   d_I        device float [n_dir][lam_end - lam_begin][n_probes]: intensity
  *              arriving at each probe along each direction.
+ * n_probes = 0 traces nothing (d_probes and d_I may then be NULL).
  * Asynchronous.  Errors: RT_E_ARG, RT_E_STATE (no batch built).
  */
 rt_status rt_trace(const rt_scene* scene, const rt_trace_params* params, const float* d_dirs, int32_t n_dir,

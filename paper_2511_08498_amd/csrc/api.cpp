@@ -397,10 +397,11 @@ static rt_status check_trace(const rt_scene* sc, const rt_trace_params* p, int32
         if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
     if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
         return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
+    if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
+    if (n_probes == 0) return RT_OK;  // nothing to trace (probe and output pointers may be null)
     const long long all = (long long)sc->n_active * sc->g.bvox;
     if (!d_probes && n_probes != all)
         return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
-    if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
     if ((long long)n_dir * ((n_probes + 63) / 64) > (long long)0x7fffffff * 4)
         return fail(RT_E_ARG, "launch too large");
     return RT_OK;
@@ -412,7 +413,7 @@ rt_status rt_trace(const rt_scene* sc, const rt_trace_params* p, const float* d_
                    const int32_t* d_probes, int64_t n_probes, float* d_I, void* stream)
 {
     g_err.clear();
-    if (!sc || !p || !d_dirs || !d_I) return fail(RT_E_ARG, "null argument");
+    if (!sc || !p || !d_dirs || (!d_I && n_probes != 0)) return fail(RT_E_ARG, "null argument");
     rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace");
     if (st != RT_OK || n_probes == 0) return st;
     TraceLaunch t = make_trace(sc, p);
@@ -430,7 +431,7 @@ rt_status rt_trace_interval(const rt_scene* sc, const rt_trace_params* p, const 
                             void* stream)
 {
     g_err.clear();
-    if (!sc || !p || !d_dirs || !d_I) return fail(RT_E_ARG, "null argument");
+    if (!sc || !p || !d_dirs || (!d_I && n_probes != 0)) return fail(RT_E_ARG, "null argument");
     if (!(t1 >= 0.0) || !(t1 < INFINITY)) return fail(RT_E_ARG, "t1 must be finite and >= 0 (got %g)", t1);
     if (!(t2 >= t1)) return fail(RT_E_ARG, "t2 must be >= t1 (got t1 = %g, t2 = %g)", t1, t2);
     rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace_interval");
@@ -457,6 +458,7 @@ rt_status rt_trace_interval(const rt_scene* sc, const rt_trace_params* p, const 
 static long long j_target_chunks(int n_dir, long long n_probes)
 {
     const long long tiles = (n_probes + 63) / 64;
+    if (tiles <= 0) return 1;
     long long c = ((1ll << 18) + tiles - 1) / tiles;
     if (c < 1) c = 1;
     if (c > n_dir) c = n_dir;
@@ -481,19 +483,9 @@ rt_status rt_trace_j(const rt_scene* sc, const rt_trace_params* p, const float* 
                      size_t work_bytes, void* stream)
 {
     g_err.clear();
-    if (!sc || !p || !d_dirs || !d_weights || !d_J) return fail(RT_E_ARG, "null argument");
-    if (sc->batch_begin < 0) return fail(RT_E_STATE, "rt_trace_j before rt_scene_build");
-    if (p->mode != RT_TRACE_LEVEL0 && p->mode != RT_TRACE_VLM) return fail(RT_E_ARG, "bad trace mode");
-    if (n_dir < 1) return fail(RT_E_ARG, "n_dir must be >= 1");
-    for (int m = 1; m < RT_MAX_LEVELS; ++m)
-        if (!(p->level_dist[m] >= 0.f)) return fail(RT_E_ARG, "level_dist[%d] must be >= 0", m);
-    if (p->grade_mode != RT_GRADE_BLOCK_ENTRY && p->grade_mode != RT_GRADE_PATH)
-        return fail(RT_E_ARG, "bad grade_mode %d", (int)p->grade_mode);
-    const long long all = (long long)sc->n_active * sc->g.bvox;
-    if (!d_probes && n_probes != all)
-        return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
-    if (n_probes < 0) return fail(RT_E_ARG, "n_probes must be >= 0");
-    if (n_probes == 0) return RT_OK;
+    if (!sc || !p || !d_dirs || !d_weights || (!d_J && n_probes != 0)) return fail(RT_E_ARG, "null argument");
+    rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace_j");
+    if (st != RT_OK || n_probes == 0) return st;
     const int nl = sc->batch_end - sc->batch_begin;
     const long long per_chunk = (long long)nl * n_probes * (d_psi ? 2 : 1);
     long long chunks = j_target_chunks(n_dir, n_probes);

@@ -355,6 +355,7 @@ __global__ void k_read_cells(Geo g, SceneBufs bufs, int n, const int32_t* cells,
 hipError_t launch_read_cells(const Geo& g, const SceneBufs& b, int storage, int n, const int32_t* cells,
                              float* out, hipStream_t s)
 {
+    if (n <= 0) return hipSuccess;
     unsigned blocks = (unsigned)((n + 127) / 128);
     if (storage == RT_F32) hipLaunchKernelGGL(k_read_cells<float>, dim3(blocks), dim3(128), 0, s, g, b, n, cells, out);
     else if (storage == RT_BF16)

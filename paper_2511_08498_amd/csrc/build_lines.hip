@@ -294,6 +294,7 @@ __global__ void k_cav_encode(const float* cav, T* out, long long n)
 
 hipError_t launch_cav_encode(const float* cav, void* out, long long n, int storage, hipStream_t s)
 {
+    if (n <= 0) return hipSuccess;  // no active block
     const unsigned nb = (unsigned)((n + 255) / 256);
     if (storage == RT_BF16)
         hipLaunchKernelGGL(k_cav_encode<__hip_bfloat16>, dim3(nb), dim3(256), 0, s, cav, (__hip_bfloat16*)out, n);

@@ -1,0 +1,116 @@
+"""GPU edge cases: a scene with no active block, empty probe lists, probes inside empty blocks.
+
+Rays through empty space carry the boundary intensity unchanged (the recurrence of
+Eq. RteIntegral with eta = chi = 0), so these cases have exact answers.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import make_cfg1
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_08498_amd as rt
+    rt.lib()
+    return rt
+
+
+def _dirs2(n, seed):
+    rng = np.random.default_rng(seed)
+    th = rng.uniform(0, 2 * np.pi, n)
+    return np.stack([np.cos(th), np.sin(th)], 1).astype(np.float32)
+
+
+def test_scene_without_active_blocks(rt):
+    import torch
+    n = 32
+    zeros = np.zeros((2, n * n), np.float32)
+    sc = dict(dim=2, n=(n, n, 1), brick=8, n_levels=3, model="static", eta=zeros, chi=zeros, ds0=1.0)
+    scene = rt.Scene.from_dict(sc)
+    assert scene.info["n_active"] == 0 and scene.info["n_probes"] == 0
+    scene.build(0, 2, iod_threshold=1e-2)
+    assert np.all(scene.levels() == -1)
+    dirs = torch.from_numpy(_dirs2(6, 1)).cuda()
+    I = scene.trace(dirs, I0=0.6)
+    assert tuple(I.shape) == (6, 2, 0)
+    probes = np.arange(0, n * n, 37, dtype=np.int32)  # explicit probes anywhere in the (empty) grid
+    for grade in ("entry", "path"):
+        I = scene.trace(dirs, probes=probes, I0=0.6, level_dist=rt.CASCADE_LEVEL_DIST, grade=grade).cpu().numpy()
+        assert np.all(I == np.float32(0.6))
+    Ii, Ti = scene.trace_interval(dirs, 2.0, 9.0, probes=probes, I0=0.6)
+    assert torch.all(Ti == 1).item()
+    # I0 only where the ray leaves the grid inside [2, 9]
+    I_all, _ = scene.trace_interval(dirs, 0.0, np.inf, probes=probes, I0=0.6)
+    assert torch.all(I_all == np.float32(0.6)).item()
+    J, psi = scene.trace_j(dirs, probes=probes, I0=0.6)
+    np.testing.assert_allclose(J.cpu().numpy(), 0.6, rtol=1e-6)
+    assert torch.all(psi == 0).item()
+
+
+def test_line_scene_without_active_blocks_reduced_precision(rt):
+    """Core and Voigt with no active block: the BF16 copy of an empty parameter chain is a no-op."""
+    import torch
+    n = 16
+    z = np.zeros((2, n * n), np.float32)
+    sc = dict(dim=2, n=(n, n, 1), brick=8, n_levels=3, model="lines", profile="voigt", lam=np.array([500.0, 500.01]),
+              lam0=np.array([500.0]), eta_star=z[:1], chi_star=z[:1], damp=z[:1], inv_dld=z[:1] + 10.0,
+              eta_bg=z[0], chi_bg=z[0], vel=np.zeros((2, n * n), np.float32), dirs=_dirs2(4, 2),
+              block_active=np.zeros(4, np.uint8), ds0=1.0, I0=0.0)
+    scene = rt.Scene.from_dict(sc, emission="cav")
+    assert scene.info["n_active"] == 0
+    scene.build(0, 2, storage="bf16")
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    I = scene.trace(dirs, probes=np.array([0, 17, 255], np.int32), I0=0.25).cpu().numpy()
+    assert np.all(I == np.float32(0.25))
+
+
+def test_empty_probe_lists(rt):
+    import torch
+    sc = make_cfg1()
+    scene = rt.Scene.from_dict(sc)
+    scene.build(0, 8, iod_threshold=1e-2)
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    none = np.zeros(0, np.int32)
+    assert tuple(scene.trace(dirs, probes=none).shape) == (8, 8, 0)
+    I, T = scene.trace_interval(dirs, 1.5, 6.0, probes=none)
+    assert tuple(I.shape) == (8, 8, 0) and tuple(T.shape) == (8, 8, 0)
+    J, psi = scene.trace_j(dirs, probes=none)
+    assert tuple(J.shape) == (8, 0)
+
+
+def test_probes_inside_empty_blocks(rt):
+    """Probe voxels in empty blocks: the ray starts in empty space; intensities against the oracle on the same
+    cells, and I0 alone for rays that meet no active block."""
+    import torch
+    sc = make_cfg1()
+    T = 1e-2
+    scene = rt.Scene.from_dict(sc)
+    scene.build(0, 8, iod_threshold=T)
+    empty = np.nonzero(sc["block_active"] == 0)[0]
+    rng = np.random.default_rng(4)
+    vox = []
+    for b in rng.choice(empty, 6, replace=False):
+        bx, by = int(b) % 8, int(b) // 8
+        for _ in range(20):
+            vox.append((bx * 8 + int(rng.integers(0, 8))) + 64 * (by * 8 + int(rng.integers(0, 8))))
+    vox = np.array(vox, np.int32)
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    I = scene.trace(dirs, probes=vox, I0=0.3).cpu().numpy()  # [dir][lam][probe]
+    s = orc.Scene(sc)
+    lvs, st_e, st_c = orc.static_level_values(s, sc["eta"][:8], sc["chi"][:8], sc["block_active"], T=T)
+    lv = orc.batch_levels(lvs)
+    assert np.array_equal(lv, scene.levels())
+    s.set_static_levels(st_e, st_c)
+    s.s.I0 = 0.3
+    d = np.repeat(np.arange(8, dtype=np.int32), vox.size)
+    ref = orc.march(s, orc.STATIC, lv, np.tile(vox, 8), d).reshape(8, vox.size, 8).transpose(0, 2, 1)
+    st = orc.rel_err_stats(I, ref)
+    assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 2e-5, st
+    assert np.any(I == np.float32(0.3))  # some rays cross only empty blocks
