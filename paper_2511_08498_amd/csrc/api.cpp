@@ -642,20 +642,20 @@ rt_status rt_debug_visited(const rt_scene* sc, const rt_trace_params* p, int32_t
     int32_t* dc = nullptr;
     double* dt = nullptr;
     int32_t* dn = nullptr;
-    RT_HIP(hipMalloc(&dc, sizeof(int32_t) * 4 * (size_t)cap));
-    RT_HIP(hipMalloc(&dt, sizeof(double) * 2 * (size_t)cap));
-    RT_HIP(hipMalloc(&dn, sizeof(int32_t)));
+    hipError_t e = hipMalloc(&dc, sizeof(int32_t) * 4 * (size_t)cap);
+    if (e == hipSuccess) e = hipMalloc(&dt, sizeof(double) * 2 * (size_t)cap);
+    if (e == hipSuccess) e = hipMalloc(&dn, sizeof(int32_t));
     float w[3] = {h_dir[0], sc->g.dim > 1 ? h_dir[1] : 0.f, sc->g.dim > 2 ? h_dir[2] : 0.f};
-    hipError_t e = launch_debug_visited(t, probe_vox, w[0], w[1], w[2], cap, dc, dt, dn, s);
+    if (e == hipSuccess) e = launch_debug_visited(t, probe_vox, w[0], w[1], w[2], cap, dc, dt, dn, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     int32_t n = 0;
     if (e == hipSuccess) e = hipMemcpy(&n, dn, sizeof(int32_t), hipMemcpyDeviceToHost);
     int ncp = std::min(std::max(n, 0), cap);
     if (e == hipSuccess && ncp > 0) e = hipMemcpy(h_cells, dc, sizeof(int32_t) * 4 * (size_t)ncp, hipMemcpyDeviceToHost);
     if (e == hipSuccess && ncp > 0) e = hipMemcpy(h_t, dt, sizeof(double) * 2 * (size_t)ncp, hipMemcpyDeviceToHost);
-    (void)hipFree(dc);
-    (void)hipFree(dt);
-    (void)hipFree(dn);
+    if (dc) (void)hipFree(dc);
+    if (dt) (void)hipFree(dt);
+    if (dn) (void)hipFree(dn);
     if (e != hipSuccess) return fail(RT_E_HIP, "debug visited: %s", hipGetErrorString(e));
     *h_count = n;
     if (n < 0) return fail(RT_E_DEVICE, "step cap reached");
