@@ -1,0 +1,80 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py times.
+
+cfg2: 2D 1024^2, 64 directions, all 419,328 probes, velocity interpolation (n_v 21),
+VLM T = 1e-2 with path-graded cascade levels; the first and last wavelength batches are
+traced exactly as the benchmark traces them and sampled rays are compared with the FP64
+oracle marching its own levels (rays through a block whose level sits in the threshold
+tie band are left out, as in the small-scene tests).
+cfg3: 3D 256^3, 32 directions, all 4.2 M probes, Core and Voigt; the sparse MIP-0 march
+(Classic per voxel) on sampled rays against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as orc
+from synth import make_cfg2, make_cfg3
+from test_gpu_lines import oracle_levels, rays_avoiding
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_08498_amd as rt
+    rt.lib()
+    return rt
+
+
+def test_cfg2_full_size_vlm_parity(rt):
+    import torch
+    sc = make_cfg2()
+    T = 1e-2
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    scene = rt.Scene.from_dict(sc, emission="velinterp", n_v=21)
+    probes = scene.probe_voxels()
+    assert probes.size == 419328 and dirs.shape[0] == 64
+    out = torch.empty((64, 8, probes.size), dtype=torch.float32, device="cuda")
+    rng = np.random.default_rng(31)
+    k = rng.choice(probes.size, 1500, replace=False)
+    d = rng.integers(0, 64, k.size).astype(np.int32)
+    nb = sc["lam"].size // 8
+    for b in (0, nb - 1):
+        lam_idx = list(range(8 * b, 8 * b + 8))
+        scene.build(8 * b, 8 * b + 8, iod_threshold=T, avg_mode="linear", tau_thin=0.25)
+        scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST, grade="path", out=out)
+        got = out[torch.from_numpy(d).long().cuda(), :, torch.from_numpy(k).long().cuda()].cpu().numpy()
+        lv_gpu = scene.levels()
+        lv = oracle_levels(sc, lam_idx, 0, T)
+        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], probes[k], d)
+        assert ok.mean() > 0.8
+        s = orc.Scene(sc, lam_idx=lam_idx, n_v=21)
+        s.set_level_dist(rt.CASCADE_LEVEL_DIST, mode="path")
+        ref = orc.march(s, orc.VELINTERP, lv, probes[k], d, n_threads=16)
+        st = orc.rel_err_stats(got[ok], ref[ok])
+        assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 1e-4, (b, st)
+
+
+def test_cfg3_full_size_level0_parity(rt):
+    import torch
+    sc = make_cfg3()
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    scene = rt.Scene.from_dict(sc, emission="cav")
+    probes = scene.probe_voxels()
+    n_dir = dirs.shape[0]
+    assert n_dir == 32 and probes.size > 4_000_000
+    scene.build(0, 8, iod_threshold=1e-2)
+    out = torch.empty((n_dir, 8, probes.size), dtype=torch.float32, device="cuda")
+    scene.trace(dirs, mode="level0", out=out)
+    rng = np.random.default_rng(32)
+    k = rng.choice(probes.size, 300, replace=False)
+    d = rng.integers(0, n_dir, k.size).astype(np.int32)
+    got = out[torch.from_numpy(d).long().cuda(), :, torch.from_numpy(k).long().cuda()].cpu().numpy()
+    del out
+    s = orc.Scene(sc, lam_idx=list(range(8)))
+    lev = np.where(np.asarray(sc["block_active"]) > 0, 0, -1).astype(np.int8)
+    ref = orc.march(s, orc.CAV, lev, probes[k], d, n_threads=16)
+    st = orc.rel_err_stats(got, ref)
+    assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < 1e-3 and st["p100"] < 5e-3, st
