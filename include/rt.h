@@ -248,7 +248,11 @@ typedef struct rt_scene rt_scene;
  * builds the wavelength-independent level chains (velocity grid parameters,
  * Core-and-Voigt line parameters).  Synchronises `stream` (the active-block
  * count sizes the allocation).  On success *out owns device memory released
- * by rt_scene_destroy.  Errors: RT_E_ARG (shape/enum/pointer), RT_E_HIP.
+ * by rt_scene_destroy.  Every input value is checked on the device first:
+ * eta, chi, line strengths, damping, Doppler widths and background must be
+ * finite and >= 0, velocities finite.
+ * Errors: RT_E_ARG (shape/enum/pointer, or negative / non-finite input
+ * values, counted in the message), RT_E_HIP.
  */
 rt_status rt_scene_create(const rt_scene_desc* desc, const rt_scene_inputs* inputs, void* stream, rt_scene** out);
 
@@ -511,6 +515,16 @@ void rt_nrc_destroy(rt_nrc* nrc);
 /* FP32 master weights, host float [num_params] (checkpoint / restore). */
 rt_status rt_nrc_get_weights(const rt_nrc* nrc, float* h_w);
 rt_status rt_nrc_set_weights(rt_nrc* nrc, const float* h_w, void* stream);
+/* Whole training state, for resuming training: FP32 master weights, Adam's first
+ * and second moments (host float [num_params] each) and the step count (which
+ * also keys the counter-based batch sampling).  Training is deterministic, so
+ * steps run after rt_nrc_set_state on a cache created with the same descriptor
+ * repeat those run after the matching rt_nrc_get_state bit for bit.
+ * get synchronises; set is ordered on `stream` and synchronises it.
+ * Errors: RT_E_ARG (null pointer, negative step), RT_E_HIP. */
+rt_status rt_nrc_get_state(const rt_nrc* nrc, float* h_w, float* h_m, float* h_v, int32_t* h_step);
+rt_status rt_nrc_set_state(rt_nrc* nrc, const float* h_w, const float* h_m, const float* h_v, int32_t step,
+                           void* stream);
 /* Packs generation-mode outputs of one batch into training rows starting at row0
  * (rows ordered (dir, lam, probe)); d_raw [.][12], d_target [.]. */
 rt_status rt_nrc_pack(const rt_scene* scene, const float* d_dirs, int32_t n_dir, int64_t n_probes,

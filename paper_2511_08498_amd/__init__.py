@@ -35,7 +35,7 @@ EXPORTS = (
     "rt_graph_destroy", "rt_trace_truncated", "rt_nrc_num_params", "rt_nrc_create", "rt_nrc_destroy",
     "rt_nrc_get_weights", "rt_nrc_set_weights", "rt_nrc_pack", "rt_nrc_train", "rt_nrc_loss", "rt_nrc_gradients",
     "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate", "rt_scene_workspace_bytes", "rt_nrc_workspace_bytes",
-    "rt_trace_j", "rt_trace_j_workspace_bytes", "rt_trace_interval",
+    "rt_trace_j", "rt_trace_j_workspace_bytes", "rt_trace_interval", "rt_nrc_get_state", "rt_nrc_set_state",
 )
 _VOID = ("rt_scene_destroy", "rt_last_error", "rt_version", "rt_batch_destroy", "rt_graph_destroy", "rt_nrc_destroy")
 
@@ -154,6 +154,8 @@ def lib():
     L.rt_nrc_destroy.restype = None
     L.rt_nrc_get_weights.argtypes = [_P, _P]
     L.rt_nrc_set_weights.argtypes = [_P, _P, _P]
+    L.rt_nrc_get_state.argtypes = [_P, _P, _P, _P, _P]
+    L.rt_nrc_set_state.argtypes = [_P, _P, _P, _P, i32, _P]
     L.rt_nrc_pack.argtypes = [_P, _P, i32, i64, _P, _P, _P, _P, _P, i64, _P]
     L.rt_nrc_train.argtypes = [_P, _P, _P, i64, i32, i32, ctypes.c_float, _P]
     L.rt_nrc_loss.argtypes = [_P, _P]
@@ -645,6 +647,28 @@ class Nrc:
         w = np.ascontiguousarray(w, np.float32)
         assert w.size == self.n_params
         _check(lib().rt_nrc_set_weights(self.h, _np_ptr(w), _stream(stream)))
+
+    def get_state(self):
+        """Training state: dict of FP32 weights w, Adam moments m and v (host arrays) and the step count."""
+        w, m, v = (np.zeros(self.n_params, np.float32) for _ in range(3))
+        st = ctypes.c_int32(0)
+        _check(lib().rt_nrc_get_state(self.h, _np_ptr(w), _np_ptr(m), _np_ptr(v), ctypes.byref(st)))
+        return {"w": w, "m": m, "v": v, "step": int(st.value)}
+
+    def set_state(self, state, stream=None):
+        w, m, v = (np.ascontiguousarray(state[k], np.float32) for k in ("w", "m", "v"))
+        assert w.size == m.size == v.size == self.n_params
+        _check(lib().rt_nrc_set_state(self.h, _np_ptr(w), _np_ptr(m), _np_ptr(v), int(state["step"]),
+                                      _stream(stream)))
+
+    def save_checkpoint(self, path):
+        """Writes the training state to an .npz file (plain arrays, no pickled objects)."""
+        st = self.get_state()
+        np.savez(path, w=st["w"], m=st["m"], v=st["v"], step=np.array([st["step"]], np.int64))
+
+    def load_checkpoint(self, path, stream=None):
+        with np.load(path, allow_pickle=False) as z:
+            self.set_state({"w": z["w"], "m": z["m"], "v": z["v"], "step": int(z["step"][0])}, stream)
 
     def _dev(self, a, dt=None):
         torch = self.torch

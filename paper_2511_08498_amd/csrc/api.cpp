@@ -15,6 +15,12 @@
 
 using namespace rt;
 
+namespace rt {
+// build.hip: counts negative or non-finite input values (scene creation)
+hipError_t launch_validate(const Inputs& in, int model, int n_lam, int n_lines, int dim, unsigned long long* count,
+                           hipStream_t s);
+}  // namespace rt
+
 namespace {
 
 thread_local std::string g_err;
@@ -145,7 +151,8 @@ static size_t scene_bytes(const rt_scene_desc* d, const Geo& g, long long na)
 {
     const size_t nb = (size_t)g.nblocks, cells = (size_t)na * g.cells;
     size_t b = alloc_bytes(nb, 4) + alloc_bytes(nb, 1) + alloc_bytes(nb, 4) + alloc_bytes(nb, 4) + alloc_bytes(1, 4) +
-               alloc_bytes(nb, 1) + alloc_bytes((size_t)g.n_state_words, 8) + alloc_bytes(2, 8);
+               alloc_bytes(nb, 1) + alloc_bytes((size_t)g.n_state_words, 8) + alloc_bytes(2, 8) +
+               alloc_bytes(1, 8);  // the last: the input-validation counter
     b += alloc_bytes(((size_t)na << (d->dim * (g.log2B - g.feat_level))) * kLam, 16);
     if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) b += alloc_bytes(cells * kLam * 2, 4);
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP)
@@ -238,6 +245,12 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     unsigned long long err0[2] = {0ull, ~0ull};
     if ((e = hipMemcpyAsync(B.err, err0, sizeof(err0), hipMemcpyHostToDevice, s)) != hipSuccess)
         return cleanup(fail(RT_E_HIP, "upload: %s", hipGetErrorString(e)));
+    unsigned long long* d_bad = nullptr;
+    if ((st = sc->alloc(&d_bad, 1)) != RT_OK) return cleanup(st);
+    if ((e = hipMemsetAsync(d_bad, 0, sizeof(unsigned long long), s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "clear: %s", hipGetErrorString(e)));
+    if ((e = launch_validate(in, d->model, d->n_lam, d->n_lines, d->dim, d_bad, s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "validate: %s", hipGetErrorString(e)));
     if ((e = launch_classify(g, in, d->model, d->n_lam, d->n_lines, d->dense, B.active, s)) != hipSuccess)
         return cleanup(fail(RT_E_HIP, "classify: %s", hipGetErrorString(e)));
     if ((e = launch_slots(g, B.morton, B.active, B.slot, B.active_list, B.n_active, s)) != hipSuccess)
@@ -245,10 +258,14 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     if ((e = launch_fill_levels(g, B.levels, s)) != hipSuccess)
         return cleanup(fail(RT_E_HIP, "levels: %s", hipGetErrorString(e)));
     int32_t na = 0;
+    unsigned long long n_bad = 0;
     if ((e = hipMemcpyAsync(&na, B.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return cleanup(fail(RT_E_HIP, "readback: %s", hipGetErrorString(e)));
+    if ((e = hipMemcpyAsync(&n_bad, d_bad, sizeof(n_bad), hipMemcpyDeviceToHost, s)) != hipSuccess)
         return cleanup(fail(RT_E_HIP, "readback: %s", hipGetErrorString(e)));
     if ((e = hipStreamSynchronize(s)) != hipSuccess)
         return cleanup(fail(RT_E_HIP, "synchronize: %s", hipGetErrorString(e)));
+    if (n_bad) return cleanup(fail(RT_E_ARG, "inputs hold %llu negative or non-finite values", n_bad));
     sc->n_active = na;
     const size_t cells = (size_t)na * g.cells;
     {

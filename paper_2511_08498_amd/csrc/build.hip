@@ -51,6 +51,44 @@ hipError_t launch_classify(const Geo& g, const Inputs& in, int model, int n_lam,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- validate
+// Counts input values that are negative or not finite (eta, chi, line
+// strengths, damping, Doppler widths, background) or not finite (velocity).
+__device__ __forceinline__ int bad_nonneg(float x) { return !(x >= 0.f && x <= 3.402823466e38f); }
+__device__ __forceinline__ int bad_finite(float x) { return !(x >= -3.402823466e38f && x <= 3.402823466e38f); }
+
+__global__ void k_validate(Inputs in, int model, int n_lam, int n_lines, int dim, unsigned long long* count)
+{
+    unsigned long long c = 0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < in.nvox; v += stride) {
+        if (model == RT_MODEL_STATIC) {
+            for (int l = 0; l < n_lam; ++l)
+                c += bad_nonneg(in.eta[(long long)l * in.nvox + v]) + bad_nonneg(in.chi[(long long)l * in.nvox + v]);
+        } else {
+            for (int l = 0; l < n_lines; ++l) {
+                const long long o = (long long)l * in.nvox + v;
+                c += bad_nonneg(in.eta_star[o]) + bad_nonneg(in.chi_star[o]) + bad_nonneg(in.damp[o]) +
+                     bad_nonneg(in.inv_dld[o]);
+            }
+            c += bad_nonneg(in.eta_bg[v]) + bad_nonneg(in.chi_bg[v]);
+            for (int a = 0; a < dim; ++a) c += bad_finite(in.vel[(long long)a * in.nvox + v]);
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) c += (unsigned long long)__shfl_xor((long long)c, o, 64);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+hipError_t launch_validate(const Inputs& in, int model, int n_lam, int n_lines, int dim, unsigned long long* count,
+                           hipStream_t s)
+{
+    if (in.nvox <= 0) return hipSuccess;
+    long long blocks = (in.nvox + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_validate, dim3((unsigned)blocks), dim3(256), 0, s, in, model, n_lam, n_lines, dim, count);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------- slots
 // One workgroup walks the Morton order in chunks of 1024 blocks and assigns
 // each active block the next storage slot (exclusive prefix sum).

@@ -704,6 +704,33 @@ rt_status rt_nrc_set_weights(rt_nrc* nn, const float* h, void* stream)
     return RT_OK;
 }
 
+rt_status rt_nrc_get_state(const rt_nrc* nn, float* h_w, float* h_m, float* h_v, int32_t* h_step)
+{
+    if (!nn || !h_w || !h_m || !h_v || !h_step) return set_error(RT_E_ARG, "null argument");
+    NRC_HIP(hipDeviceSynchronize());
+    NRC_HIP(hipMemcpy(h_w, nn->w, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    NRC_HIP(hipMemcpy(h_m, nn->m, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    NRC_HIP(hipMemcpy(h_v, nn->v, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    *h_step = nn->step;
+    return RT_OK;
+}
+
+rt_status rt_nrc_set_state(rt_nrc* nn, const float* h_w, const float* h_m, const float* h_v, int32_t step,
+                           void* stream)
+{
+    if (!nn || !h_w || !h_m || !h_v) return set_error(RT_E_ARG, "null argument");
+    if (step < 0) return set_error(RT_E_ARG, "step must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    NRC_HIP(hipMemcpyAsync(nn->w, h_w, sizeof(float) * kNParams, hipMemcpyHostToDevice, s));
+    NRC_HIP(hipMemcpyAsync(nn->m, h_m, sizeof(float) * kNParams, hipMemcpyHostToDevice, s));
+    NRC_HIP(hipMemcpyAsync(nn->v, h_v, sizeof(float) * kNParams, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_to_bf16, dim3((kParamsPadded + 255) / 256), dim3(256), 0, s, nn->w, nn->wb, kParamsPadded);
+    NRC_HIP(hipGetLastError());
+    NRC_HIP(hipStreamSynchronize(s));
+    nn->step = step;
+    return RT_OK;
+}
+
 rt_status rt_nrc_train(rt_nrc* nn, const float* d_raw, const float* d_target, int64_t n, int32_t steps, int32_t batch,
                        float lr, void* stream)
 {

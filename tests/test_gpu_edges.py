@@ -114,3 +114,32 @@ def test_probes_inside_empty_blocks(rt):
     st = orc.rel_err_stats(I, ref)
     assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 2e-5, st
     assert np.any(I == np.float32(0.3))  # some rays cross only empty blocks
+
+
+def test_invalid_inputs_rejected_at_create(rt):
+    """Negative or non-finite emissivity / opacity / line parameters, and non-finite velocities, are rejected
+    when the scene is created (a device pass over every input value)."""
+    n = 32
+    rng = np.random.default_rng(5)
+    eta = rng.uniform(0.1, 1.0, (2, n * n)).astype(np.float32)
+    chi = rng.uniform(0.1, 1.0, (2, n * n)).astype(np.float32)
+    base = dict(dim=2, n=(n, n, 1), brick=8, n_levels=3, model="static", ds0=1.0)
+    rt.Scene.from_dict(dict(base, eta=eta, chi=chi))  # valid
+    for name, arr, idx, val in (("chi", chi, (0, 5), np.nan), ("chi", chi, (1, 9), np.inf),
+                                ("eta", eta, (1, 7), -1e-3), ("eta", eta, (0, 0), -np.inf)):
+        bad = arr.copy()
+        bad[idx] = val
+        kw = dict(eta=eta, chi=chi)
+        kw[name] = bad
+        with pytest.raises(RuntimeError, match="negative or non-finite"):
+            rt.Scene.from_dict(dict(base, **kw))
+    from test_gpu_lines import cav_scene
+    sc = cav_scene(n=16)
+    rt.Scene.from_dict(sc, emission="cav")  # valid
+    for key, val in (("damp", -0.1), ("vel", np.nan), ("inv_dld", np.inf), ("chi_bg", -1.0)):
+        bad = dict(sc)
+        arr = np.array(sc[key], np.float32, copy=True)
+        arr.reshape(-1)[123] = val
+        bad[key] = arr
+        with pytest.raises(RuntimeError, match="negative or non-finite"):
+            rt.Scene.from_dict(bad, emission="cav")

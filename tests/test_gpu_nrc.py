@@ -192,6 +192,30 @@ def test_gradients_match_oracle(rt):
         assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b) + 1e-7, k
 
 
+def test_checkpoint_resume_is_bit_exact(rt, tmp_path):
+    """Weights, Adam moments and step count saved to .npz and loaded into a new cache with the same descriptor:
+    the resumed training repeats the uninterrupted one bit for bit (no float atomics, counter-based batches)."""
+    rng = np.random.default_rng(6)
+    raw = _raw_rows(rng, 32768)
+    tgt = (0.2 * np.sin(2 * np.pi * raw[:, 1]) - 0.3).astype(np.float32)
+    nn = rt.Nrc(max_batch=4096, freq_max=8.0, seed=9)
+    nn.train(raw, tgt, steps=25, batch=2048, lr=2e-3)
+    path = str(tmp_path / "nrc.npz")
+    nn.save_checkpoint(path)
+    nn.train(raw, tgt, steps=25, batch=2048, lr=2e-3)
+    a = nn.get_state()
+    nn2 = rt.Nrc(max_batch=4096, freq_max=8.0, seed=9)
+    nn2.load_checkpoint(path)
+    assert nn2.get_state()["step"] == 25
+    nn2.train(raw, tgt, steps=25, batch=2048, lr=2e-3)
+    b = nn2.get_state()
+    assert a["step"] == b["step"] == 50
+    for k in ("w", "m", "v"):
+        assert np.array_equal(a[k], b[k]), k
+    with np.load(path, allow_pickle=False) as z:
+        assert sorted(z.files) == ["m", "step", "v", "w"]
+
+
 def test_training_lowers_loss_and_weights_round_trip(rt):
     nn = rt.Nrc(max_batch=8192, freq_max=8.0, seed=5)
     rng = np.random.default_rng(4)
