@@ -227,6 +227,29 @@ def scene_workspace_bytes(sc, n_active=None, emission=None, n_v=21, dense=False)
     return v.value
 
 
+C_KMS = 299792.458  # speed of light, km/s
+
+
+class VelocityGridWarning(UserWarning):
+    """Velocity-interpolation node spacing coarser than the configured number of thermal widths."""
+
+
+def velocity_grid_ratio(vel, inv_dld, lam0, n_v):
+    """Per line, the largest ratio over voxels of the velocity-node spacing 2 |v| / (n_v - 1) to the line's
+    thermal (Doppler) width c / (lam0 inv_dld) (host arithmetic on the inputs, no device work)."""
+    def host(a):
+        return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+    v = host(vel).astype(np.float32)
+    speed = np.sqrt((v * v).sum(axis=0))
+    spacing = 2.0 * speed / max(int(n_v) - 1, 1)
+    idl = host(inv_dld).astype(np.float32)
+    out = []
+    for k, l0 in enumerate(np.asarray(lam0, np.float64).reshape(-1)):
+        vd = np.where(idl[k] > 0, C_KMS / (l0 * np.where(idl[k] > 0, idl[k], 1.0)), np.inf)
+        out.append(float(np.max(spacing / vd)) if speed.size else 0.0)
+    return np.array(out)
+
+
 class Scene:
     """A scene resident on the GPU: inputs (device tensors) + the library's handle.
 
@@ -275,6 +298,9 @@ class Scene:
             inp.d_block_mask = tm.data_ptr()
         self.n_lam = d.n_lam
         self.desc = d
+        self.velocity_grid_ratio = None
+        if model != "static" and emission == "velinterp":
+            self.velocity_grid_ratio = velocity_grid_ratio(vel, inv_dld, lam0, n_v)
         h = _P()
         _check(lib().rt_scene_create(ctypes.byref(d), ctypes.byref(inp), _stream(stream), ctypes.byref(h)))
         self.h = h
@@ -307,7 +333,18 @@ class Scene:
         return {k: getattr(inf, k) for k, _ in RtSceneInfo._fields_ if k != "reserved_"}
 
     def build(self, lam_begin, lam_end, iod_threshold=1e-2, tau_thin=0.25, max_level=-1, avg_mode="linear",
-              storage="f32", iod_frame="rest", stream=None):
+              storage="f32", iod_frame="rest", velocity_grid_warn=2.0, stream=None):
+        """Builds the level structure for wavelengths [lam_begin, lam_end).  Velocity interpolation: warns
+        (VelocityGridWarning) when the node spacing exceeds `velocity_grid_warn` thermal widths of the line whose
+        rest wavelength is closest to the batch (Sect. 3.1)."""
+        if self.velocity_grid_ratio is not None and velocity_grid_warn:
+            mid = 0.5 * (self.lam[int(lam_begin)] + self.lam[int(lam_end) - 1])
+            k = int(np.argmin(np.abs(np.asarray(self.lam0) - mid)))
+            r = float(self.velocity_grid_ratio[k])
+            if r > velocity_grid_warn:
+                import warnings
+                warnings.warn("velocity nodes are %.2f thermal widths of line %d apart (more than %g): raise n_v"
+                              % (r, k, velocity_grid_warn), VelocityGridWarning, stacklevel=2)
         p = RtBuildParams()
         p.iod_frame = {"rest": 0, "core": 1}[iod_frame]
         p.iod_threshold = float(iod_threshold)

@@ -238,3 +238,17 @@ def test_workspace_bytes_match_allocation(rt, vscene):
     for sc, emis in ((vscene, "velinterp"), (cav_scene(), "cav")):
         s = rt.Scene.from_dict(sc, emission=emis)
         assert s.info["storage_bytes"] == rt.scene_workspace_bytes(sc, n_active=s.info["n_active"], emission=emis)
+
+
+def test_velocity_grid_warning(rt, vscene):
+    """Sect. 3.1: the build warns when velocity nodes are more than two thermal widths apart."""
+    import warnings
+    sc = vscene  # |v| <= 30 km/s, thermal width 10 km/s
+    coarse = rt.Scene.from_dict(sc, emission="velinterp", n_v=3)   # 30 km/s apart: 3 widths
+    with pytest.warns(rt.VelocityGridWarning):
+        coarse.build(0, 8)
+    fine = rt.Scene.from_dict(sc, emission="velinterp", n_v=21)    # 3 km/s apart
+    with warnings.catch_warnings():
+        warnings.simplefilter("error", rt.VelocityGridWarning)
+        fine.build(0, 8)
+    assert fine.velocity_grid_ratio.max() < 0.31

@@ -1,4 +1,5 @@
 """Host-only entry points of the C ABI (no device work): size queries and descriptor validation."""
+import numpy as np
 import pytest
 
 from synth import make_cfg1
@@ -53,3 +54,19 @@ def test_nrc_workspace_bytes(rt):
     for bad in (0, 300, 1 << 20):
         with pytest.raises(rt.RtError):
             rt.nrc_workspace_bytes(bad)
+
+
+def test_velocity_grid_ratio():
+    """Node spacing 2 |v| / (n_v - 1) against the thermal width c / (lam0 inv_dld) (Sect. 3.1 warning rule)."""
+    import paper_2511_08498_amd as rt
+    nvox = 50
+    vel = np.zeros((2, nvox), np.float32)
+    vel[0, 7] = 30.0                                  # 30 km/s in one voxel: spacing 3 km/s with 21 nodes
+    lam0 = np.array([500.0, 600.0])
+    idl = np.zeros((2, nvox), np.float32)
+    idl[0] = rt.C_KMS / (500.0 * 1.0)                 # line 0: thermal width 1 km/s
+    idl[1] = rt.C_KMS / (600.0 * 10.0)                # line 1: 10 km/s
+    idl[1, 3] = 0.0                                   # no line in this voxel: ignored
+    r = rt.velocity_grid_ratio(vel, idl, lam0, 21)
+    np.testing.assert_allclose(r, [3.0, 0.3], rtol=1e-5)
+    assert np.all(rt.velocity_grid_ratio(np.zeros((2, nvox), np.float32), idl, lam0, 21) == 0)
