@@ -419,7 +419,8 @@ static rt_status check_trace(const rt_scene* sc, const rt_trace_params* p, int32
     const long long all = (long long)sc->n_active * sc->g.bvox;
     if (!d_probes && n_probes != all)
         return fail(RT_E_ARG, "all-probes trace needs n_probes = %lld (got %lld)", all, (long long)n_probes);
-    if ((long long)n_dir * ((n_probes + 63) / 64) > (long long)0x7fffffff * 4)
+    // waves: n_dir x 64-probe tiles, padded to eight equal chunks in 3D
+    if ((long long)n_dir * ((n_probes + 63) / 64 + 7) > (long long)0x7fffffff * 4)
         return fail(RT_E_ARG, "launch too large");
     return RT_OK;
 }

@@ -873,14 +873,23 @@ k_trace(TraceLaunch t)
     // step signs and reciprocals) in scalar registers
     const long long wave = (long long)lwg * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     const int lane = threadIdx.x & 63;
-    const long long dir = wave / tiles;
-    const long long probe = (wave - dir * tiles) * 64 + lane;
+    // 2D: direction-major over all tiles, so the waves in flight march parallel rays through
+    // the same volume and share its cells in L2.  3D (a much larger volume per direction):
+    // each XCD takes one eighth of the probe tiles, a compact region in Morton order, for
+    // every direction (direction-major inside it), so its own L2 holds that region's cells.
+    const long long per = D == 3 ? (tiles + 7) / 8 : tiles;
+    const long long xc = D == 3 ? wave / (per * t.n_dir) : 0;
+    const long long rem = wave - xc * per * t.n_dir;
+    const long long dir = rem / per;
+    const long long tile = xc * per + (rem - dir * per);
+    const long long probe = tile * 64 + lane;
+    const bool in_grid = xc < 8 && dir < t.n_dir && tile < tiles;
     Counters cnt = {0, 0, 0};
-    if (dir < t.n_dir && probe < t.n_probes) trace_ray<D, Vis>(t, sts, dir, probe, cnt);
+    if (in_grid && probe < t.n_probes) trace_ray<D, Vis>(t, sts, dir, probe, cnt);
     if (t.stats) {
         // the whole wave is active again here; [4] sums the longest ray of each wave
         // (in traversal steps), so ([0] + [2]) / (64 [4]) is the lane utilisation
-        const bool live = dir < t.n_dir && probe < t.n_probes;
+        const bool live = in_grid && probe < t.n_probes;
         unsigned steps = cnt.segs + cnt.empty, wmax = steps;
         for (int o = 32; o > 0; o >>= 1) wmax = max(wmax, (unsigned)__shfl_xor((int)wmax, o, 64));
         if (live) {
@@ -889,7 +898,7 @@ k_trace(TraceLaunch t)
             atomicAdd(&t.stats[2], (unsigned long long)cnt.empty);
             atomicAdd(&t.stats[3], (unsigned long long)cnt.lvlchg);
         }
-        if (lane == 0 && dir < t.n_dir) atomicAdd(&t.stats[4], (unsigned long long)wmax);
+        if (lane == 0 && in_grid) atomicAdd(&t.stats[4], (unsigned long long)wmax);
     }
 }
 
@@ -995,8 +1004,9 @@ static hipError_t launch_one(const TraceLaunch& t, hipStream_t s)
         if (wgs <= 0) return hipSuccess;
         hipLaunchKernelGGL((k_trace_j<D, Vis>), dim3((unsigned)wgs), dim3(256), shm, s, t);
     } else {
-        long long waves = tiles * t.n_dir;
-        long long wgs = (waves + 3) / 4;
+        // 3D: eight equal tile chunks (one per XCD), the last padded
+        const long long waves = (D == 3 ? 8 * ((tiles + 7) / 8) : tiles) * t.n_dir;
+        const long long wgs = (waves + 3) / 4;
         if (wgs <= 0) return hipSuccess;
         hipLaunchKernelGGL((k_trace<D, Vis>), dim3((unsigned)wgs), dim3(256), shm, s, t);
     }
