@@ -264,3 +264,26 @@ def test_path_graded_lines(rt, emission):
     st = orc.rel_err_stats(I[ok], ref[ok])
     bound = 1e-4 if emission == "velinterp" else 5e-3
     assert st["n_ref_zero_mismatch"] == 0 and _p100(st) < bound, st
+
+
+@pytest.mark.parametrize("grade", ["entry", "path"])
+def test_intervals_compose_in_3d(rt, grade):
+    """3D Core and Voigt, distance-graded: the whole ray equals its cascade intervals composed (the start block of
+    each interval keeps the cap of the path length at which the ray entered it, or the cap along the path)."""
+    import torch
+    sc = cav_scene()
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    scene = rt.Scene.from_dict(sc, emission="cav")
+    scene.build(0, 8, iod_threshold=0.1)
+    ld = (0.0, 2.0, 6.0, 12.0)
+    kw = dict(mode="vlm", level_dist=ld, grade=grade)
+    full = scene.trace(dirs, **kw).double()
+    ends = [0.0, 1.5, 4.0, 9.0, 20.0, np.inf]
+    acc = torch.zeros_like(full)
+    trans = torch.ones_like(full)
+    for t1, t2 in zip(ends[:-1], ends[1:]):
+        I, T = scene.trace_interval(dirs, t1, t2, **kw)
+        acc += trans * I.double()
+        trans *= T.double()
+    st = orc.rel_err_stats(acc.cpu().numpy(), full.cpu().numpy())
+    assert st["n_ref_zero_mismatch"] == 0 and _p100(st) < 5e-4, st
