@@ -69,6 +69,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+STORAGE_T = {"f32": "float", "bf16": "__hip_bfloat16", "f16": "__half"}
+
+
 def bytes_per_seg_lam(emission, storage, dim, lam_batch=8):
     s = 4 if storage == "f32" else 2
     if emission == "static":
@@ -89,6 +92,8 @@ def main():
                          "matrix: the paper's method matrix on a prominence-like 2D scene")
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=21)
+    ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
+                    help="cfg2: storage of the velocity-node / value records (FP32 accumulation in every case)")
     ap.add_argument("--iod", type=float, default=None, help="IoD threshold T (default 1 for matrix, else 1e-2)")
     ap.add_argument("--avg", default="linear", choices=["log", "linear"], help="stored level values: arithmetic "
                     "(box filter, default) or geometric mean of the children")
@@ -177,7 +182,7 @@ def bench_cfg2(args):
     def step(record=False, stats=None):
         for b in range(nb_lam):
             scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
-                        iod_frame=args.iod_frame)
+                        iod_frame=args.iod_frame, storage=args.storage)
             if record:
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
@@ -220,12 +225,12 @@ def bench_cfg2(args):
     raw = seglam_step / (ms_step / 1e3) / 1e9
 
     # ---- roofline of the march kernel
-    bps = bytes_per_seg_lam(args.emission, "f32", sc["dim"])
+    bps = bytes_per_seg_lam(args.emission, args.storage, sc["dim"])
     seglam_launch = seglam_step / nb_lam
     achieved = bps * seglam_launch / (mean_trace_ms / 1e3)
     # measured DRAM bytes and VALU issue per launch from the committed rocprofv3 counter summary,
     # only while it matches the kernel sources (else null)
-    cnt = measured_counters("counters_%s_cfg2" % args.emission) if args.n_v == 21 else None
+    cnt = measured_counters("counters_%s_cfg2" % args.emission) if args.n_v == 21 and args.storage == "f32" else None
     traffic = None
     valu = None
     if cnt is not None:
@@ -235,19 +240,19 @@ def bench_cfg2(args):
                 "measured_hbm_gbs": traffic / (mean_trace_ms * 1e6)}
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": traffic, "valu": valu,
-                "kernel": "k_trace<2, VisVelinterp<2>>" if args.emission == "velinterp" else "k_trace",
+                "kernel": ("k_trace<2, VisVelinterp<2, %s>>" % STORAGE_T[args.storage]) if args.emission == "velinterp"
+                else "k_trace",
                 "bytes_per_seg_lam": bps, "seg_lam_per_launch": seglam_launch,
                 "mean_launch_ms": mean_trace_ms}
 
     out = {"metric": METRIC, "value": value, "unit": "Gsegments/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
            "config": {"workload": (
                "2D 1024^2, 16^2 bricks, 40%% active, 2 Gaussian lines + continuum, |v| <= 30 km/s, %s (n_v=%d), "
-               "4-level VLM T=%g, %s means, thin %g, level test %s frame, %s, 64 dirs, 256 lambda (32 batches of 8), "
-               "all %d probes" % (args.emission, args.n_v, args.iod, args.avg, args.tau_thin, args.iod_frame,
-                                  _grading(args),
-                                  n_probes)),
+               "%s storage, 4-level VLM T=%g, %s means, thin %g, level test %s frame, %s, 64 dirs, 256 lambda "
+               "(32 batches of 8), all %d probes" % (args.emission, args.n_v, args.storage.upper(), args.iod, args.avg,
+                                                     args.tau_thin, args.iod_frame, _grading(args), n_probes)),
                       "value_kind": "dense-equivalent segment-wavelength updates per second"},
            "raw_gseg_s": raw, "seg_lam_per_step": seglam_step, "dense_seg_lam_per_step": dense_seglam_step,
            "lane_utilisation": lane_util,
@@ -357,6 +362,34 @@ def bench_cfg2(args):
                                             "ms_per_batch": (tb - ta) * 1e3 / nbc,
                                             "speedup_vs_dense_classic":
                                                 cmp["dense_classic"]["ms_per_batch"] / ((tb - ta) * 1e3 / nbc)}
+            # the same VLM march with the node records stored in FP32 / BF16 / FP16, timed on the same
+            # batches (error filled in below)
+            node_t = {}
+            for dt in ("f32", "bf16", "f16"):
+                kwd = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                           iod_frame=args.iod_frame, storage=dt)
+                for b in range(nbc):
+                    scene.build(8 * b, 8 * b + 8, **kwd)
+                    scene.trace(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, out=tmp)
+                torch.cuda.synchronize()
+                evd = []
+                ta = time.perf_counter()
+                for b in range(nbc):
+                    scene.build(8 * b, 8 * b + 8, **kwd)
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    scene.trace(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, out=tmp)
+                    e1.record(stream)
+                    evd.append((e0, e1))
+                torch.cuda.synchronize()
+                tb = time.perf_counter()
+                node_t[dt] = ((tb - ta) * 1e3 / nbc, float(np.mean([a.elapsed_time(b2) for a, b2 in evd])))
+            for dt, (ms_b, lms) in node_t.items():
+                cmp["vlm_%s_nodes" % dt] = {
+                    "ms_per_batch": ms_b, "mean_launch_ms": lms,
+                    "step_speedup_vs_f32": node_t["f32"][0] / ms_b, "launch_speedup_vs_f32": node_t["f32"][1] / lms,
+                    "note": "batches 0-%d, build + VLM trace; node records %d B per segment" % (
+                        nbc - 1, 128 if dt == "f32" else 64)}
         out["comparators"] = cmp
 
     # ---- accuracy and CPU baseline on a seeded ray sample
@@ -397,6 +430,14 @@ def bench_cfg2(args):
                              dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin), {},
                              dirs, probes[k], d, ref, nb_lam)
             out["comparators"]["sparse_velinterp_nv81"]["error_vs_fp64_classic"] = e81["sparse MIP 0, n_v=81"]
+            base_b = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, iod_frame=args.iod_frame)
+            for dt in ("f32", "bf16", "f16"):
+                key = "vlm_%s_nodes" % dt
+                if key in out["comparators"]:
+                    e = run_ladder(torch, np, [(key, scene, {"storage": dt}, {})], base_b,
+                                   dict(mode="vlm", level_dist=level_dist, grade=args.grade), dirs, probes[k], d, ref,
+                                   nb_lam)
+                    out["comparators"][key]["error_vs_fp64_classic"] = e[key]
         if args.ladder:
             out["accuracy_ladder"] = accuracy_ladder(args, rt, torch, np, sc, scene, dirs, probes[k], d, ref, nb_lam,
                                                      level_dist)
@@ -405,7 +446,8 @@ def bench_cfg2(args):
 
 def accuracy_ladder(args, rt, torch, np, sc, scene, dirs, probe_vox, d, ref, nb_lam, level_dist):
     """cfg2: error against the FP64 oracle of other settings on the same sampled rays."""
-    base = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, iod_frame=args.iod_frame)
+    base = dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, iod_frame=args.iod_frame,
+                storage=args.storage)
     scene81 = rt.Scene.from_dict(sc, emission=args.emission, n_v=81)
     ld4 = [v * 4 for v in rt.CASCADE_LEVEL_DIST]
     settings = [("as benchmarked", scene, {}, {}),

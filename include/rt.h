@@ -159,8 +159,10 @@ typedef struct rt_scene_inputs {
  *   max_level      cap on the selected level (-1: none).
  *   avg_mode       rt_avg for the stored level values (the IoD always uses ln values).
  *   storage        rt_dtype of the stored values (BF16/F16 round to nearest even):
- *                  static emission values, Core-and-Voigt line parameters;
- *                  velocity-interpolation nodes are FP32 only (RT_E_UNSUPPORTED).
+ *                  static emission values, Core-and-Voigt line parameters,
+ *                  velocity-interpolation node values (computed in FP32, then rounded;
+ *                  a BF16/F16 node record is 32 bytes instead of 64, in the same
+ *                  buffer).  Level selection does not depend on it.
  *   iod_frame      line model with velocity interpolation: the frame in which the
  *                  MIP-0 eta, chi of the level test are evaluated.  RT_IOD_REST (0):
  *                  every line at rest (Sect. 3.1); RT_IOD_CORE (1): each voxel's line

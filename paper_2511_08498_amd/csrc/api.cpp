@@ -334,8 +334,6 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     if (p->avg_mode != RT_AVG_LOG && p->avg_mode != RT_AVG_LINEAR) return fail(RT_E_ARG, "bad avg_mode");
     if (p->storage < RT_F32 || p->storage > RT_F16) return fail(RT_E_ARG, "bad storage dtype");
     const bool static_emis = d.model == RT_MODEL_STATIC || d.emission == RT_EMIS_STATIC;
-    if (d.emission == RT_EMIS_VELINTERP && p->storage != RT_F32)
-        return fail(RT_E_UNSUPPORTED, "velocity-interpolation nodes are stored in FP32");
     LamBatch lb = make_batch(sc, lam_begin, lam_end);
     const Geo& g = sc->g;
     int cap = p->max_level < 0 ? -1 : p->max_level;
@@ -345,7 +343,7 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     RT_HIP(launch_build_static(g, sc->in, sc->b, sc->n_active, d.model, vrule, lb, lam_begin, d.ds0, p->iod_threshold,
                                p->tau_thin, cap, p->avg_mode, p->storage, static_emis ? 1 : 0, s));
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_VELINTERP)
-        RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, d.ds0, p->avg_mode, s));
+        RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, d.ds0, p->avg_mode, p->storage, s));
     RT_HIP(launch_pack_states(g, sc->b.levels, sc->b.states, s));
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_CAV && p->avg_mode != sc->cav_mode) {
         // the wavelength-independent chain follows the stored-value mode of the build

@@ -15,6 +15,8 @@
 #include "common.h"
 #include "profile.h"
 
+#include <type_traits>
+
 namespace rt {
 
 __device__ __forceinline__ void voxel_of(const Geo& g, int blk, int tid, int D, long long& v)
@@ -108,8 +110,16 @@ hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int 
 // thread walks the cell's MIP-0 voxels once, reads each voxel's line
 // parameters once, evaluates eta, chi at the node velocity for all 8 batch
 // wavelengths and accumulates them (ln values in log mode) in registers, then
-// writes the item's 64-byte record.  Values, not decisions: FP32 sums.
-template <int D>
+// writes the item's record: 64 bytes in FP32, or 32 bytes rounded to nearest
+// even in BF16 / FP16 (packed at half the stride in the same buffer).  Values,
+// not decisions: FP32 sums.
+__device__ __forceinline__ unsigned enc_bits(__hip_bfloat16, float v)
+{
+    return __bfloat16_as_ushort(Codec<__hip_bfloat16>::enc(v));
+}
+__device__ __forceinline__ unsigned enc_bits(__half, float v) { return __half_as_ushort(Codec<__half>::enc(v)); }
+
+template <int D, typename T>
 __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, SceneBufs bufs, LamBatch lb, int n_v,
                                                           float ds0, int avg_mode)
 {
@@ -176,34 +186,54 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
             }
         }
         const float inv = 1.0f / (float)nvx;
-        float4* out = (float4*)(bufs.vnodes + ((rec * n_v + kn) * kLam) * 2);
+        float r[2 * kLam];
 #pragma unroll
-        for (int l = 0; l < kLam; l += 2) {
-            float r[4];
-            for (int j = 0; j < 2; ++j) {
-                float oe = ae[l + j] * inv, oc = ac[l + j] * inv;
-                if (m > 0 && logm) {
-                    oe = __expf(oe) / ds0;
-                    oc = __expf(oc) / ds0;
-                }
-                r[2 * j] = oe;
-                r[2 * j + 1] = oc;
+        for (int l = 0; l < kLam; ++l) {
+            float oe = ae[l] * inv, oc = ac[l] * inv;
+            if (m > 0 && logm) {
+                oe = __expf(oe) / ds0;
+                oc = __expf(oc) / ds0;
             }
-            out[l / 2] = make_float4(r[0], r[1], r[2], r[3]);
+            r[2 * l] = oe;
+            r[2 * l + 1] = oc;
+        }
+        const long long o = (rec * n_v + kn) * (kLam * 2);  // in elements of T
+        if constexpr (std::is_same<T, float>::value) {
+            float4* out = (float4*)(bufs.vnodes + o);
+#pragma unroll
+            for (int q = 0; q < kLam / 2; ++q) out[q] = make_float4(r[4 * q], r[4 * q + 1], r[4 * q + 2], r[4 * q + 3]);
+        } else {
+            uint4* out = (uint4*)((T*)bufs.vnodes + o);
+            unsigned wd[kLam];
+#pragma unroll
+            for (int q = 0; q < kLam; ++q) wd[q] = enc_bits(T(), r[2 * q]) | (enc_bits(T(), r[2 * q + 1]) << 16);
+#pragma unroll
+            for (int q = 0; q < kLam / 4; ++q) out[q] = make_uint4(wd[4 * q], wd[4 * q + 1], wd[4 * q + 2], wd[4 * q + 3]);
         }
     }
 }
 
+template <int D>
+static void launch_nodes_dim(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, const LamBatch& lb,
+                             int n_v, float ds0, int avg_mode, int storage, hipStream_t s)
+{
+    if (storage == RT_F32)
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, float>), dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, ds0,
+                           avg_mode);
+    else if (storage == RT_BF16)
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, __hip_bfloat16>), dim3(n_active), dim3(256), 0, s, g, in, b, lb,
+                           n_v, ds0, avg_mode);
+    else
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, __half>), dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, ds0,
+                           avg_mode);
+}
+
 hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
-                                  const LamBatch& lb, int n_v, double ds0, int avg_mode, hipStream_t s)
+                                  const LamBatch& lb, int n_v, double ds0, int avg_mode, int storage, hipStream_t s)
 {
     if (n_active == 0) return hipSuccess;
-    if (g.dim == 2)
-        hipLaunchKernelGGL(k_velinterp_nodes2<2>, dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, (float)ds0,
-                           avg_mode);
-    else
-        hipLaunchKernelGGL(k_velinterp_nodes2<3>, dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, (float)ds0,
-                           avg_mode);
+    if (g.dim == 2) launch_nodes_dim<2>(g, in, b, n_active, lb, n_v, (float)ds0, avg_mode, storage, s);
+    else launch_nodes_dim<3>(g, in, b, n_active, lb, n_v, (float)ds0, avg_mode, storage, s);
     return hipGetLastError();
 }
 

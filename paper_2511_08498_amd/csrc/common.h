@@ -124,7 +124,7 @@ hipError_t launch_build_static(const Geo& g, const Inputs& in, const SceneBufs& 
 hipError_t launch_pack_states(const Geo& g, const int8_t* levels, uint64_t* states, hipStream_t s);
 hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, hipStream_t s);
 hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
-                                  const LamBatch& lb, int n_v, double ds0, int avg_mode, hipStream_t s);
+                                  const LamBatch& lb, int n_v, double ds0, int avg_mode, int storage, hipStream_t s);
 hipError_t launch_cav_chain(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_lines,
                             double ds0, int avg_mode, hipStream_t s);
 hipError_t launch_read_cells(const Geo& g, const SceneBufs& b, int storage, int n, const int32_t* cells,

@@ -639,7 +639,8 @@ struct VisStatic {
     }
 };
 
-template <int D, class Acc = AccPlain>
+// T: storage of the node records (FP32, or BF16 / FP16 at half the record size).
+template <int D, typename T = float, class Acc = AccPlain>
 struct VisVelinterp {
     using AccT = Acc;
     static constexpr int kMinWaves = (D == 2 && !Acc::kTrunc && !Acc::kJ) ? 4 : 1;
@@ -677,11 +678,11 @@ struct VisVelinterp {
         int kn = (int)floorf(f);
         kn = kn < 0 ? 0 : (kn > nv - 2 ? nv - 2 : kn);
         float wt = f - (float)kn;
-        // the two node records around u are adjacent (128 B)
-        const float* r0 = tl->vnodes + (cell * (unsigned)nv + (unsigned)kn) * (unsigned)(kLam * 2);
+        // the two node records around u are adjacent (128 B in FP32, 64 B in BF16 / FP16)
+        const T* r0 = (const T*)tl->vnodes + (cell * (unsigned)nv + (unsigned)kn) * (unsigned)(kLam * 2);
         float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
-        load_rec<float>(r0, e0, x0);
-        load_rec<float>(r0 + kLam * 2, e1, x1);
+        load_rec<T>(r0, e0, x0);
+        load_rec<T>(r0 + kLam * 2, e1, x1);
         float ee[kLam], xx[kLam];
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
@@ -1042,8 +1043,14 @@ static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
         return launch_one<3, VisStatic<3, __half, Acc>>(t, s);
     }
     if (t.emission == RT_EMIS_VELINTERP) {
-        if (t.g.dim == 2) return launch_one<2, VisVelinterp<2, Acc>>(t, s);
-        return launch_one<3, VisVelinterp<3, Acc>>(t, s);
+        if (t.g.dim == 2) {
+            if (t.storage == RT_F32) return launch_one<2, VisVelinterp<2, float, Acc>>(t, s);
+            if (t.storage == RT_BF16) return launch_one<2, VisVelinterp<2, __hip_bfloat16, Acc>>(t, s);
+            return launch_one<2, VisVelinterp<2, __half, Acc>>(t, s);
+        }
+        if (t.storage == RT_F32) return launch_one<3, VisVelinterp<3, float, Acc>>(t, s);
+        if (t.storage == RT_BF16) return launch_one<3, VisVelinterp<3, __hip_bfloat16, Acc>>(t, s);
+        return launch_one<3, VisVelinterp<3, __half, Acc>>(t, s);
     }
     if (t.g.dim == 2) {
         return launch_cav<2, Acc>(t, s);
