@@ -22,14 +22,28 @@
 
 namespace rt {
 
+// Scenes have at most 8192 voxels per axis (checked at creation): block
+// coordinates stay below 2^10 and block indices below 2^30, so block
+// arithmetic is exact in 32 bits and its products in 24 bits.
 __device__ __forceinline__ int block_level(const uint64_t* sts, long long b, int mode, int maxl)
 {
-    int w = (int)(b / kStatesPerWord);
-    int sh = 3 * (int)(b - (long long)w * kStatesPerWord);
+    const unsigned bb = (unsigned)b;
+    const unsigned w = bb / (unsigned)kStatesPerWord;
+    const unsigned sh = 3u * (bb - w * (unsigned)kStatesPerWord);
     int s = (int)((sts[w] >> sh) & 7ull);
     if (s == 0) return -1;
     int l = mode == RT_TRACE_LEVEL0 ? 0 : s - 1;
     return l < maxl ? l : maxl;
+}
+
+// Block index of an in-grid cell.
+template <int D>
+__device__ __forceinline__ long long block_of(const Geo& g, const int* c)
+{
+    const unsigned l = (unsigned)g.log2B;
+    unsigned r = (unsigned)c[1] >> l;
+    if (D > 2) r += __umul24((unsigned)g.nb[1], (unsigned)c[2] >> l);
+    return (long long)(((unsigned)c[0] >> l) + __umul24((unsigned)g.nb[0], r));
 }
 
 // Fine cell (multiple of nvs inside [c0, c0 + vs)) containing x_a(t*) with
@@ -152,8 +166,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         capp = path_cap(ld, g.n_levels, t);
         tb = capp + 1 < g.n_levels ? ld[capp + 1] : INFINITY;
     }
-    long long blk = (c0[0] >> g.log2B) +
-                    (long long)g.nb[0] * ((c0[1] >> g.log2B) + (long long)g.nb[1] * (c0[2] >> g.log2B));
+    long long blk = block_of<D>(g, c0);
     int cap0 = maxl;
     if (graded == 2) {
         cap0 = capp < maxl ? capp : maxl;
@@ -284,8 +297,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
         }
         if (out) return 0;
         if (bchg) {
-            blk = (c[0] >> g.log2B) +
-                  (long long)g.nb[0] * ((c[1] >> g.log2B) + (long long)g.nb[1] * (c[2] >> g.log2B));
+            blk = block_of<D>(g, c);
             int nl;
             if (graded == 2) {
                 // the path cap at the crossing (exact), and the new block's level under it
