@@ -139,6 +139,8 @@ static void make_geo(const rt_scene_desc* d, Geo& g)
         if (m < d->n_levels) off += 1 << (d->dim * (log2B - m));
     }
     g.cells = off;
+    g.lvl_pack = 0;
+    for (int m = 0; m < kMaxLevels; ++m) g.lvl_pack |= (unsigned long long)g.lvl_off[m] << (11 * m);
     g.n_state_words = (int)((g.nblocks + kStatesPerWord - 1) / kStatesPerWord);
     g.feat_level = std::min(2, d->n_levels - 1);
 }

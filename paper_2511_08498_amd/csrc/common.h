@@ -14,6 +14,7 @@ namespace rt {
 constexpr int kLam = RT_LAM_BATCH;   // wavelengths per batch, kept in registers by the march
 constexpr int kMaxLines = RT_MAX_LINES;
 constexpr int kMaxLevels = RT_MAX_LEVELS;
+constexpr long long kSlotLdsMax = 8192;  // blocks whose slot table a trace workgroup keeps in LDS (32 KiB)
 constexpr int kStatesPerWord = 21;   // 3-bit block states per 64-bit word
 constexpr double kCkms = 299792.458; // speed of light, km/s
 
@@ -28,6 +29,7 @@ struct Geo {
     int bvox;         // B^dim voxels per block
     int cells;        // cells per block over all levels
     int lvl_off[kMaxLevels + 1];  // first cell of each level inside a block record
+    unsigned long long lvl_pack;  // lvl_off[m] in bits 11m .. 11m + 10, m < kMaxLevels (cells < 2^11)
     long long nblocks;
     int n_state_words;
     int feat_level;   // level whose statistics are kept as neural-cache features (min(2, n_levels - 1))
@@ -136,6 +138,7 @@ struct TraceLaunch {
     Geo g;
     const uint64_t* states;
     const int32_t* slot;
+    int slot_lds;  // the trace kernels copy slot[] to LDS after the state words (grids of <= kSlotLdsMax blocks)
     const void* vals;
     const float4* vgrid;
     const float* vnodes;

@@ -418,6 +418,36 @@ __device__ __forceinline__ void load_rec<__half>(const __half* r, float* e, floa
     }
 }
 
+// First cell of level lvl inside a block record, unpacked from the launch's
+// 11-bit level offsets (a block holds at most 585 cells): a per-lane indexed
+// load here would sit in front of every cell fetch.
+__device__ __forceinline__ int level_offset(const Geo& g, int lvl)
+{
+    return (int)((g.lvl_pack >> (11 * lvl)) & 2047ull);
+}
+
+// Storage slot of block blk: from the trace workgroup's LDS copy of the slot
+// table (placed after the state words) on small grids, else from global memory.
+__device__ __forceinline__ long long block_slot(const Geo& g, const int32_t* slot, int lds, long long blk)
+{
+    if (lds) {
+        extern __shared__ uint64_t lds_words[];
+        return ((const int32_t*)(lds_words + g.n_state_words))[blk];
+    }
+    return slot[blk];
+}
+
+// Copies the block-state words, and on small grids the slot table, to LDS.
+__device__ __forceinline__ void stage_blocks(const TraceLaunch& t, uint64_t* sts)
+{
+    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
+    if (t.slot_lds) {
+        int32_t* ls = (int32_t*)(sts + t.g.n_state_words);
+        for (long long i = threadIdx.x; i < t.g.nblocks; i += blockDim.x) ls[i] = t.slot[i];
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ int local_index(const Geo& g, const int* c, int lvl, int D)
 {
     int sl = g.log2B - lvl;
@@ -623,6 +653,7 @@ struct VisStatic {
     long long cur_blk;
     long long base;
     float dsf;
+    int slot_lds;
     Acc acc;
     __device__ void init_src(const Geo* geo, const int32_t* sl, const void* v, float ds0)
     {
@@ -632,19 +663,21 @@ struct VisStatic {
         cur_blk = -1;
         base = 0;
         dsf = ds0;
+        slot_lds = 0;
     }
     __device__ void init(const TraceLaunch* t, const float*)
     {
         init_src(&t->g, t->slot, t->vals, t->ds0);
+        slot_lds = t->slot_lds;
         acc.init(t);
     }
     __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
     {
         if (blk != cur_blk) {
             cur_blk = blk;
-            base = (long long)slot[blk] * g->cells;
+            base = block_slot(*g, slot, slot_lds, blk) * g->cells;
         }
-        const T* r = vals + (base + g->lvl_off[lvl] + local_index(*g, c, lvl, D)) * (kLam * 2);
+        const T* r = vals + (base + level_offset(*g, lvl) + local_index(*g, c, lvl, D)) * (kLam * 2);
         float e[kLam], x[kLam];
         load_rec<T>(r, e, x);
         return acc.add(e, x, c, lvl, blk, t0, t1, dsf);
@@ -677,9 +710,9 @@ struct VisVelinterp {
     {
         if (blk != cur_blk) {
             cur_blk = blk;
-            base = (long long)tl->slot[blk] * tl->g.cells;
+            base = block_slot(tl->g, tl->slot, tl->slot_lds, blk) * tl->g.cells;
         }
-        const unsigned cell = (unsigned)(base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D));
+        const unsigned cell = (unsigned)(base + level_offset(tl->g, lvl) + local_index(tl->g, c, lvl, D));
         // vgrid = (s, vbar): node coordinate f = (u + V)/(2V) (n_v - 1) = u s + (n_v - 1)/2,
         // s = (n_v - 1)/(2V) (0 when V = 0: all nodes are equal, the middle one is used)
         float4 vg = tl->vgrid[cell];
@@ -733,9 +766,9 @@ struct VisCav {
     {
         if (blk != cur_blk) {
             cur_blk = blk;
-            base = (long long)tl->slot[blk] * tl->g.cells;
+            base = block_slot(tl->g, tl->slot, tl->slot_lds, blk) * tl->g.cells;
         }
-        long long cell = base + tl->g.lvl_off[lvl] + local_index(tl->g, c, lvl, D);
+        long long cell = base + level_offset(tl->g, lvl) + local_index(tl->g, c, lvl, D);
         const T* r = (const T*)(sizeof(T) == 4 ? (const void*)tl->cav : tl->cav_lp) + cell * tl->cav_rec;
         const int nln = tl->lb.n_lines;
         float ls[NL][4];
@@ -874,8 +907,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Vis::k
 k_trace(TraceLaunch t)
 {
     extern __shared__ uint64_t sts[];
-    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
-    __syncthreads();
+    stage_blocks(t, sts);
     // XCD-aware order: workgroups are dealt round-robin over the 8 XCDs; give
     // each XCD a contiguous range of (direction, probe tile) work.
     const unsigned G = gridDim.x, wg = blockIdx.x;
@@ -924,8 +956,7 @@ template <int D, class Vis>
 __global__ void __launch_bounds__(256) k_trace_j(TraceLaunch t)
 {
     extern __shared__ uint64_t sts[];
-    for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
-    __syncthreads();
+    stage_blocks(t, sts);
     const unsigned G = gridDim.x, wg = blockIdx.x;
     const unsigned q = G / 8u, r = G % 8u, xcd = wg % 8u, i = wg / 8u;
     const unsigned lwg = xcd < r ? xcd * (q + 1u) + i : r * (q + 1u) + (xcd - r) * q + i;
@@ -1007,10 +1038,14 @@ hipError_t launch_reduce_chunks(const float* part, int n_chunks, long long n, fl
 }
 
 template <int D, class Vis>
-static hipError_t launch_one(const TraceLaunch& t, hipStream_t s)
+static hipError_t launch_one(const TraceLaunch& t0, hipStream_t s)
 {
+    TraceLaunch t = t0;
     long long tiles = (t.n_probes + 63) / 64;
     size_t shm = sizeof(uint64_t) * (size_t)t.g.n_state_words;
+    // small grids: the slot table joins the state words in LDS (at most 32 KiB more per workgroup)
+    t.slot_lds = t.g.nblocks <= kSlotLdsMax ? 1 : 0;
+    if (t.slot_lds) shm += sizeof(int32_t) * (size_t)t.g.nblocks;
     if constexpr (Vis::AccT::kJ) {
         const long long n_chunks = (t.n_dir + t.dirs_per_chunk - 1) / t.dirs_per_chunk;
         const long long wgs = (tiles * n_chunks + 3) / 4;
