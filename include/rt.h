@@ -239,6 +239,7 @@ typedef struct rt_scene_info {
 typedef struct rt_device_err {
     unsigned long long step_cap_hits; /* rays stopped at the step cap */
     long long first_ray;              /* smallest ray id that hit it, -1 if none */
+    unsigned long long bad_probes;    /* caller probe indices outside [0, nvox): not traced, outputs NaN */
 } rt_device_err;
 
 typedef struct rt_scene rt_scene;
@@ -283,7 +284,10 @@ rt_status rt_scene_build(rt_scene* scene, const rt_build_params* params, int32_t
  * RteIntegral per segment).
  *   d_dirs     device float [n_dir][dim], unit vectors (|w| - 1 within 1e-5).
  *   d_probes   device int32 [n_probes] voxel linear indices, or NULL for all
- *              probes (then n_probes must equal rt_scene_info.n_probes).
+ *              probes (then n_probes must equal rt_scene_info.n_probes).  An
+ *              index outside [0, nvox) is not traced: its outputs are NaN and
+ *              rt_scene_device_error counts it (bad_probes); the same holds for
+ *              every entry point that takes a probe list.
  *   d_I        device float [n_dir][lam_end - lam_begin][n_probes]: intensity
  *              arriving at each probe along each direction.
  * n_probes = 0 traces nothing (d_probes and d_I may then be NULL).

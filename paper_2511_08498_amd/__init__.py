@@ -82,7 +82,8 @@ class RtSceneInfo(ctypes.Structure):
 
 
 class RtDeviceErr(ctypes.Structure):
-    _fields_ = [("step_cap_hits", ctypes.c_ulonglong), ("first_ray", ctypes.c_longlong)]
+    _fields_ = [("step_cap_hits", ctypes.c_ulonglong), ("first_ray", ctypes.c_longlong),
+                ("bad_probes", ctypes.c_ulonglong)]
 
 
 class RtBatchJob(ctypes.Structure):
@@ -545,6 +546,12 @@ class Scene:
         e = RtDeviceErr()
         _check(lib().rt_scene_device_error(self.h, ctypes.byref(e)))
         return int(e.step_cap_hits), int(e.first_ray)
+
+    def bad_probes(self):
+        """Probe indices outside the grid met by traces since the last reset (their outputs are NaN)."""
+        e = RtDeviceErr()
+        _check(lib().rt_scene_device_error(self.h, ctypes.byref(e)))
+        return int(e.bad_probes)
 
     def reset_device_error(self, stream=None):
         _check(lib().rt_scene_reset_device_error(self.h, _stream(stream)))

@@ -153,7 +153,7 @@ static size_t scene_bytes(const rt_scene_desc* d, const Geo& g, long long na)
 {
     const size_t nb = (size_t)g.nblocks, cells = (size_t)na * g.cells;
     size_t b = alloc_bytes(nb, 4) + alloc_bytes(nb, 1) + alloc_bytes(nb, 4) + alloc_bytes(nb, 4) + alloc_bytes(1, 4) +
-               alloc_bytes(nb, 1) + alloc_bytes((size_t)g.n_state_words, 8) + alloc_bytes(2, 8) +
+               alloc_bytes(nb, 1) + alloc_bytes((size_t)g.n_state_words, 8) + alloc_bytes(4, 8) +
                alloc_bytes(1, 8);  // the last: the input-validation counter
     b += alloc_bytes(((size_t)na << (d->dim * (g.log2B - g.feat_level))) * kLam, 16);
     if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) b += alloc_bytes(cells * kLam * 2, 4);
@@ -239,12 +239,13 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     if ((st = sc->alloc(&B.n_active, 1)) != RT_OK) return cleanup(st);
     if ((st = sc->alloc(&B.levels, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
     if ((st = sc->alloc(&B.states, (size_t)g.n_state_words)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.err, 2)) != RT_OK) return cleanup(st);
+    if ((st = sc->alloc(&B.err, 4)) != RT_OK) return cleanup(st);
     hipError_t e;
     if ((e = hipMemcpyAsync(B.morton, morton.data(), morton.size() * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
         hipSuccess)
         return cleanup(fail(RT_E_HIP, "upload: %s", hipGetErrorString(e)));
-    unsigned long long err0[2] = {0ull, ~0ull};
+    // step-cap hits, first ray that hit the cap, probe indices outside the grid, unused
+    unsigned long long err0[4] = {0ull, ~0ull, 0ull, 0ull};
     if ((e = hipMemcpyAsync(B.err, err0, sizeof(err0), hipMemcpyHostToDevice, s)) != hipSuccess)
         return cleanup(fail(RT_E_HIP, "upload: %s", hipGetErrorString(e)));
     unsigned long long* d_bad = nullptr;
@@ -684,18 +685,19 @@ rt_status rt_debug_visited(const rt_scene* sc, const rt_trace_params* p, int32_t
 rt_status rt_scene_device_error(const rt_scene* sc, rt_device_err* h)
 {
     if (!sc || !h) return fail(RT_E_ARG, "null argument");
-    unsigned long long v[2];
+    unsigned long long v[4];
     RT_HIP(hipDeviceSynchronize());
     RT_HIP(hipMemcpy(v, sc->b.err, sizeof(v), hipMemcpyDeviceToHost));
     h->step_cap_hits = v[0];
     h->first_ray = v[0] ? (long long)v[1] : -1;
+    h->bad_probes = v[2];
     return RT_OK;
 }
 
 rt_status rt_scene_reset_device_error(rt_scene* sc, void* stream)
 {
     if (!sc) return fail(RT_E_ARG, "null argument");
-    unsigned long long err0[2] = {0ull, ~0ull};
+    unsigned long long err0[4] = {0ull, ~0ull, 0ull, 0ull};
     RT_HIP(hipMemcpyAsync(sc->b.err, err0, sizeof(err0), hipMemcpyHostToDevice, (hipStream_t)stream));
     RT_HIP(hipStreamSynchronize((hipStream_t)stream));
     return RT_OK;
@@ -865,6 +867,7 @@ rt_status rt_batch_device_error(const rt_batch* bt, rt_device_err* h)
     RT_HIP(hipMemcpy(v, bt->err, sizeof(v), hipMemcpyDeviceToHost));
     h->step_cap_hits = v[0];
     h->first_ray = v[0] ? (long long)v[1] : -1;
+    h->bad_probes = 0;  // batched jobs trace every probe of their scenes
     return RT_OK;
 }
 

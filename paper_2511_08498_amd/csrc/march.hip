@@ -815,6 +815,34 @@ struct VisCav {
 };
 
 // ------------------------------------------------------------ trace kernel
+// A caller's probe index outside the grid's voxels: the ray is not traced, its
+// outputs are NaN, and the first direction's ray counts it in err[2].
+__device__ __forceinline__ bool bad_probe(const TraceLaunch& t, long long v)
+{
+    return v < 0 || v >= (long long)t.g.n[0] * t.g.n[1] * t.g.n[2];
+}
+
+template <class Acc>
+__device__ __forceinline__ void write_bad_probe(const TraceLaunch& t, long long dir, long long probe)
+{
+    const float nan = __builtin_nanf("");
+    const int nl = t.lb.nl;
+    if (dir == 0) atomicAdd(&t.err[2], 1ull);
+    for (int l = 0; l < nl; ++l) {
+        const long long q = ((long long)dir * nl + l) * t.n_probes + probe;
+        if constexpr (Acc::kTrunc) {
+            t.I_near[q] = nan;
+            t.T_near[q] = nan;
+            if constexpr (Acc::kGen) t.I_far[q] = nan;
+            t.fstat_out[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+        } else {
+            t.I[q] = nan;
+            if (Acc::kIv && t.T_out) t.T_out[q] = nan;
+        }
+    }
+    if constexpr (Acc::kTrunc) t.feat[dir * t.n_probes + probe] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
 // One ray (direction dir, probe index probe) of a trace launch.
 template <int D, class Vis>
 __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* sts, long long dir, long long probe,
@@ -823,6 +851,10 @@ __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* 
     int pv[3] = {0, 0, 0};
     if (t.probes) {
         long long v = t.probes[probe];
+        if (bad_probe(t, v)) {
+            write_bad_probe<typename Vis::AccT>(t, dir, probe);
+            return;
+        }
         pv[0] = (int)(v % t.g.n[0]);
         pv[1] = (int)((v / t.g.n[0]) % t.g.n[1]);
         pv[2] = (int)(v / ((long long)t.g.n[0] * t.g.n[1]));
@@ -968,11 +1000,22 @@ __global__ void __launch_bounds__(256) k_trace_j(TraceLaunch t)
     const long long d0 = chunk * t.dirs_per_chunk;
     if (d0 >= t.n_dir) return;  // whole wave
     const long long d1 = d0 + t.dirs_per_chunk < t.n_dir ? d0 + t.dirs_per_chunk : t.n_dir;
-    const bool live = probe < t.n_probes;
+    bool live = probe < t.n_probes;
     int pv[3] = {0, 0, 0};
     if (live) {
         if (t.probes) {
             long long v = t.probes[probe];
+            if (bad_probe(t, v)) {
+                // not traced: NaN partials make the probe's J and psi NaN
+                if (chunk == 0) atomicAdd(&t.err[2], 1ull);
+                const int nl = t.lb.nl;
+                for (int l = 0; l < nl; ++l) {
+                    const long long o = (chunk * nl + l) * t.n_probes + probe;
+                    t.part_J[o] = __builtin_nanf("");
+                    if (t.part_psi) t.part_psi[o] = __builtin_nanf("");
+                }
+                return;
+            }
             pv[0] = (int)(v % t.g.n[0]);
             pv[1] = (int)((v / t.g.n[0]) % t.g.n[1]);
             pv[2] = (int)(v / ((long long)t.g.n[0] * t.g.n[1]));

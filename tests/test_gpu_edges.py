@@ -1,4 +1,5 @@
-"""GPU edge cases: a scene with no active block, empty probe lists, probes inside empty blocks.
+"""GPU edge cases: a scene with no active block, empty probe lists, probes inside empty blocks, probe
+indices outside the grid.
 
 Rays through empty space carry the boundary intensity unchanged (the recurrence of
 Eq. RteIntegral with eta = chi = 0), so these cases have exact answers.
@@ -83,6 +84,38 @@ def test_empty_probe_lists(rt):
     assert tuple(I.shape) == (8, 8, 0) and tuple(T.shape) == (8, 8, 0)
     J, psi = scene.trace_j(dirs, probes=none)
     assert tuple(J.shape) == (8, 0)
+
+
+def test_probe_indices_outside_the_grid(rt):
+    """A probe index outside [0, nvox) is not traced: its outputs are NaN in every entry point, the valid
+    probes of the same list are unaffected, and each bad index is counted once per call."""
+    import torch
+    sc = make_cfg1()
+    scene = rt.Scene.from_dict(sc)
+    scene.build(0, 8, iod_threshold=1e-2)
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    nvox = 64 * 64
+    good = np.array([0, 77, 1000, nvox - 1], np.int32)
+    bad = np.array([-1, nvox, 2 ** 31 - 1], np.int32)
+    mixed = np.array([good[0], bad[0], good[1], bad[1], good[2], bad[2], good[3]], np.int32)
+    isbad = np.isin(mixed, bad) & ~np.isin(mixed, good)
+    scene.reset_device_error()
+    I_ref = scene.trace(dirs, probes=good).cpu().numpy()
+    assert scene.bad_probes() == 0
+    I = scene.trace(dirs, probes=mixed).cpu().numpy()
+    assert scene.bad_probes() == bad.size
+    assert np.all(np.isnan(I[:, :, isbad])) and np.array_equal(I[:, :, ~isbad], I_ref)
+    Iv, Tv = scene.trace_interval(dirs, 1.5, 6.0, probes=mixed)
+    Iv_ref, Tv_ref = scene.trace_interval(dirs, 1.5, 6.0, probes=good)
+    assert torch.all(torch.isnan(Iv[:, :, isbad])) and torch.all(torch.isnan(Tv[:, :, isbad]))
+    assert torch.equal(Iv[:, :, ~isbad], Iv_ref) and torch.equal(Tv[:, :, ~isbad], Tv_ref)
+    J, psi = scene.trace_j(dirs, probes=mixed)
+    J_ref, psi_ref = scene.trace_j(dirs, probes=good)
+    assert torch.all(torch.isnan(J[:, isbad])) and torch.equal(J[:, ~isbad], J_ref)
+    assert torch.equal(psi[:, ~isbad], psi_ref)
+    assert scene.bad_probes() == 3 * bad.size
+    scene.reset_device_error()
+    assert scene.bad_probes() == 0 and scene.device_error() == (0, -1)
 
 
 def test_probes_inside_empty_blocks(rt):
