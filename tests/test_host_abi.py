@@ -17,7 +17,7 @@ def _layout_bytes(nb, n_state_words, na, cells, feat_cells, n_lam_batch=8):
     active count, levels, states, error counters, input-validation counter, level statistics
     [na][feat cells][8] float4, values [na][cells][8][eta, chi] float."""
     a = lambda n: max(n, 256)  # noqa: E731
-    return (a(4 * nb) + a(nb) + a(4 * nb) + a(4 * nb) + a(4) + a(nb) + a(8 * n_state_words) + a(16) + a(8)
+    return (a(4 * nb) + a(nb) + a(4 * nb) + a(4 * nb) + a(4) + a(nb) + a(8 * n_state_words) + a(32) + a(8)
             + a(16 * na * feat_cells * n_lam_batch) + a(4 * 2 * n_lam_batch * na * cells))
 
 
