@@ -125,11 +125,24 @@ __device__ __forceinline__ void row_raw(const NrcFwd& a, long long row, float* r
         w = p[11];
         tgt = a.target[src];
     } else {
-        long long per_dir = (long long)a.nl * a.np;
-        long long d = row / per_dir;
-        long long rem = row - d * per_dir;
-        long long l = rem / a.np, p = rem - l * a.np;
+        long long d, l, p;
+        if (a.rows <= 0xffffffffll) {
+            // 32-bit decode (the common case: fewer than 2^32 rows per call)
+            const unsigned per_dir = (unsigned)a.nl * (unsigned)a.np, np32 = (unsigned)a.np;
+            const unsigned rw = (unsigned)row, d32 = rw / per_dir, rem = rw - d32 * per_dir, l32 = rem / np32;
+            d = d32;
+            l = l32;
+            p = rem - l32 * np32;
+        } else {
+            const long long per_dir = (long long)a.nl * a.np;
+            d = row / per_dir;
+            const long long rem = row - d * per_dir;
+            l = rem / a.np;
+            p = rem - l * a.np;
+        }
         float4 f = a.feat[d * a.np + p];
+        w = f.w;
+        if (!(f.w > 0.f)) return;  // no query on this ray: the row is copied, its features are not needed
         r[0] = f.x * a.inv_n[0];
         r[1] = f.y * a.inv_n[1];
         r[2] = f.z * a.inv_n[2];
@@ -140,7 +153,6 @@ __device__ __forceinline__ void row_raw(const NrcFwd& a, long long row, float* r
         r[8] = log1pf(fmaxf(s.y, 0.f));
         r[9] = (s.z - s.x) * 0.1f;
         r[10] = log1pf(fmaxf(s.w, 0.f));
-        w = f.w;
     }
 }
 
