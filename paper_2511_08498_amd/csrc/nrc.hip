@@ -156,6 +156,25 @@ __device__ __forceinline__ void row_raw(const NrcFwd& a, long long row, float* r
     }
 }
 
+// Inference-compose: whether row `row` (q = (d nl + l) np + p) belongs to a ray with a query.
+__device__ __forceinline__ bool row_queried(const NrcFwd& a, long long row)
+{
+    if (row >= a.rows) return false;
+    long long d, p;
+    if (a.rows <= 0xffffffffll) {
+        const unsigned per_dir = (unsigned)a.nl * (unsigned)a.np, np32 = (unsigned)a.np;
+        const unsigned rw = (unsigned)row, d32 = rw / per_dir, rem = rw - d32 * per_dir;
+        d = d32;
+        p = rem - (rem / np32) * np32;
+    } else {
+        const long long per_dir = (long long)a.nl * a.np;
+        d = row / per_dir;
+        const long long rem = row - d * per_dir;
+        p = rem - (rem / a.np) * a.np;
+    }
+    return a.feat[d * a.np + p].w > 0.f;
+}
+
 __global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
 {
     __shared__ __attribute__((aligned(16))) __bf16 sW1[kHid * kFeat];
@@ -188,95 +207,113 @@ __global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
     float lsum = 0.f;
     const long long n_tiles = (a.rows + 15) / 16;
     const long long wstride = (long long)gridDim.x * 4;
-    for (long long tile = (long long)blockIdx.x * 4 + wv; tile < n_tiles; tile += wstride) {
-        const long long row_a = tile * 16 + r16;  // the row this lane feeds as an A operand
-        float r[11], w, tgt;
-        bool valid;
-        row_raw(a, row_a, r, w, tgt, valid);
-        if (a.mode == 1 && !__any(valid && w > 0.f)) {
-            // no query in these 16 rows (rays that left the grid or fell back): copy I_near
-            if (g == 0 && valid) a.I_out[row_a] = a.I_near[row_a];
-            continue;
-        }
-        // ---- layer 1: 256 -> 64
-        f32x4 acc[4];
-        for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < kFeat / 32; ++ks) {
-            bf16x8 av;
-            const int k0 = 32 * ks + 8 * g;
-            for (int j = 0; j < 8; ++j) av[j] = (__bf16)(valid ? encode(r, k0 + j, a.lg2fmax) : 0.f);
-            if (a.mode == 0 && a.x_out && valid) *(bf16x8*)(a.x_out + row_a * kFeat + k0) = av;
-            for (int nt = 0; nt < 4; ++nt) {
-                bf16x8 bv = *(const bf16x8*)(sW1 + (16 * nt + r16) * kFeat + k0);
-                acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+    // inference-compose: a wave first checks 64 rows (one per lane); a group without any query
+    // (rays that left the grid or fell back) is copied whole, a group with one runs its 4 tiles
+    const bool grouped = a.mode == 1;
+    const long long n_items = grouped ? (a.rows + 63) / 64 : n_tiles;
+    for (long long item = (long long)blockIdx.x * 4 + wv; item < n_items; item += wstride) {
+        int n_sub = 1;
+        long long tile0 = item;
+        if (grouped) {
+            const long long row = item * 64 + lane;
+            if (!__any(row_queried(a, row))) {
+                if (row < a.rows) a.I_out[row] = a.I_near[row];
+                continue;
             }
+            n_sub = 4;
+            tile0 = item * 4;
         }
-        // ---- hidden layers
-        for (int L = 0; L < 4; ++L) {
-            // bias + SiLU; D element (row 4 g + j, col 16 nt + r16)
-            for (int nt = 0; nt < 4; ++nt)
-                for (int j = 0; j < 4; ++j) {
-                    float z = acc[nt][j] + bias[L][nt];
-                    float h = silu(z);
-                    const int row = 4 * g + j, col = 16 * nt + r16;
-                    sH[wv][row * kHid + col] = (__bf16)h;
-                    const long long grow = tile * 16 + row;
-                    if (a.mode == 0 && grow < a.rows) {
-                        if (a.z_out) a.z_out[((long long)L * a.rows + grow) * kHid + col] = z;
-                        if (a.h_out) a.h_out[((long long)L * a.rows + grow) * kHid + col] = (__bf16)h;
-                    }
-                    acc[nt][j] = h;
-                }
-            if (L == 3) break;
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            f32x4 nacc[4];
-            for (int nt = 0; nt < 4; ++nt) nacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
-            for (int ks = 0; ks < kHid / 32; ++ks) {
+        for (int sub = 0; sub < n_sub; ++sub) {
+            const long long tile = tile0 + sub;
+            const long long row_a = tile * 16 + r16;  // the row this lane feeds as an A operand
+            float r[11], w, tgt;
+            bool valid;
+            row_raw(a, row_a, r, w, tgt, valid);
+            if (a.mode == 1 && !__any(valid && w > 0.f)) {
+                // no query in these 16 rows (rays that left the grid or fell back): copy I_near
+                if (g == 0 && valid) a.I_out[row_a] = a.I_near[row_a];
+                continue;
+            }
+            // ---- layer 1: 256 -> 64
+            f32x4 acc[4];
+            for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int ks = 0; ks < kFeat / 32; ++ks) {
+                bf16x8 av;
                 const int k0 = 32 * ks + 8 * g;
-                bf16x8 av = *(const bf16x8*)(&sH[wv][r16 * kHid + k0]);
+                for (int j = 0; j < 8; ++j) av[j] = (__bf16)(valid ? encode(r, k0 + j, a.lg2fmax) : 0.f);
+                if (a.mode == 0 && a.x_out && valid) *(bf16x8*)(a.x_out + row_a * kFeat + k0) = av;
                 for (int nt = 0; nt < 4; ++nt) {
-                    bf16x8 bv = *(const bf16x8*)(sW[L] + (16 * nt + r16) * kHid + k0);
-                    nacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, nacc[nt], 0, 0, 0);
+                    bf16x8 bv = *(const bf16x8*)(sW1 + (16 * nt + r16) * kFeat + k0);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+                }
+            }
+            // ---- hidden layers
+            for (int L = 0; L < 4; ++L) {
+                // bias + SiLU; D element (row 4 g + j, col 16 nt + r16)
+                for (int nt = 0; nt < 4; ++nt)
+                    for (int j = 0; j < 4; ++j) {
+                        float z = acc[nt][j] + bias[L][nt];
+                        float h = silu(z);
+                        const int row = 4 * g + j, col = 16 * nt + r16;
+                        sH[wv][row * kHid + col] = (__bf16)h;
+                        const long long grow = tile * 16 + row;
+                        if (a.mode == 0 && grow < a.rows) {
+                            if (a.z_out) a.z_out[((long long)L * a.rows + grow) * kHid + col] = z;
+                            if (a.h_out) a.h_out[((long long)L * a.rows + grow) * kHid + col] = (__bf16)h;
+                        }
+                        acc[nt][j] = h;
+                    }
+                if (L == 3) break;
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                f32x4 nacc[4];
+                for (int nt = 0; nt < 4; ++nt) nacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+                for (int ks = 0; ks < kHid / 32; ++ks) {
+                    const int k0 = 32 * ks + 8 * g;
+                    bf16x8 av = *(const bf16x8*)(&sH[wv][r16 * kHid + k0]);
+                    for (int nt = 0; nt < 4; ++nt) {
+                        bf16x8 bv = *(const bf16x8*)(sW[L] + (16 * nt + r16) * kHid + k0);
+                        nacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, nacc[nt], 0, 0, 0);
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                for (int nt = 0; nt < 4; ++nt) acc[nt] = nacc[nt];
+            }
+            // ---- output: y[row] = sum_c h4[row][c] w5[c] + b5 (h4 rounded to BF16 as the GEMMs see it)
+            float part[4];
+            for (int j = 0; j < 4; ++j) {
+                float s = 0.f;
+                for (int nt = 0; nt < 4; ++nt) s += (float)(__bf16)acc[nt][j] * w5[nt];
+                part[j] = s;
+            }
+            for (int o = 1; o < 16; o <<= 1)
+                for (int j = 0; j < 4; ++j) part[j] += __shfl_xor(part[j], o, 64);
+            // lanes with r16 == j hold row 4 g + j
+            float y = 0.f;
+            for (int j = 0; j < 4; ++j)
+                if (r16 == j) y = part[j] + b5;
+            if (r16 < 4) {
+                const long long grow = tile * 16 + 4 * g + r16;
+                float rr[11], ww, tt;
+                bool v2;
+                row_raw(a, grow, rr, ww, tt, v2);
+                if (v2) {
+                    if (a.yhat) a.yhat[grow] = y;
+                    if (a.mode == 0) {
+                        float e = y - tt;
+                        if (a.dy) a.dy[grow] = ww * 2.0f * e / (float)a.rows;
+                        lsum += ww * e * e;
+                    } else if (ww > 0.f) {
+                        float yc = fminf(fmaxf(y, -8.0f), 8.0f);
+                        a.I_out[grow] = fmaf(a.T_near[grow], __expf(10.0f * yc), a.I_near[grow]);
+                    } else {
+                        a.I_out[grow] = a.I_near[grow];
+                    }
                 }
             }
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            for (int nt = 0; nt < 4; ++nt) acc[nt] = nacc[nt];
         }
-        // ---- output: y[row] = sum_c h4[row][c] w5[c] + b5 (h4 rounded to BF16 as the GEMMs see it)
-        float part[4];
-        for (int j = 0; j < 4; ++j) {
-            float s = 0.f;
-            for (int nt = 0; nt < 4; ++nt) s += (float)(__bf16)acc[nt][j] * w5[nt];
-            part[j] = s;
-        }
-        for (int o = 1; o < 16; o <<= 1)
-            for (int j = 0; j < 4; ++j) part[j] += __shfl_xor(part[j], o, 64);
-        // lanes with r16 == j hold row 4 g + j
-        float y = 0.f;
-        for (int j = 0; j < 4; ++j)
-            if (r16 == j) y = part[j] + b5;
-        if (r16 < 4) {
-            const long long grow = tile * 16 + 4 * g + r16;
-            float rr[11], ww, tt;
-            bool v2;
-            row_raw(a, grow, rr, ww, tt, v2);
-            if (v2) {
-                if (a.yhat) a.yhat[grow] = y;
-                if (a.mode == 0) {
-                    float e = y - tt;
-                    if (a.dy) a.dy[grow] = ww * 2.0f * e / (float)a.rows;
-                    lsum += ww * e * e;
-                } else if (ww > 0.f) {
-                    float yc = fminf(fmaxf(y, -8.0f), 8.0f);
-                    a.I_out[grow] = fmaf(a.T_near[grow], __expf(10.0f * yc), a.I_near[grow]);
-                } else {
-                    a.I_out[grow] = a.I_near[grow];
-                }
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
     }
     if (a.mode == 0 && a.loss_part) {
         for (int o = 1; o < 64; o <<= 1) lsum += __shfl_xor(lsum, o, 64);
