@@ -3,8 +3,9 @@
 Velocity interpolation (2D, Gaussian lines + continuum, cfg2 recipe at 128^2)
 and Core and Voigt (3D 32^3, two Voigt lines): block levels (exact outside
 the threshold tie band), intensities on the same adapted cells, level-0
-equivalence with the Classic march, and the approximation error against the
-dense Classic march (reported).
+equivalence with the Classic march, BF16/FP16 storage of velocity nodes and
+line parameters within their rounding bounds, and the approximation error
+against the dense Classic march (reported).
 """
 import math
 
