@@ -642,6 +642,14 @@ struct AccJ {
     }
 };
 
+// Whether an accumulator is the inference-mode truncated one (no far-field accumulation).
+template <class A>
+constexpr bool trunc_inference()
+{
+    if constexpr (A::kTrunc) return !A::kGen;
+    else return false;
+}
+
 // ------------------------------------------------------------- visitors
 template <int D, typename T, class Acc = AccPlain>
 struct VisStatic {
@@ -743,8 +751,12 @@ struct VisVelinterp {
 template <int D, typename T = float, class Acc = AccPlain, int NL = kMaxLines>
 struct VisCav {
     using AccT = Acc;
-    // the plain 3D march needs a few registers more than three waves per SIMD allow
-    static constexpr int kMinWaves = (Acc::kTrunc || Acc::kJ) ? 1 : (D == 2 && NL == 2) ? 4 : (D == 3 ? 3 : 1);
+    // the plain 3D march needs a few registers more than three waves per SIMD allow; the
+    // inference-mode truncated march (the cache path, mostly full-length fallback rays) is held
+    // to three waves in 3D with two lines as well
+    static constexpr int kMinWaves = Acc::kJ ? 1
+                                     : Acc::kTrunc ? ((D == 3 && NL == 2 && trunc_inference<Acc>()) ? 3 : 1)
+                                     : (D == 2 && NL == 2) ? 4 : (D == 3 ? 3 : 1);
     const TraceLaunch* tl;
     long long cur_blk;
     long long base;
