@@ -1,7 +1,7 @@
 """Parity at the benchmark's full sizes, in the launch configuration bench.py times.
 
-cfg2: 2D 1024^2, 64 directions, all 419,328 probes, velocity interpolation (n_v 21),
-VLM T = 1e-2 with path-graded cascade levels; the first and last wavelength batches are
+cfg2: 2D 1024^2, 64 directions, all 419,328 probes, velocity interpolation (n_v 21) with FP32
+and with BF16 node records, VLM T = 1e-2 with path-graded cascade levels; the first and last wavelength batches are
 traced exactly as the benchmark traces them and sampled rays are compared with the FP64
 oracle marching its own levels (rays through a block whose level sits in the threshold
 tie band are left out, as in the small-scene tests).
@@ -28,7 +28,10 @@ def rt():
     return rt
 
 
-def test_cfg2_full_size_vlm_parity(rt):
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_cfg2_full_size_vlm_parity(rt, storage):
+    """FP32 node records: within FP32 rounding of the oracle.  BF16 node records (unit roundoff u = 2^-8): each
+    intensity within the storage-rounding bound of the small-scene test, 4u at p99.9 and 16u overall."""
     import torch
     sc = make_cfg2()
     T = 1e-2
@@ -43,7 +46,7 @@ def test_cfg2_full_size_vlm_parity(rt):
     nb = sc["lam"].size // 8
     for b in (0, nb - 1):
         lam_idx = list(range(8 * b, 8 * b + 8))
-        scene.build(8 * b, 8 * b + 8, iod_threshold=T, avg_mode="linear", tau_thin=0.25)
+        scene.build(8 * b, 8 * b + 8, iod_threshold=T, avg_mode="linear", tau_thin=0.25, storage=storage)
         scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST, grade="path", out=out)
         got = out[torch.from_numpy(d).long().cuda(), :, torch.from_numpy(k).long().cuda()].cpu().numpy()
         lv_gpu = scene.levels()
@@ -54,7 +57,11 @@ def test_cfg2_full_size_vlm_parity(rt):
         s.set_level_dist(rt.CASCADE_LEVEL_DIST, mode="path")
         ref = orc.march(s, orc.VELINTERP, lv, probes[k], d, n_threads=16)
         st = orc.rel_err_stats(got[ok], ref[ok])
-        assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 1e-4, (b, st)
+        if storage == "f32":
+            assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 1e-4, (b, st)
+        else:
+            u = 2.0 ** -8
+            assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < 4 * u and st["p100"] < 16 * u, (b, st)
 
 
 def test_cfg3_full_size_level0_parity(rt):
