@@ -16,7 +16,13 @@ Parity status per function (pins live in tests/test_oracle_*.py):
                             thin bypass, hand-built IoD cases
   voigt_h                   pinned: scipy.special.wofz, H(0,x), H(a,0)
   march (velinterp)         pinned: zero velocity reduces to the rest-frame
-                            static march; linear-in-u profile interpolated exactly
+                            static march; second-order convergence in the node
+                            spacing; at merged levels, rays whose projected
+                            velocity falls on a node equal the box-filtered
+                            Doppler-shifted static march (uniform velocity, and
+                            cells mixing speeds, which fixes V = max |v|, the
+                            mean velocity vbar, the node frame and the orthant
+                            ranges of both grid modes)
   march (cav)               pinned: level 0 equals Classic; CaV wavelength scalings
   VLM approximation error   parity unpinned (no closed form; judged against
                             the dense march at the p99.9 bound)
@@ -34,6 +40,7 @@ _LIB = None
 STATIC, CLASSIC, VELINTERP, CAV = 0, 1, 2, 3
 GAUSS, VOIGT = 0, 1
 AVG_LOG, AVG_LINEAR = 0, 1
+VGRID = {"full": 0, "orthant": 1}
 
 _P = ctypes.c_void_p
 
@@ -46,7 +53,7 @@ class OrcScene(ctypes.Structure):
         ("grade_mode", ctypes.c_int32), ("ds0", ctypes.c_double), ("I0", ctypes.c_double),
         ("st_eta", _P), ("st_chi", _P), ("lam", _P), ("lam0", _P), ("eta_star", _P),
         ("chi_star", _P), ("damp", _P), ("inv_dld", _P), ("eta_bg", _P), ("chi_bg", _P),
-        ("vel", _P), ("level_dist", _P),
+        ("vel", _P), ("level_dist", _P), ("vgrid_mode", ctypes.c_int32),
     ]
 
 
@@ -96,7 +103,7 @@ def _c(a, dt):
 class Scene:
     """Keeps numpy inputs alive and exposes an OrcScene struct."""
 
-    def __init__(self, sc: dict, lam_idx=None, n_v: int = 21, avg_mode: int = AVG_LINEAR):
+    def __init__(self, sc: dict, lam_idx=None, n_v: int = 21, avg_mode: int = AVG_LINEAR, vgrid: str = "orthant"):
         self.sc = sc
         self.dim = sc["dim"]
         self.n = tuple(int(v) for v in sc["n"])
@@ -111,6 +118,7 @@ class Scene:
         s.I0 = float(sc.get("I0", 0.0))
         s.n_v = int(n_v)
         s.avg_mode = int(avg_mode)
+        s.vgrid_mode = VGRID[vgrid]
         self._keep = {}
         if sc["model"] == "lines":
             lam = np.asarray(sc["lam"], np.float64)

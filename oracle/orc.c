@@ -60,6 +60,7 @@ enum { ORC_STATIC = 0, ORC_CLASSIC = 1, ORC_VELINTERP = 2, ORC_CAV = 3 };
 enum { ORC_GAUSS = 0, ORC_VOIGT = 1 };
 enum { ORC_AVG_LOG = 0, ORC_AVG_LINEAR = 1 };
 enum { ORC_GRADE_ENTRY = 0, ORC_GRADE_PATH = 1 };
+enum { ORC_VGRID_FULL = 0, ORC_VGRID_ORTHANT = 1 };
 
 typedef struct orc_scene {
     int32_t dim;
@@ -90,6 +91,10 @@ typedef struct orc_scene {
     /* distance-graded level cap: level m only in blocks entered at path length
      * >= level_dist[m] (m = 1 .. n_levels-1); NULL = no grading */
     const double* level_dist;
+    /* velocity-interpolation node grid: ORC_VGRID_FULL (one grid over [-V, V]
+     * for every direction) or ORC_VGRID_ORTHANT (one grid per orthant of
+     * directions, over the projections reachable from it) */
+    int32_t vgrid_mode;
 } orc_scene;
 
 static int64_t nvox_of(const orc_scene* s) { return (int64_t)s->n[0] * s->n[1] * s->n[2]; }
@@ -667,23 +672,90 @@ static double node_log(const orc_scene* s, int64_t v, const void* ctx)
 }
 
 /*
- * Velocity interpolation (Sect. 3.1): for a level cell, V = max |v| over its
- * MIP-0 voxels, nodes u_k = -V + 2V k/(n_v - 1); node value = average over the
- * voxels of eta, chi evaluated at projected velocity u_k; the ray's projected
- * velocity u = vbar . w (vbar = mean velocity of the cell) is interpolated
- * linearly between the two bracketing nodes.
+ * Range of projected velocities u = v . w of MIP-0 voxel v over the unit
+ * directions w of one orthant (class q: bit a set <=> w_a < 0).  With
+ * b_a = v_a for a positive axis and -v_a for a negative one, u = sum_a b_a |w_a|
+ * over the non-negative part of the unit sphere.  Its largest value is the
+ * length of the positive part of b when some b_a > 0 (the direction along that
+ * part lies in the orthant), otherwise the largest b_a (on an axis); the
+ * smallest value likewise with the negative part.
+ */
+static void voxel_orthant_range(const orc_scene* s, int64_t v, int q, double* lo, double* hi)
+{
+    int64_t nv = nvox_of(s);
+    double pos = 0.0, neg = 0.0, bmax = -INFINITY, bmin = INFINITY;
+    int any_pos = 0, any_neg = 0;
+    for (int a = 0; a < s->dim; ++a) {
+        double b = s->vel[a * nv + v];
+        if ((q >> a) & 1) b = -b;
+        if (b > 0.0) {
+            pos += b * b;
+            any_pos = 1;
+        }
+        if (b < 0.0) {
+            neg += b * b;
+            any_neg = 1;
+        }
+        if (b > bmax) bmax = b;
+        if (b < bmin) bmin = b;
+    }
+    *hi = any_pos ? sqrt(pos) : bmax;
+    *lo = any_neg ? -sqrt(neg) : bmin;
+}
+
+typedef struct { int q; int want_hi; } orth_ctx;
+/* hi, or -lo, of a voxel's orthant range (so that both bounds are maxima) */
+static double field_orth(const orc_scene* s, int64_t v, const void* vctx)
+{
+    const orth_ctx* c = (const orth_ctx*)vctx;
+    double lo, hi;
+    voxel_orthant_range(s, v, c->q, &lo, &hi);
+    return c->want_hi ? hi : -lo;
+}
+
+/*
+ * Node range [lo, hi] of a level cell for the ray direction w (Sect. 3.1: the
+ * grid spans the projections of velocity reachable in the cell, from the
+ * MIP-0 voxels it contains).  Full grid: [-V, V], V = max |v|.  Orthant grid
+ * (the quadrant-by-quadrant solution of Sect. 4.1): the union of the cell's
+ * voxel ranges over the orthant holding w.
+ */
+static void cell_vrange(const orc_scene* s, const int32_t c[3], int size, const double* wd, double* lo, double* hi)
+{
+    if (s->vgrid_mode == ORC_VGRID_ORTHANT) {
+        int q = 0;
+        for (int a = 0; a < s->dim; ++a)
+            if (wd[a] < 0.0) q |= 1 << a;
+        orth_ctx ch = {q, 1}, cl = {q, 0};
+        *hi = cube_max(s, field_orth, &ch, c, size);
+        *lo = -cube_max(s, field_orth, &cl, c, size);
+    } else {
+        double V = cube_max(s, field_speed, NULL, c, size);
+        *lo = -V;
+        *hi = V;
+    }
+}
+
+/*
+ * Velocity interpolation (Sect. 3.1): a level cell carries n_v nodes u_k
+ * uniform in its range [lo, hi] (above); a node value is the average over the
+ * cell's MIP-0 voxels of eta, chi evaluated at projected velocity u_k; the
+ * ray's projected velocity u = vbar . w (vbar = mean velocity of the cell) is
+ * interpolated linearly between the two bracketing nodes.  An empty range
+ * (lo = hi, e.g. V = 0) uses its single value.
  */
 static void cell_velinterp(const orc_scene* s, const int32_t c[3], int size, const double* wd, int il,
                            double* eta, double* chi)
 {
-    double V = cube_max(s, field_speed, NULL, c, size);
+    double lo, hi;
+    cell_vrange(s, c, size, wd, &lo, &hi);
     double u = 0.0;
     for (int a = 0; a < s->dim; ++a) u += cell_lin(s, 6 + a, 0, c, size) * wd[a];
     int nvn = s->n_v;
     int k = 0;
     double wgt = 0.0;
-    if (V > 0.0) {
-        double f = (u + V) / (2.0 * V) * (nvn - 1);
+    if (hi > lo) {
+        double f = (u - lo) / (hi - lo) * (nvn - 1);
         k = (int)floor(f);
         if (k < 0) k = 0;
         if (k > nvn - 2) k = nvn - 2;
@@ -691,7 +763,7 @@ static void cell_velinterp(const orc_scene* s, const int32_t c[3], int size, con
     }
     double nodes_e[2], nodes_c[2];
     for (int j = 0; j < 2; ++j) {
-        double uk = (V > 0.0) ? (-V + 2.0 * V * (double)(k + j) / (double)(nvn - 1)) : 0.0;
+        double uk = (hi > lo) ? (lo + (hi - lo) * (double)(k + j) / (double)(nvn - 1)) : lo;
         for (int q = 0; q < 2; ++q) {
             node_ctx nc = {il, uk, q};
             double val;

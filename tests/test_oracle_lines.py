@@ -223,3 +223,93 @@ def test_cav_constant_parameters_any_level(orc):
     I_c = orc.march(s, orc.CLASSIC, None, vox, d)
     I_cav = orc.march(s, orc.CAV, np.full(4, 3, np.int8), vox, d)
     np.testing.assert_allclose(I_cav, I_c, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# velocity interpolation at merged levels (Sect. 3.1; orthant grids, Sect. 4.1)
+# ---------------------------------------------------------------------------
+AXIS_DIRS = np.array([[1.0, 0.0], [-1.0, 0.0], [0.0, 1.0], [0.0, -1.0]], np.float32)
+
+
+def _shifted_static_march(orc, sc, u, level, vox, d):
+    """The static march, every block at `level`, of the scene with v = 0 observed at
+    lam' = lam + lam0 u / c (a uniform projected velocity u is a pure wavelength shift),
+    whose level values are box filters of the MIP-0 values: what a velocity-interpolation
+    node at projected velocity u holds."""
+    sc0 = dict(sc)
+    sc0["vel"] = np.zeros_like(sc["vel"])
+    sc0["lam"] = sc["lam"] + sc["lam0"][0] * u / C_KMS
+    s0 = orc.Scene(sc0)
+    lvs, st_e, st_c = orc.static_level_values(s0, np.array([orc.lines_mip0(s0, il, 0)[0] for il in range(s0.s.n_lam)]),
+                                              np.array([orc.lines_mip0(s0, il, 0)[1] for il in range(s0.s.n_lam)]),
+                                              sc["block_active"], T=0.0)
+    s0.set_static_levels(st_e, st_c)
+    lv = np.full(sc["block_active"].size, level, np.int8)
+    return orc.march(s0, orc.STATIC, lv, vox, d)
+
+
+@pytest.mark.parametrize("vgrid,n_v", [("full", 9), ("orthant", 9)])
+def test_velinterp_uniform_velocity_node_any_level(orc, vgrid, n_v):
+    """Uniform v along x: rays along +-x project u = +-V, the end nodes of the full
+    grid and of both x-orthant grids; rays along y project u = 0, the middle node of
+    the full grid and an end node of the orthant grids.  At every level the
+    velocity-interpolation march then equals the static march of the Doppler-shifted
+    scene with box-filtered level values."""
+    V = 12.0
+    sc = tiny_lines_scene(n=(32, 32), B=8, L=4, profile="gauss", uniform_v=(V, 0.0), n_lam=6)
+    sc["dirs"] = AXIS_DIRS
+    s = orc.Scene(sc, n_v=n_v, vgrid=vgrid)
+    rng = np.random.default_rng(5)
+    vox = rng.integers(0, 1024, 48).astype(np.int32)
+    for d_idx in range(4):
+        u = float(np.dot(np.array([V, 0.0]), AXIS_DIRS[d_idx].astype(np.float64)))
+        d = np.full(vox.size, d_idx, np.int32)
+        for level in range(4):
+            lv = np.full(16, level, np.int8)
+            got = orc.march(s, orc.VELINTERP, lv, vox, d)
+            ref = _shifted_static_march(orc, sc, u, level, vox, d)
+            np.testing.assert_allclose(got, ref, rtol=1e-9, err_msg="%s dir %d level %d" % (vgrid, d_idx, level))
+
+
+@pytest.mark.parametrize("vgrid,n_v", [("full", 7), ("orthant", 5)])
+def test_velinterp_mixed_speeds_in_a_cell(orc, vgrid, n_v):
+    """Cells mixing speeds: v_x = -1 on voxels with even x and y, +3 elsewhere (v_y = 0), so
+    every merged cell has mean velocity vbar = (2, 0), V = max |v| = 3 and x-orthant ranges
+    [-1, 3] (w_x > 0) and [-3, 1] (w_x < 0).  With 7 full-grid nodes (spacing 1) or 5
+    orthant nodes (spacing 1) a ray along +-x projects u = vbar . w = +-2 onto a node, whose
+    value is the cell's box filter of eta, chi with every voxel at u.  A grid over the mean
+    speed (2.5) instead of the maximum, a different vbar, voxels taken at their own
+    velocities, or a wrong orthant range would put u between nodes or change the node."""
+    sc = tiny_lines_scene(n=(32, 32), B=8, L=4, profile="gauss", uniform_v=(3.0, 0.0), n_lam=6)
+    x = np.arange(32)
+    slow = ((x[None, :] % 2 == 0) & (x[:, None] % 2 == 0)).ravel()  # [y][x] flattened, x fastest
+    sc["vel"][0, slow] = -1.0
+    sc["dirs"] = AXIS_DIRS
+    s = orc.Scene(sc, n_v=n_v, vgrid=vgrid)
+    rng = np.random.default_rng(6)
+    vox = rng.integers(0, 1024, 48).astype(np.int32)
+    for d_idx, u in ((0, 2.0), (1, -2.0)):
+        d = np.full(vox.size, d_idx, np.int32)
+        for level in (1, 2, 3):
+            lv = np.full(16, level, np.int8)
+            got = orc.march(s, orc.VELINTERP, lv, vox, d)
+            ref = _shifted_static_march(orc, sc, u, level, vox, d)
+            np.testing.assert_allclose(got, ref, rtol=1e-9, err_msg="%s dir %d level %d" % (vgrid, d_idx, level))
+
+
+def test_velinterp_orthant_grid_is_finer(orc):
+    """The orthant grids (Sect. 4.1: each quadrant solved with its own grid) span at most the
+    full range, so at equal n_v they interpolate at least as finely: at MIP 0 their error
+    against Classic is smaller, and both converge to it."""
+    sc = tiny_lines_scene(n=(16, 16), B=8, L=1, profile="gauss", vmax=25.0, n_lam=8, dv_span=25.0)
+    rng = np.random.default_rng(7)
+    vox = rng.integers(0, 256, 80).astype(np.int32)
+    d = rng.integers(0, 8, 80).astype(np.int32)
+    ref = orc.march(orc.Scene(sc), orc.CLASSIC, None, vox, d)
+    err = {}
+    for vg in ("full", "orthant"):
+        I = orc.march(orc.Scene(sc, n_v=21, vgrid=vg), orc.VELINTERP, None, vox, d)
+        err[vg] = np.max(np.abs(I - ref) / np.abs(ref))
+    assert err["orthant"] < 0.75 * err["full"], err
+    I = orc.march(orc.Scene(sc, n_v=161, vgrid="orthant"), orc.VELINTERP, None, vox, d)
+    assert np.max(np.abs(I - ref) / np.abs(ref)) < 1e-3
