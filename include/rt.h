@@ -85,6 +85,18 @@ typedef enum rt_avg {
 
 typedef enum rt_dtype { RT_F32 = 0, RT_BF16 = 1, RT_F16 = 2 } rt_dtype;
 
+/* Node grids of velocity interpolation.  Every level cell carries n_v nodes
+ * uniform over a range of projected velocities u = v . w (Sect. 3.1: from the
+ * MIP-0 voxels the cell contains).
+ *   FULL:    one grid over [-V, V], V = max |v|, for every direction.
+ *   ORTHANT: one grid per orthant of directions (2^dim classes; class bit a
+ *            set when w_a < 0), over the projections reachable from that
+ *            orthant: the paper's deployment solves the angles quadrant by
+ *            quadrant with a grid per quadrant (Sect. 4.1), so that n_v nodes
+ *            per quadrant give up to 4 n_v effective bins.  2^dim times the
+ *            node storage; a trace reads only its directions' grids. */
+typedef enum rt_vgrid { RT_VGRID_FULL = 0, RT_VGRID_ORTHANT = 1 } rt_vgrid;
+
 typedef enum rt_trace_mode {
     RT_TRACE_LEVEL0 = 0, /* every active block at MIP 0 (SPARSE; DENSE if the scene is dense) */
     RT_TRACE_VLM = 1     /* each block at its VLM level of the current batch */
@@ -100,11 +112,13 @@ typedef enum rt_trace_mode {
  *   emission   rt_emission the scene is built for (STATIC for the static model).
  *   profile    rt_profile (lines model).
  *   n_lines    1..RT_MAX_LINES (lines model).
- *   n_v        velocity nodes per cell, >= 2 (velocity interpolation).
+ *   n_v        velocity nodes per cell and direction class, >= 2 (velocity
+ *              interpolation).
  *   dense      nonzero: every block is active (the dense comparator); 0: blocks
  *              whose inputs are all zero (or masked out) are empty.
  *   n_lam      number of wavelengths of the scene.
  *   ds0        physical side of a MIP-0 voxel (> 0).
+ *   vgrid      rt_vgrid: velocity-interpolation node grids (Sect. 3.1, 4.1).
  *   h_lam      host [n_lam] wavelengths in nm (lines model; may be NULL for static).
  *   h_lam0     host [n_lines] rest wavelengths in nm (lines model).
  */
@@ -120,7 +134,7 @@ typedef struct rt_scene_desc {
     int32_t n_v;
     int32_t dense;
     int32_t n_lam;
-    int32_t reserved_;
+    int32_t vgrid;
     double ds0;
     const double* h_lam;
     const double* h_lam0;

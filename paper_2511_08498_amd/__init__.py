@@ -46,7 +46,7 @@ class RtSceneDesc(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("brick", ctypes.c_int32),
                 ("n_levels", ctypes.c_int32), ("model", ctypes.c_int32), ("emission", ctypes.c_int32),
                 ("profile", ctypes.c_int32), ("n_lines", ctypes.c_int32), ("n_v", ctypes.c_int32),
-                ("dense", ctypes.c_int32), ("n_lam", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("dense", ctypes.c_int32), ("n_lam", ctypes.c_int32), ("vgrid", ctypes.c_int32),
                 ("ds0", ctypes.c_double), ("h_lam", _P), ("h_lam0", _P)]
 
 
@@ -188,7 +188,11 @@ def _stream(stream=None):
     return _P(s.cuda_stream)
 
 
-def _scene_desc(dim, n, brick, n_levels, model, emission, profile, n_v, dense, ds0, n_lam_static, lam, lam0):
+VGRID = {"full": 0, "orthant": 1}
+
+
+def _scene_desc(dim, n, brick, n_levels, model, emission, profile, n_v, dense, ds0, n_lam_static, lam, lam0,
+                vgrid="orthant"):
     """rt_scene_desc of a scene (plus the wavelength arrays it points to, which must stay alive)."""
     n = tuple(int(v) for v in n) + (1,) * (3 - len(n))
     d = RtSceneDesc()
@@ -201,6 +205,7 @@ def _scene_desc(dim, n, brick, n_levels, model, emission, profile, n_v, dense, d
     d.emission = EMISSION[emission]
     d.profile = PROFILE[profile]
     d.n_v = int(n_v)
+    d.vgrid = VGRID[vgrid]
     d.dense = 1 if dense else 0
     d.ds0 = float(ds0)
     if model == "static":
@@ -213,14 +218,15 @@ def _scene_desc(dim, n, brick, n_levels, model, emission, profile, n_v, dense, d
     return d, lam, lam0
 
 
-def scene_workspace_bytes(sc, n_active=None, emission=None, n_v=21, dense=False):
+def scene_workspace_bytes(sc, n_active=None, emission=None, n_v=21, dense=False, vgrid="orthant"):
     """Device bytes a scene made from the synthetic scene dict `sc` holds (host only; n_active
     defaults to the dict's active-block count, or every block when dense)."""
     model = sc["model"]
     emis = "static" if model == "static" else (emission or "static")
     d, lam, lam0 = _scene_desc(sc["dim"], sc["n"], sc["brick"], sc["n_levels"], model, emis,
                                sc.get("profile", "gauss"), n_v, dense, sc.get("ds0", 1.0),
-                               sc["eta"].shape[0] if model == "static" else None, sc.get("lam"), sc.get("lam0"))
+                               sc["eta"].shape[0] if model == "static" else None, sc.get("lam"), sc.get("lam0"),
+                               vgrid)
     if n_active is None:
         n_active = sc["block_active"].size if dense else int(sc["block_active"].sum())
     v = ctypes.c_size_t(0)
@@ -235,19 +241,29 @@ class VelocityGridWarning(UserWarning):
     """Velocity-interpolation node spacing coarser than the configured number of thermal widths."""
 
 
-def velocity_grid_ratio(vel, inv_dld, lam0, n_v):
-    """Per line, the largest ratio over voxels of the velocity-node spacing 2 |v| / (n_v - 1) to the line's
-    thermal (Doppler) width c / (lam0 inv_dld) (host arithmetic on the inputs, no device work)."""
+def velocity_grid_ratio(vel, inv_dld, lam0, n_v, vgrid="orthant"):
+    """Per line, the largest ratio over voxels of the velocity-node spacing to the line's thermal (Doppler)
+    width c / (lam0 inv_dld) (host arithmetic on the inputs, no device work).  The spacing of a voxel's grid is
+    2 |v| / (n_v - 1) for the full grid, and the widest of its orthant ranges / (n_v - 1) for orthant grids."""
     def host(a):
         return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
-    v = host(vel).astype(np.float32)
-    speed = np.sqrt((v * v).sum(axis=0))
-    spacing = 2.0 * speed / max(int(n_v) - 1, 1)
+    v = host(vel).astype(np.float64)
+    if vgrid == "full":
+        width = 2.0 * np.sqrt((v * v).sum(axis=0))
+    else:
+        width = np.zeros(v.shape[1:])
+        for q in range(1 << v.shape[0]):
+            b = np.stack([-v[a] if (q >> a) & 1 else v[a] for a in range(v.shape[0])])
+            pos, neg = np.clip(b, 0, None), np.clip(b, None, 0)
+            hi = np.where((b > 0).any(axis=0), np.sqrt((pos * pos).sum(axis=0)), b.max(axis=0))
+            lo = np.where((b < 0).any(axis=0), -np.sqrt((neg * neg).sum(axis=0)), b.min(axis=0))
+            width = np.maximum(width, hi - lo)
+    spacing = width / max(int(n_v) - 1, 1)
     idl = host(inv_dld).astype(np.float32)
     out = []
     for k, l0 in enumerate(np.asarray(lam0, np.float64).reshape(-1)):
         vd = np.where(idl[k] > 0, C_KMS / (l0 * np.where(idl[k] > 0, idl[k], 1.0)), np.inf)
-        out.append(float(np.max(spacing / vd)) if speed.size else 0.0)
+        out.append(float(np.max(spacing / vd)) if spacing.size else 0.0)
     return np.array(out)
 
 
@@ -260,7 +276,7 @@ class Scene:
     """
 
     def __init__(self, *, dim, n, brick, n_levels, model="static", emission="static", profile="gauss",
-                 n_v=21, dense=False, ds0=1.0, lam=None, lam0=None, n_lam=None, eta=None, chi=None,
+                 n_v=21, vgrid="orthant", dense=False, ds0=1.0, lam=None, lam0=None, n_lam=None, eta=None, chi=None,
                  eta_star=None, chi_star=None, damp=None, inv_dld=None, eta_bg=None, chi_bg=None, vel=None,
                  block_mask=None, device="cuda", stream=None):
         import torch
@@ -281,7 +297,7 @@ class Scene:
             return t
 
         d, self.lam, self.lam0 = _scene_desc(self.dim, self.n, self.brick, n_levels, model, emission, profile, n_v,
-                                             dense, ds0, None if eta is None else eta.shape[0], lam, lam0)
+                                             dense, ds0, None if eta is None else eta.shape[0], lam, lam0, vgrid)
         inp = RtSceneInputs()
         if model == "static":
             te, tc = dev(eta), dev(chi)
@@ -301,7 +317,7 @@ class Scene:
         self.desc = d
         self.velocity_grid_ratio = None
         if model != "static" and emission == "velinterp":
-            self.velocity_grid_ratio = velocity_grid_ratio(vel, inv_dld, lam0, n_v)
+            self.velocity_grid_ratio = velocity_grid_ratio(vel, inv_dld, lam0, n_v, vgrid)
         h = _P()
         _check(lib().rt_scene_create(ctypes.byref(d), ctypes.byref(inp), _stream(stream), ctypes.byref(h)))
         self.h = h

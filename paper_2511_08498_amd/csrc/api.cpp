@@ -104,6 +104,7 @@ static rt_status check_desc(const rt_scene_desc* d, const rt_scene_inputs* inp)
         if (d->profile != RT_PROFILE_GAUSS && d->profile != RT_PROFILE_VOIGT) return fail(RT_E_ARG, "bad profile");
         if (d->emission < RT_EMIS_STATIC || d->emission > RT_EMIS_CAV) return fail(RT_E_ARG, "bad emission");
         if (d->emission == RT_EMIS_VELINTERP && d->n_v < 2) return fail(RT_E_ARG, "n_v must be >= 2");
+        if (d->vgrid != RT_VGRID_FULL && d->vgrid != RT_VGRID_ORTHANT) return fail(RT_E_ARG, "bad vgrid %d", d->vgrid);
         if (!d->h_lam || !d->h_lam0) return fail(RT_E_ARG, "lines model needs h_lam and h_lam0");
         if (inp && (!inp->d_eta_star || !inp->d_chi_star || !inp->d_damp || !inp->d_inv_dld || !inp->d_eta_bg ||
                     !inp->d_chi_bg || !inp->d_vel))
@@ -145,6 +146,9 @@ static void make_geo(const rt_scene_desc* d, Geo& g)
     g.feat_level = std::min(2, d->n_levels - 1);
 }
 
+// Direction classes of the velocity-interpolation grids.
+static int vclasses(const rt_scene_desc* d) { return d->vgrid == RT_VGRID_ORTHANT ? 1 << d->dim : 1; }
+
 // Bytes of one allocation as rt_scene::alloc makes it.
 static size_t alloc_bytes(size_t count, size_t elem) { return std::max<size_t>(count * elem, 256); }
 
@@ -157,8 +161,11 @@ static size_t scene_bytes(const rt_scene_desc* d, const Geo& g, long long na)
                alloc_bytes(1, 8);  // the last: the input-validation counter
     b += alloc_bytes(((size_t)na << (d->dim * (g.log2B - g.feat_level))) * kLam, 16);
     if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) b += alloc_bytes(cells * kLam * 2, 4);
-    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP)
-        b += alloc_bytes(cells, 16) + alloc_bytes(cells, 4) + alloc_bytes(cells * (size_t)d->n_v * kLam * 2, 4);
+    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP) {
+        const size_t nq = (size_t)vclasses(d);
+        b += alloc_bytes(nq * cells, 16) + alloc_bytes(nq * cells, 8) +
+             alloc_bytes(nq * cells * (size_t)d->n_v * kLam * 2, 4);
+    }
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
         const size_t rec = (size_t)cav_rec_floats(d->n_lines);
         b += alloc_bytes(cells * rec, 4) + alloc_bytes(cells * rec, 2);
@@ -279,12 +286,14 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
         if ((st = sc->alloc((float**)&B.vals, cells * kLam * 2)) != RT_OK) return cleanup(st);
     }
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP) {
+        // per class, node offsets inside the trace kernels are 32-bit
         if (cells * (size_t)d->n_v * kLam * 2 >= (size_t)1 << 31)
-            return cleanup(fail(RT_E_UNSUPPORTED, "velocity-node storage exceeds 2^31 floats"));
-        if ((st = sc->alloc(&B.vgrid, cells)) != RT_OK) return cleanup(st);
-        if ((st = sc->alloc(&B.vmax, cells)) != RT_OK) return cleanup(st);
-        if ((st = sc->alloc(&B.vnodes, cells * (size_t)d->n_v * kLam * 2)) != RT_OK) return cleanup(st);
-        if ((e = launch_vgrid(g, in, B, na, d->n_v, s)) != hipSuccess)
+            return cleanup(fail(RT_E_UNSUPPORTED, "velocity-node storage of one direction class exceeds 2^31 floats"));
+        const size_t nq = (size_t)vclasses(d);
+        if ((st = sc->alloc(&B.vgrid, nq * cells)) != RT_OK) return cleanup(st);
+        if ((st = sc->alloc(&B.vrange, nq * cells)) != RT_OK) return cleanup(st);
+        if ((st = sc->alloc(&B.vnodes, nq * cells * (size_t)d->n_v * kLam * 2)) != RT_OK) return cleanup(st);
+        if ((e = launch_vgrid(g, in, B, na, d->n_v, (int)nq, s)) != hipSuccess)
             return cleanup(fail(RT_E_HIP, "velocity grid: %s", hipGetErrorString(e)));
     }
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
@@ -346,7 +355,8 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     RT_HIP(launch_build_static(g, sc->in, sc->b, sc->n_active, d.model, vrule, lb, lam_begin, d.ds0, p->iod_threshold,
                                p->tau_thin, cap, p->avg_mode, p->storage, static_emis ? 1 : 0, s));
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_VELINTERP)
-        RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, d.ds0, p->avg_mode, p->storage, s));
+        RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, vclasses(&d), d.ds0, p->avg_mode,
+                                      p->storage, s));
     RT_HIP(launch_pack_states(g, sc->b.levels, sc->b.states, s));
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_CAV && p->avg_mode != sc->cav_mode) {
         // the wavelength-independent chain follows the stored-value mode of the build
@@ -396,6 +406,8 @@ TraceLaunch rt::make_trace(const rt_scene* sc, const rt_trace_params* p)
     t.emission = sc->desc.model == RT_MODEL_STATIC ? RT_EMIS_STATIC : sc->desc.emission;
     t.storage = sc->storage;
     t.n_v = sc->desc.n_v;
+    t.n_vclass = vclasses(&sc->desc);
+    t.n_active = sc->n_active;
     t.cav_rec = sc->cav_rec;
     t.lb = make_batch(sc, sc->batch_begin, sc->batch_end);
     t.stats = p->d_stats;

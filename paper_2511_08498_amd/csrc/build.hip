@@ -171,43 +171,57 @@ struct Lvl0 {
 // the line model with each line at projected velocity u = 0 (vrule 0: the rest
 // frame used by velocity interpolation, Sect. 3.1) or at the shift within
 // [-|v|, |v|] closest to the line core, u* = clamp(c (1 - lam/lam0)) (vrule 1:
-// Core and Voigt, Sect. 3.2).
+// Core and Voigt, Sect. 3.2).  Evaluated in FP64 in the order of the defining
+// expressions, x = (lam - lam0 (1 - u/c)) / dlD and eta = bg + sum (s eta*) phi
+// (s = lam0/lam for Voigt lines, 1 for Gaussian ones), because these values
+// decide the levels: a Gaussian line is exp(-x^2) in FP64, so a level test
+// moves only where an index of dispersion lies within rounding of the
+// threshold; a Voigt line takes the single-precision profile of the march
+// (relative error below 1e-4), promoted.
 __device__ inline void mip0_value(const Inputs& in, int model, int vrule, int dim, const LamBatch& lb,
-                                  int lam_global, int l, long long v, float& e, float& c)
+                                  int lam_global, int l, long long v, double& e, double& c)
 {
     if (model == RT_MODEL_STATIC) {
         e = in.eta[(long long)lam_global * in.nvox + v];
         c = in.chi[(long long)lam_global * in.nvox + v];
-    } else {
-        float ee = in.eta_bg[v], cc = in.chi_bg[v];
-        float sp = 0.f;
-        if (vrule == 1) {
-            float q = 0.f;
-            for (int a = 0; a < dim; ++a) {
-                float va = in.vel[(long long)a * in.nvox + v];
-                q = fmaf(va, va, q);
-            }
-            sp = sqrtf(q);
-        }
-        for (int k = 0; k < lb.n_lines; ++k) {
-            long long o = (long long)k * in.nvox + v;
-            float idl = in.inv_dld[o];
-            double dl = lb.lam[l] - lb.lam0[k];
-            float x;
-            if (vrule == 1) {
-                double us = kCkms * (1.0 - lb.lam[l] / lb.lam0[k]);
-                us = us > sp ? sp : (us < -sp ? -sp : us);
-                x = (float)(dl + lb.lam0[k] * us / kCkms) * idl;
-            } else {
-                x = (float)dl * idl;
-            }
-            float phi = line_shape(lb.profile, x, in.damp[o], lb.lam[l], lb.lam0[k], idl);
-            ee += in.eta_star[o] * phi;
-            cc += in.chi_star[o] * phi;
-        }
-        e = ee;
-        c = cc;
+        return;
     }
+    double ee = in.eta_bg[v], cc = in.chi_bg[v];
+    double sp = 0.0;
+    if (vrule == 1) {
+        double q = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            const double va = in.vel[(long long)a * in.nvox + v];
+            q += va * va;
+        }
+        sp = sqrt(q);
+    }
+    const double lam = lb.lam[l];
+    for (int k = 0; k < lb.n_lines; ++k) {
+        const long long o = (long long)k * in.nvox + v;
+        const double lam0 = lb.lam0[k];
+        const double idl = in.inv_dld[o];
+        double u = 0.0;
+        if (vrule == 1) {
+            u = kCkms * (1.0 - lam / lam0);
+            if (u > sp) u = sp;
+            if (u < -sp) u = -sp;
+        }
+        const double x = (lam - lam0 * (1.0 - u / kCkms)) * idl;
+        double phi, sc;
+        if (lb.profile == RT_PROFILE_GAUSS) {
+            phi = exp(-x * x);
+            sc = 1.0;
+        } else {
+            const double r = lam / lam0;
+            phi = (double)voigt_h((float)(in.damp[o] * r * r), (float)x) * idl / 1.7724538509055160273;
+            sc = lam0 / lam;
+        }
+        ee += sc * (double)in.eta_star[o] * phi;
+        cc += sc * (double)in.chi_star[o] * phi;
+    }
+    e = ee;
+    c = cc;
 }
 
 template <int D, typename T>
@@ -232,19 +246,19 @@ __global__ void k_build_static(Geo g, Inputs in, SceneBufs bufs, int model, int 
     int lv_batch = 127;
     // LDS: level m occupies cells_m * 4 doubles starting at lvl_off[m] * 4.
     for (int l = 0; l < lb.nl; ++l) {
-        float e, c;
+        double e, c;
         mip0_value(in, model, vrule, D, lb, lam_begin + l, l, v, e, c);
         if (write_values) {
             T* r = vals + ((rec0 + tid) * kLam + l) * 2;
-            r[0] = Codec<T>::enc(e);
-            r[1] = Codec<T>::enc(c);
+            r[0] = Codec<T>::enc((float)e);
+            r[1] = Codec<T>::enc((float)c);
         }
-        double qe = (double)e * ds0, qc = (double)c * ds0;
+        double qe = e * ds0, qc = c * ds0;
         double* s0 = lds + 4 * tid;
         s0[0] = log(qe > 1e-300 ? qe : 1e-300);
         s0[1] = log(qc > 1e-300 ? qc : 1e-300);
-        s0[2] = (double)e;
-        s0[3] = (double)c;
+        s0[2] = e;
+        s0[3] = c;
         if (bufs.fstats && g.feat_level == 0)
             bufs.fstats[((long long)slot * g.bvox + tid) * kLam + l] =
                 make_float4((float)s0[1], 0.f, (float)s0[0], 0.f);

@@ -1,15 +1,18 @@
 // Level chains of the moving-medium line model.
 //
-//  * Velocity interpolation (Sect. 3.1): every cell of every level gets a
-//    velocity grid of n_v nodes uniform in [-V, V], V = max |v| over its MIP-0
-//    voxels, plus the mean velocity vbar used to project the ray direction.
-//    The node value of a level-m cell is the average (log or linear mode) over
-//    its MIP-0 voxels of eta, chi evaluated as if each voxel's projected
-//    velocity were the node velocity.
+//  * Velocity interpolation (Sect. 3.1): every cell of every level gets, per
+//    direction class (one full grid, or one per orthant of directions as in
+//    the quadrant-by-quadrant solution of Sect. 4.1), a velocity grid of n_v
+//    nodes uniform over the projected velocities its MIP-0 voxels reach from
+//    that class ([-V, V], V = max |v|, for the full grid), plus the mean
+//    velocity vbar used to project the ray direction.  The node value of a
+//    level-m cell is the average (log or linear mode) over its MIP-0 voxels of
+//    eta, chi evaluated as if each voxel's projected velocity were the node
+//    velocity.
 //  * Core and Voigt (Sect. 3.2): eta*, chi* and the background averaged in
 //    the stored-value mode, damping, 1/Doppler width and velocity linearly.
 //
-// The V / vbar and Core-and-Voigt chains average children level by level in
+// The vbar and Core-and-Voigt chains average children level by level in
 // the fixed pairwise order of the level statistics (x pairs, then y, then z).
 // Velocity-node values are FP32 sums over the cell's voxels (values only).
 #include "common.h"
@@ -44,69 +47,118 @@ __device__ __forceinline__ F tsum(const F* q)
     return ((q[0] + q[1]) + (q[2] + q[3])) + ((q[4] + q[5]) + (q[6] + q[7]));
 }
 
-// ------------------------------------------------------ velocity grid (V, vbar)
-__device__ __forceinline__ float4 vgrid_rec(double V, const double* vb, int n_v)
+// ------------------------------------------------------ velocity grids
+// Projected-velocity range of one voxel over the directions of class q.  Full
+// grid (n_vclass = 1): [-|v|, |v|].  Orthant q (bit a set <=> w_a < 0): with
+// b_a = +-v_a signed by the orthant, u = sum_a b_a |w_a| over non-negative unit
+// vectors, whose maximum is the length of the positive part of b (or, with no
+// positive component, the largest b_a, on an axis) and whose minimum is minus
+// the length of the negative part (or the smallest b_a).
+template <int D>
+__device__ __forceinline__ void voxel_vrange(const double* v, int q, int n_vclass, double& lo, double& hi)
 {
-    float s = V > 0.0 ? (float)(0.5 * (double)(n_v - 1) / V) : 0.f;
-    return make_float4(s, (float)vb[0], (float)vb[1], (float)vb[2]);
+    if (n_vclass == 1) {
+        double s2 = 0.0;
+        for (int a = 0; a < D; ++a) s2 += v[a] * v[a];
+        hi = sqrt(s2);
+        lo = -hi;
+        return;
+    }
+    double pos = 0.0, neg = 0.0, bmax = -1e300, bmin = 1e300;
+    bool any_pos = false, any_neg = false;
+    for (int a = 0; a < D; ++a) {
+        const double b = ((q >> a) & 1) ? -v[a] : v[a];
+        if (b > 0.0) {
+            pos += b * b;
+            any_pos = true;
+        }
+        if (b < 0.0) {
+            neg += b * b;
+            any_neg = true;
+        }
+        bmax = fmax(bmax, b);
+        bmin = fmin(bmin, b);
+    }
+    hi = any_pos ? sqrt(pos) : bmax;
+    lo = any_neg ? -sqrt(neg) : bmin;
 }
 
+// Trace record of a cell for one class: node coordinate f = g . w + off.
 template <int D>
-__global__ void k_vgrid(Geo g, Inputs in, SceneBufs bufs, int n_v)
+__device__ __forceinline__ float4 vgrid_rec(const double* vb, double lo, double hi, int n_v)
 {
-    extern __shared__ double lds[];  // per cell: V, vx, vy, vz
+    if (!(hi > lo)) return make_float4(0.f, 0.f, 0.f, 0.f);
+    const double s = (double)(n_v - 1) / (hi - lo);
+    return make_float4((float)(vb[0] * s), (float)(vb[1] * s), D > 2 ? (float)(vb[2] * s) : 0.f, (float)(-lo * s));
+}
+
+// One workgroup per active brick, one thread per MIP-0 voxel; the classes are
+// taken one after the other.  LDS per cell: vbar[D] (FP64 means of the
+// children in the pairwise order), then the class's (lo, hi) (min / max over
+// the children).
+template <int D>
+__global__ void k_vgrid(Geo g, Inputs in, SceneBufs bufs, int n_v, int n_vclass)
+{
+    extern __shared__ double lds[];
+    constexpr int stride = D + 2;
     const int slot = blockIdx.x, tid = threadIdx.x;
     const int blk = bufs.active_list[slot];
+    const long long ncell_all = (long long)gridDim.x * g.cells;  // = n_active cells: one class's record count
+    const long long rec = (long long)slot * g.cells;
     long long v;
     voxel_of(g, blk, tid, D, v);
-    double vv[3] = {0, 0, 0}, q = 0.0;
-    for (int a = 0; a < D; ++a) {
-        vv[a] = in.vel[(long long)a * in.nvox + v];
-        q += vv[a] * vv[a];
-    }
-    double* s0 = lds + 4 * tid;
-    s0[0] = sqrt(q);
-    s0[1] = vv[0];
-    s0[2] = vv[1];
-    s0[3] = vv[2];
-    const long long rec = (long long)slot * g.cells;
-    bufs.vgrid[rec + tid] = vgrid_rec(s0[0], vv, n_v);
-    bufs.vmax[rec + tid] = (float)s0[0];
-    __syncthreads();
-    for (int m = 1; m < g.n_levels; ++m) {
-        const int side = g.B >> m;
-        const int ncell = D == 2 ? side * side : side * side * side;
-        if (tid < ncell) {
-            int idx[8];
-            children<D>(tid, side, idx);
-            const double* sc = lds + 4 * g.lvl_off[m - 1];
-            double* so = lds + 4 * (g.lvl_off[m] + tid);
-            double qq[8];
-            double V = 0.0;
-            for (int j = 0; j < (1 << D); ++j) V = fmax(V, sc[4 * idx[j]]);
-            so[0] = V;
-            for (int f = 1; f < 4; ++f) {
-                for (int j = 0; j < (1 << D); ++j) qq[j] = sc[4 * idx[j] + f];
-                so[f] = tsum<D>(qq) / (1 << D);
-            }
-            bufs.vgrid[rec + g.lvl_off[m] + tid] = vgrid_rec(so[0], so + 1, n_v);
-            bufs.vmax[rec + g.lvl_off[m] + tid] = (float)so[0];
-        }
+    for (int q = 0; q < n_vclass; ++q) {
+        double* s0 = lds + (size_t)stride * tid;
+        for (int a = 0; a < D; ++a) s0[a] = in.vel[(long long)a * in.nvox + v];
+        double lo, hi;
+        voxel_vrange<D>(s0, q, n_vclass, lo, hi);
+        s0[D] = lo;
+        s0[D + 1] = hi;
+        bufs.vgrid[q * ncell_all + rec + tid] = vgrid_rec<D>(s0, lo, hi, n_v);
+        bufs.vrange[q * ncell_all + rec + tid] = make_float2((float)lo, (float)hi);
         __syncthreads();
+        for (int m = 1; m < g.n_levels; ++m) {
+            const int side = g.B >> m;
+            const int ncell = D == 2 ? side * side : side * side * side;
+            if (tid < ncell) {
+                int idx[8];
+                children<D>(tid, side, idx);
+                const double* sc = lds + (size_t)stride * g.lvl_off[m - 1];
+                double* so = lds + (size_t)stride * (g.lvl_off[m] + tid);
+                double qq[8];
+                for (int a = 0; a < D; ++a) {
+                    for (int j = 0; j < (1 << D); ++j) qq[j] = sc[stride * idx[j] + a];
+                    so[a] = tsum<D>(qq) / (1 << D);
+                }
+                double clo = 1e300, chi = -1e300;
+                for (int j = 0; j < (1 << D); ++j) {
+                    clo = fmin(clo, sc[stride * idx[j] + D]);
+                    chi = fmax(chi, sc[stride * idx[j] + D + 1]);
+                }
+                so[D] = clo;
+                so[D + 1] = chi;
+                const long long o = q * ncell_all + rec + g.lvl_off[m] + tid;
+                bufs.vgrid[o] = vgrid_rec<D>(so, clo, chi, n_v);
+                bufs.vrange[o] = make_float2((float)clo, (float)chi);
+            }
+            __syncthreads();
+        }
     }
 }
 
-hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, hipStream_t s)
+hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, int n_vclass,
+                        hipStream_t s)
 {
     if (n_active == 0) return hipSuccess;
-    size_t shm = sizeof(double) * 4 * (size_t)g.cells;
-    if (g.dim == 2) hipLaunchKernelGGL(k_vgrid<2>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b, n_v);
-    else hipLaunchKernelGGL(k_vgrid<3>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b, n_v);
+    size_t shm = sizeof(double) * (size_t)(g.dim + 2) * (size_t)g.cells;
+    if (g.dim == 2) hipLaunchKernelGGL(k_vgrid<2>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b, n_v, n_vclass);
+    else hipLaunchKernelGGL(k_vgrid<3>, dim3(n_active), dim3(g.bvox), shm, s, g, in, b, n_v, n_vclass);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------ velocity node values
-// One workgroup per active brick; one thread per (level cell, node) item.  The
+// One workgroup per (active brick, direction class); one thread per (level
+// cell, node) item.  The
 // thread walks the cell's MIP-0 voxels once, reads each voxel's line
 // parameters once, evaluates eta, chi at the node velocity for all 8 batch
 // wavelengths and accumulates them (ln values in log mode) in registers, then
@@ -123,7 +175,8 @@ template <int D, typename T>
 __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, SceneBufs bufs, LamBatch lb, int n_v,
                                                           float ds0, int avg_mode)
 {
-    const int slot = blockIdx.x;
+    const int slot = blockIdx.x, q_cls = blockIdx.y;
+    const long long ncell_all = (long long)gridDim.x * g.cells;
     const int blk = bufs.active_list[slot];
     const int B = g.B;
     const int bc0 = blk % g.nb[0], bc1 = (blk / g.nb[0]) % g.nb[1], bc2 = blk / (g.nb[0] * g.nb[1]);
@@ -146,9 +199,9 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
         const int cell = rem / n_v, kn = rem - cell * n_v;
         const int side = B >> m, size = 1 << m;
         const int cx = cell % side, cy = (cell / side) % side, cz = D > 2 ? cell / (side * side) : 0;
-        const long long rec = (long long)slot * g.cells + g.lvl_off[m] + cell;
-        const float Vc = bufs.vmax[rec];
-        const float uk = Vc > 0.f ? -Vc + 2.0f * Vc * (float)kn / (float)(n_v - 1) : 0.f;
+        const long long rec = q_cls * ncell_all + (long long)slot * g.cells + g.lvl_off[m] + cell;
+        const float2 vr = bufs.vrange[rec];
+        const float uk = vr.y > vr.x ? vr.x + (vr.y - vr.x) * (float)kn / (float)(n_v - 1) : vr.x;
         float ae[kLam], ac[kLam];
 #pragma unroll
         for (int l = 0; l < kLam; ++l) ae[l] = ac[l] = 0.f;
@@ -215,25 +268,25 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
 
 template <int D>
 static void launch_nodes_dim(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, const LamBatch& lb,
-                             int n_v, float ds0, int avg_mode, int storage, hipStream_t s)
+                             int n_v, int n_vclass, float ds0, int avg_mode, int storage, hipStream_t s)
 {
+    const dim3 grid(n_active, n_vclass);
     if (storage == RT_F32)
-        hipLaunchKernelGGL((k_velinterp_nodes2<D, float>), dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, ds0,
-                           avg_mode);
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, float>), grid, dim3(256), 0, s, g, in, b, lb, n_v, ds0, avg_mode);
     else if (storage == RT_BF16)
-        hipLaunchKernelGGL((k_velinterp_nodes2<D, __hip_bfloat16>), dim3(n_active), dim3(256), 0, s, g, in, b, lb,
-                           n_v, ds0, avg_mode);
-    else
-        hipLaunchKernelGGL((k_velinterp_nodes2<D, __half>), dim3(n_active), dim3(256), 0, s, g, in, b, lb, n_v, ds0,
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, __hip_bfloat16>), grid, dim3(256), 0, s, g, in, b, lb, n_v, ds0,
                            avg_mode);
+    else
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, __half>), grid, dim3(256), 0, s, g, in, b, lb, n_v, ds0, avg_mode);
 }
 
 hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
-                                  const LamBatch& lb, int n_v, double ds0, int avg_mode, int storage, hipStream_t s)
+                                  const LamBatch& lb, int n_v, int n_vclass, double ds0, int avg_mode, int storage,
+                                  hipStream_t s)
 {
     if (n_active == 0) return hipSuccess;
-    if (g.dim == 2) launch_nodes_dim<2>(g, in, b, n_active, lb, n_v, (float)ds0, avg_mode, storage, s);
-    else launch_nodes_dim<3>(g, in, b, n_active, lb, n_v, (float)ds0, avg_mode, storage, s);
+    if (g.dim == 2) launch_nodes_dim<2>(g, in, b, n_active, lb, n_v, n_vclass, (float)ds0, avg_mode, storage, s);
+    else launch_nodes_dim<3>(g, in, b, n_active, lb, n_v, n_vclass, (float)ds0, avg_mode, storage, s);
     return hipGetLastError();
 }
 

@@ -60,9 +60,11 @@ struct SceneBufs {
     int8_t* levels;         // [nblocks] current batch
     uint64_t* states;       // [n_state_words]
     void* vals;             // [n_active][cells][kLam][2] static emission values (storage dtype)
-    float4* vgrid;          // [n_active][cells] velocity grid: (n_v-1)/(2V) (0 if V = 0), vbar
-    float* vmax;            // [n_active][cells] V = max |v| over the cell's MIP-0 voxels
-    float* vnodes;          // [n_active][cells][n_v][kLam][2] node values (velocity interpolation)
+    // velocity interpolation, per direction class q (1 class for the full grid, 2^dim orthants):
+    float4* vgrid;          // [n_vclass][n_active][cells] (gx, gy, gz, off): node coordinate of direction w
+                            // f = g . w + off = (vbar . w - lo) (n_v - 1) / (hi - lo); g = 0, off = 0 if hi = lo
+    float2* vrange;         // [n_vclass][n_active][cells] (lo, hi) node range of projected velocities
+    float* vnodes;          // [n_vclass][n_active][cells][n_v][kLam][2] node values
     float* cav;             // [n_active][cells][cav_rec] line parameters (Core and Voigt)
     void* cav_lp;           // the same in BF16 or FP16 (reduced-precision storage), 2 bytes per value
     float4* fstats;         // [n_active][cells at feat_level][kLam]: mean, var of ln(chi ds0), mean, var of ln(eta ds0)
@@ -124,9 +126,11 @@ hipError_t launch_build_static(const Geo& g, const Inputs& in, const SceneBufs& 
                                int vrule, const LamBatch& lb, int lam_begin, double ds0, double T, double tau_thin,
                                int cap, int avg_mode, int storage, int write_values, hipStream_t s);
 hipError_t launch_pack_states(const Geo& g, const int8_t* levels, uint64_t* states, hipStream_t s);
-hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, hipStream_t s);
+hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, int n_vclass,
+                        hipStream_t s);
 hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
-                                  const LamBatch& lb, int n_v, double ds0, int avg_mode, int storage, hipStream_t s);
+                                  const LamBatch& lb, int n_v, int n_vclass, double ds0, int avg_mode, int storage,
+                                  hipStream_t s);
 hipError_t launch_cav_chain(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_lines,
                             double ds0, int avg_mode, hipStream_t s);
 hipError_t launch_read_cells(const Geo& g, const SceneBufs& b, int storage, int n, const int32_t* cells,
@@ -142,6 +146,8 @@ struct TraceLaunch {
     const void* vals;
     const float4* vgrid;
     const float* vnodes;
+    int n_vclass;              // velocity-grid direction classes: 1 (full grid) or 2^dim (orthants)
+    int n_active;              // active blocks (records per class = n_active * cells)
     const float* cav;
     const void* cav_lp;  // BF16/FP16 copy of cav, used when storage != RT_F32
     const float* dirs;

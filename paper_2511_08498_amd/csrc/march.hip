@@ -693,11 +693,15 @@ struct VisStatic {
 };
 
 // T: storage of the node records (FP32, or BF16 / FP16 at half the record size).
+// The direction class (full grid, or the orthant of w) is fixed per ray, so the
+// class's grid records and node values are selected once at initialisation.
 template <int D, typename T = float, class Acc = AccPlain>
 struct VisVelinterp {
     using AccT = Acc;
     static constexpr int kMinWaves = (D == 2 && !Acc::kTrunc && !Acc::kJ) ? 4 : 1;
     const TraceLaunch* tl;
+    const float4* vgrid;
+    const T* vnodes;
     long long cur_blk;
     long long base;
     float dsf;
@@ -712,6 +716,11 @@ struct VisVelinterp {
         w[0] = wf[0];
         w[1] = wf[1];
         w[2] = D > 2 ? wf[2] : 0.f;
+        int q = 0;
+        if (t->n_vclass > 1) q = (w[0] < 0.f ? 1 : 0) | (w[1] < 0.f ? 2 : 0) | (D > 2 && w[2] < 0.f ? 4 : 0);
+        const long long ncell_all = (long long)t->n_active * t->g.cells;
+        vgrid = t->vgrid + q * ncell_all;
+        vnodes = (const T*)t->vnodes + q * ncell_all * t->n_v * (kLam * 2);
         acc.init(t);
     }
     __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
@@ -721,18 +730,17 @@ struct VisVelinterp {
             base = block_slot(tl->g, tl->slot, tl->slot_lds, blk) * tl->g.cells;
         }
         const unsigned cell = (unsigned)(base + level_offset(tl->g, lvl) + local_index(tl->g, c, lvl, D));
-        // vgrid = (s, vbar): node coordinate f = (u + V)/(2V) (n_v - 1) = u s + (n_v - 1)/2,
-        // s = (n_v - 1)/(2V) (0 when V = 0: all nodes are equal, the middle one is used)
-        float4 vg = tl->vgrid[cell];
-        float u = fmaf(vg.z, w[1], vg.y * w[0]);
-        if (D > 2) u = fmaf(vg.w, w[2], u);
+        // node coordinate f = g . w + off = (vbar . w - lo) (n_v - 1) / (hi - lo) over the cell's range
+        // [lo, hi] of projected velocities (g = off = 0 for an empty range: node 0 is used)
+        float4 vg = vgrid[cell];
+        float f = fmaf(vg.x, w[0], fmaf(vg.y, w[1], vg.w));
+        if (D > 2) f = fmaf(vg.z, w[2], f);
         const int nv = tl->n_v;
-        float f = fmaf(u, vg.x, 0.5f * (float)(nv - 1));
         int kn = (int)floorf(f);
         kn = kn < 0 ? 0 : (kn > nv - 2 ? nv - 2 : kn);
         float wt = f - (float)kn;
         // the two node records around u are adjacent (128 B in FP32, 64 B in BF16 / FP16)
-        const T* r0 = (const T*)tl->vnodes + (cell * (unsigned)nv + (unsigned)kn) * (unsigned)(kLam * 2);
+        const T* r0 = vnodes + (cell * (unsigned)nv + (unsigned)kn) * (unsigned)(kLam * 2);
         float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
         load_rec<T>(r0, e0, x0);
         load_rec<T>(r0 + kLam * 2, e1, x1);

@@ -3,8 +3,8 @@
 cfg2: 2D 1024^2, 64 directions, all 419,328 probes, velocity interpolation (n_v 21) with FP32
 and with BF16 node records, VLM T = 1e-2 with path-graded cascade levels; the first and last wavelength batches are
 traced exactly as the benchmark traces them and sampled rays are compared with the FP64
-oracle marching its own levels (rays through a block whose level sits in the threshold
-tie band are left out, as in the small-scene tests).
+oracle marching the device's level map, after checking that map against the oracle's levels
+(exact outside the threshold tie band, as in the small-scene tests).
 cfg3: 3D 256^3, 32 directions, all 4.2 M probes, Core and Voigt; the sparse MIP-0 march
 (Classic per voxel) on sampled rays against the oracle.
 """
@@ -13,7 +13,7 @@ import pytest
 
 import oracle as orc
 from synth import make_cfg2, make_cfg3
-from test_gpu_lines import oracle_levels, rays_avoiding
+from test_gpu_lines import check_levels
 
 pytestmark = pytest.mark.gpu
 
@@ -49,14 +49,11 @@ def test_cfg2_full_size_vlm_parity(rt, storage):
         scene.build(8 * b, 8 * b + 8, iod_threshold=T, avg_mode="linear", tau_thin=0.25, storage=storage)
         scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST, grade="path", out=out)
         got = out[torch.from_numpy(d).long().cuda(), :, torch.from_numpy(k).long().cuda()].cpu().numpy()
-        lv_gpu = scene.levels()
-        lv = oracle_levels(sc, lam_idx, 0, T)
-        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], probes[k], d)
-        assert ok.mean() > 0.8
+        lv = check_levels(scene.levels(), sc, lam_idx, 0, T)
         s = orc.Scene(sc, lam_idx=lam_idx, n_v=21)
         s.set_level_dist(rt.CASCADE_LEVEL_DIST, mode="path")
         ref = orc.march(s, orc.VELINTERP, lv, probes[k], d, n_threads=16)
-        st = orc.rel_err_stats(got[ok], ref[ok])
+        st = orc.rel_err_stats(got, ref)
         if storage == "f32":
             assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 1e-4, (b, st)
         else:

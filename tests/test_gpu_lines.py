@@ -2,7 +2,8 @@
 
 Velocity interpolation (2D, Gaussian lines + continuum, cfg2 recipe at 128^2)
 and Core and Voigt (3D 32^3, two Voigt lines): block levels (exact outside
-the threshold tie band), intensities on the same adapted cells, level-0
+the threshold tie band; the oracle then marches the device's level map), intensities on the same adapted
+cells, both velocity-node grid modes, level-0
 equivalence with the Classic march, BF16/FP16 storage of velocity nodes and
 line parameters within their rounding bounds, and the approximation error
 against the dense Classic march (reported).
@@ -69,29 +70,33 @@ def oracle_levels(sc, lam_idx, rule, T, tau=0.25, rel=0.0):
     return orc.batch_levels(lvs)
 
 
+def level_band(sc):
+    """Relative tie band on T and tau_thin inside which device and oracle may take different levels.
+    Gaussian lines: MIP-0 values are FP64 on both sides in the same order of operations, so only the last-ulp
+    rounding of exp and log differs: 1e-9.  Voigt lines: the device takes its single-precision profile (relative
+    error below 1e-4 per value, i.e. 1e-4 absolute on every ln(q ds0)).  That moves a cell's mean by <= 1e-4 and
+    its deviations by <= 2e-4, hence its variance by <= 4e-4 sqrt(Var) + 4e-8, and near the threshold
+    (Var ~ T |mean|) its index of dispersion by <= 4e-4 sqrt(T / |mean|) + 1e-4 T / |mean|: at most 3e-3 T for
+    T >= 1e-2 and |mean ln(chi ds0)| >= 0.5, the cells that decide these scenes' levels."""
+    return 1e-9 if sc.get("profile", "gauss") == "gauss" else 3e-3
+
+
 def check_levels(lv_gpu, sc, lam_idx, rule, T):
+    """The device's level map against the oracle's.  Every block whose oracle level stays put when T and tau_thin
+    move by the tie band must match exactly; inside the band the device's level must be one of the levels the
+    band admits.  Returns the device's map: valid everywhere, it is what the oracle then marches (the intensities
+    are compared on the same adapted cells, no ray left out)."""
+    band = level_band(sc)
     lv = oracle_levels(sc, lam_idx, rule, T)
-    robust = (oracle_levels(sc, lam_idx, rule, T, rel=1e-3) == lv) & (oracle_levels(sc, lam_idx, rule, T, rel=-1e-3) == lv)
-    assert np.array_equal(lv_gpu[robust], lv[robust])
-    assert robust.mean() > 0.9
-    return lv
-
-
-def rays_avoiding(sc, blocks, vox, d):
-    """Mask of the rays (probe voxel, direction index) whose dense cells touch none of `blocks`."""
-    if len(blocks) == 0:
-        return np.ones(len(vox), bool)
-    n, B, dim = sc["n"], sc["brick"], sc["dim"]
-    nb = [n[a] // B for a in range(3)]
-    bad = set(int(b) for b in blocks)
-    ok = np.ones(len(vox), bool)
-    for i, (v, di) in enumerate(zip(vox, d)):
-        v = int(v)
-        pv = (v % n[0], (v // n[0]) % n[1], v // (n[0] * n[1]))[:dim]
-        cells, _, _ = orc.ray_cells(dim, n, pv, sc["dirs"][di])
-        b = (cells[:, 0] // B) + nb[0] * ((cells[:, 1] // B) + nb[1] * (cells[:, 2] // B))
-        ok[i] = not bad.intersection(b.tolist())
-    return ok
+    lo = oracle_levels(sc, lam_idx, rule, T, rel=-band)
+    hi = oracle_levels(sc, lam_idx, rule, T, rel=band)
+    robust = (lo == lv) & (hi == lv)
+    off = lv_gpu != lv
+    assert not np.any(off & robust), "levels differ outside the tie band: blocks %s" % np.nonzero(off & robust)[0][:8]
+    assert np.all(~off | (lv_gpu == lo) | (lv_gpu == hi)), "in-band level outside the band's choices"
+    if off.any():
+        print("levels: %d of %d blocks in the tie band (band %g) took the other level" % (off.sum(), lv.size, band))
+    return lv_gpu
 
 
 def sample_rays(scene, n_dir, n, seed):
@@ -111,23 +116,38 @@ def test_velinterp_parity(rt, vscene):
     k, vox, d = sample_rays(scene, 8, 600, 1)
     for lam0 in (0, 8):
         scene.build(lam0, lam0 + 8, iod_threshold=T)
-        lv_gpu = scene.levels()
-        lv = check_levels(lv_gpu, sc, list(range(lam0, lam0 + 8)), 0, T)
-        # the oracle marches its own levels; rays through a block whose level sits in
-        # the threshold tie band (device and host logarithms differ there) are left out
-        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
-        assert ok.mean() > 0.8
+        lv = check_levels(scene.levels(), sc, list(range(lam0, lam0 + 8)), 0, T)
         s = orc.Scene(sc, lam_idx=list(range(lam0, lam0 + 8)), n_v=21)
         for mode, lev in (("vlm", lv), ("level0", np.where(lv >= 0, 0, -1).astype(np.int8))):
             I = scene.trace(dirs, mode=mode).cpu().numpy()[d, :, k]
             ref = orc.march(s, orc.VELINTERP, lev, vox, d)
-            st = orc.rel_err_stats(I[ok], ref[ok])
+            st = orc.rel_err_stats(I, ref)
             assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 1e-4, (mode, st)
         # approximation error against the dense Classic march (reported)
         ref_c = orc.march(s, orc.CLASSIC, None, vox, d)
         I = scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST).cpu().numpy()[d, :, k]
         print("velinterp VLM(graded) vs Classic:", orc.rel_err_stats(I, ref_c))
-    assert lv_gpu.max() >= 1
+    assert lv.max() >= 1
+
+
+@pytest.mark.parametrize("vgrid", ["full", "orthant"])
+def test_velinterp_grid_modes_parity(rt, vscene, vgrid):
+    """Both node-grid modes (one grid over [-V, V], or one per orthant of directions) against the oracle's, on
+    the same adapted cells, in 2D (8 directions over the 4 quadrants) and 3D (12 directions over the 8 octants)."""
+    import torch
+    for sc, T in ((vscene, 1e-2), (dict(cav_scene(n_dir=12), profile="gauss"), 0.1)):
+        n_dir = sc["dirs"].shape[0]
+        dirs = torch.from_numpy(sc["dirs"]).cuda()
+        scene = rt.Scene.from_dict(sc, emission="velinterp", n_v=9, vgrid=vgrid)
+        k, vox, d = sample_rays(scene, n_dir, 400, 11)
+        scene.build(0, 8, iod_threshold=T)
+        lv = check_levels(scene.levels(), sc, list(range(8)), 0, T)
+        s = orc.Scene(sc, lam_idx=list(range(8)), n_v=9, vgrid=vgrid)
+        I = scene.trace(dirs, mode="vlm").cpu().numpy()[d, :, k]
+        st = orc.rel_err_stats(I, orc.march(s, orc.VELINTERP, lv, vox, d))
+        assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 1e-4, (sc["dim"], vgrid, st)
+        q = np.array([(w < 0).astype(int) @ (1 << np.arange(sc["dim"])) for w in sc["dirs"]])
+        assert len(set(q.tolist())) == 1 << sc["dim"]  # every orthant is exercised
 
 
 @pytest.mark.parametrize("dim,storage", [(2, "bf16"), (2, "f16"), (3, "bf16")])
@@ -155,12 +175,10 @@ def test_velinterp_reduced_precision_storage(rt, vscene, dim, storage):
     assert np.array_equal(scene.levels(), lv_gpu)
     I = scene.trace(dirs, mode="vlm").cpu().numpy()[d, :, k]
     lv = check_levels(lv_gpu, sc, list(range(8)), rule, T)
-    ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
-    assert ok.mean() > 0.8
     s = orc.Scene(sc, lam_idx=list(range(8)), n_v=21)
     ref = orc.march(s, orc.VELINTERP, lv, vox, d)
-    st = orc.rel_err_stats(I[ok], ref[ok])
-    st32 = orc.rel_err_stats(I32[ok], ref[ok])
+    st = orc.rel_err_stats(I, ref)
+    st32 = orc.rel_err_stats(I32, ref)
     print("velinterp %dD %s nodes vs FP64: p99.9 %.3g max %.3g = %.2f u (FP32 nodes: max %.3g)" % (
         dim, storage, st["p99.9"], st["p100"], st["p100"] / u, st32["p100"]))
     # FP32 nodes: Gaussian lines within FP32 rounding; the 3D scene's Voigt lines add the device Voigt
@@ -191,17 +209,12 @@ def test_cav_parity(rt):
     k, vox, d = sample_rays(scene, 8, 300, 2)
     for lam0 in (0, 8):
         scene.build(lam0, lam0 + 8, iod_threshold=T)
-        lv_gpu = scene.levels()
-        lv = check_levels(lv_gpu, sc, list(range(lam0, lam0 + 8)), 1, T)
-        # the oracle marches its own levels; rays through a block whose level sits in
-        # the threshold tie band (device and host logarithms differ there) are left out
-        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
-        assert ok.mean() > 0.8
+        lv = check_levels(scene.levels(), sc, list(range(lam0, lam0 + 8)), 1, T)
         s = orc.Scene(sc, lam_idx=list(range(lam0, lam0 + 8)))
         for mode, lev in (("vlm", lv), ("level0", np.where(lv >= 0, 0, -1).astype(np.int8))):
             I = scene.trace(dirs, mode=mode).cpu().numpy()[d, :, k]
             ref = orc.march(s, orc.CAV, lev, vox, d)
-            st = orc.rel_err_stats(I[ok], ref[ok])
+            st = orc.rel_err_stats(I, ref)
             assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < 1e-3 and st["p100"] < 5e-3, (mode, st)
         ref_c = orc.march(s, orc.CLASSIC, None, vox, d)
         I = scene.trace(dirs, mode="vlm", level_dist=rt.CASCADE_LEVEL_DIST).cpu().numpy()[d, :, k]
@@ -219,12 +232,10 @@ def test_cav_chain_follows_the_averaging_mode(rt):
     k, vox, d = sample_rays(scene, 8, 200, 4)
     for avg in ("log", "linear"):
         scene.build(0, 8, iod_threshold=T, avg_mode=avg)
-        lv_gpu = scene.levels()
-        lv = check_levels(lv_gpu, sc, list(range(0, 8)), 1, T)
-        ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
+        lv = check_levels(scene.levels(), sc, list(range(0, 8)), 1, T)
         s = orc.Scene(sc, lam_idx=list(range(0, 8)), avg_mode=orc.AVG_LOG if avg == "log" else orc.AVG_LINEAR)
         I = scene.trace(dirs, mode="vlm").cpu().numpy()[d, :, k]
-        st = orc.rel_err_stats(I[ok], orc.march(s, orc.CAV, lv, vox, d)[ok])
+        st = orc.rel_err_stats(I, orc.march(s, orc.CAV, lv, vox, d))
         assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < 1e-3 and st["p100"] < 5e-3, (avg, st)
 
 
@@ -247,11 +258,10 @@ def test_cav_reduced_precision_storage(rt, storage, bound):
     assert np.array_equal(scene.levels(), lv_gpu)  # levels do not depend on the storage dtype
     I = scene.trace(dirs, mode="vlm").cpu().numpy()[d, :, k]
     lv = check_levels(lv_gpu, sc, list(range(0, 8)), 1, T)
-    ok = rays_avoiding(sc, np.nonzero(lv_gpu != lv)[0], vox, d)
     s = orc.Scene(sc, lam_idx=list(range(0, 8)))
     ref = orc.march(s, orc.CAV, lv, vox, d)
-    st = orc.rel_err_stats(I[ok], ref[ok])
-    st32 = orc.rel_err_stats(I32[ok], ref[ok])
+    st = orc.rel_err_stats(I, ref)
+    st32 = orc.rel_err_stats(I32, ref)
     print("CaV %s storage vs FP64: p99.9 %.3g max %.3g (FP32 storage: p99.9 %.3g)" % (
         storage, st["p99.9"], st["p100"], st32["p99.9"]))
     assert st["n_ref_zero_mismatch"] == 0 and st["p99.9"] < bound
@@ -284,10 +294,10 @@ def test_velocity_grid_warning(rt, vscene):
     """Sect. 3.1: the build warns when velocity nodes are more than two thermal widths apart."""
     import warnings
     sc = vscene  # |v| <= 30 km/s, thermal width 10 km/s
-    coarse = rt.Scene.from_dict(sc, emission="velinterp", n_v=3)   # 30 km/s apart: 3 widths
+    coarse = rt.Scene.from_dict(sc, emission="velinterp", n_v=2)   # >= 30 km/s apart: >= 3 widths
     with pytest.warns(rt.VelocityGridWarning):
         coarse.build(0, 8)
-    fine = rt.Scene.from_dict(sc, emission="velinterp", n_v=21)    # 3 km/s apart
+    fine = rt.Scene.from_dict(sc, emission="velinterp", n_v=21)    # <= 3 km/s apart (orthant ranges <= 60 km/s)
     with warnings.catch_warnings():
         warnings.simplefilter("error", rt.VelocityGridWarning)
         fine.build(0, 8)

@@ -57,7 +57,8 @@ def test_nrc_workspace_bytes(rt):
 
 
 def test_velocity_grid_ratio():
-    """Node spacing 2 |v| / (n_v - 1) against the thermal width c / (lam0 inv_dld) (Sect. 3.1 warning rule)."""
+    """Node spacing against the thermal width c / (lam0 inv_dld) (Sect. 3.1 warning rule): 2 |v| / (n_v - 1) for
+    the full grid; the widest orthant range / (n_v - 1) for orthant grids."""
     import paper_2511_08498_amd as rt
     nvox = 50
     vel = np.zeros((2, nvox), np.float32)
@@ -67,6 +68,14 @@ def test_velocity_grid_ratio():
     idl[0] = rt.C_KMS / (500.0 * 1.0)                 # line 0: thermal width 1 km/s
     idl[1] = rt.C_KMS / (600.0 * 10.0)                # line 1: 10 km/s
     idl[1, 3] = 0.0                                   # no line in this voxel: ignored
-    r = rt.velocity_grid_ratio(vel, idl, lam0, 21)
+    r = rt.velocity_grid_ratio(vel, idl, lam0, 21, vgrid="full")
     np.testing.assert_allclose(r, [3.0, 0.3], rtol=1e-5)
-    assert np.all(rt.velocity_grid_ratio(np.zeros((2, nvox), np.float32), idl, lam0, 21) == 0)
+    # v along x: the orthant ranges are [0, 30] (w_x > 0) and [-30, 0] (w_x < 0), spacing 1.5 km/s
+    r = rt.velocity_grid_ratio(vel, idl, lam0, 21, vgrid="orthant")
+    np.testing.assert_allclose(r, [1.5, 0.15], rtol=1e-5)
+    # v at 45 degrees: the quadrants across it see [-30/sqrt 2, 30/sqrt 2], the widest range
+    vel[:, 7] = 30.0 / np.sqrt(2.0)
+    r = rt.velocity_grid_ratio(vel, idl, lam0, 21, vgrid="orthant")
+    np.testing.assert_allclose(r, [1.5 * np.sqrt(2.0), 0.15 * np.sqrt(2.0)], rtol=1e-5)
+    for vg in ("full", "orthant"):
+        assert np.all(rt.velocity_grid_ratio(np.zeros((2, nvox), np.float32), idl, lam0, 21, vgrid=vg) == 0)
