@@ -16,7 +16,4 @@ from .scenes import (  # noqa: F401
     make_cfg4_scene,
     make_prominence,
     cfg4_specs,
-    sample_pairs,
-    probe_voxels,
-    brick_morton_order,
 )

@@ -88,69 +88,6 @@ def _blocks_shape(n, dim, B):
     return tuple(n[a] // B for a in range(dim))
 
 
-def brick_morton_order(nb_axes) -> np.ndarray:
-    """Block linear indices of a block grid listed in Morton (z-order) order.
-
-    Geometry only (bit interleaving of block coordinates); used to enumerate
-    probes in the same brick order as the library's storage.
-    """
-    dim = len(nb_axes)
-    nbits = max(1, int(math.ceil(math.log2(max(nb_axes)))))
-    coords = np.stack(np.meshgrid(*[np.arange(s) for s in nb_axes], indexing="ij"), axis=-1)
-    coords = coords.reshape(-1, dim).astype(np.int64)
-    code = np.zeros(coords.shape[0], dtype=np.int64)
-    for bit in range(nbits):
-        for a in range(dim):
-            code |= ((coords[:, a] >> bit) & 1) << (bit * dim + a)
-    order = np.argsort(code, kind="stable")
-    c = coords[order]
-    lin = c[:, 0].copy()
-    mul = 1
-    for a in range(1, dim):
-        mul *= nb_axes[a - 1]
-        lin += c[:, a] * mul
-    return lin
-
-
-def probe_voxels(scene) -> np.ndarray:
-    """Voxel linear indices of all probes (voxel centres of active bricks).
-
-    Order: active bricks in Morton order, voxels inside a brick x fastest.
-    This is the probe order of the library's all-probes output.
-    """
-    dim, n, B = scene["dim"], scene["n"], scene["brick"]
-    nb = _blocks_shape(n, dim, B)
-    act = scene["block_active"]
-    order = [b for b in brick_morton_order(nb) if act[b]]
-    loc = np.stack(np.meshgrid(*[np.arange(B)] * dim, indexing="ij"), axis=-1).reshape(-1, dim)
-    # x fastest inside the brick
-    loc = loc[np.lexsort([loc[:, a] for a in range(dim)])]
-    out = []
-    for b in order:
-        bc = []
-        r = b
-        for a in range(dim):
-            bc.append(r % nb[a])
-            r //= nb[a]
-        vc = [bc[a] * B + loc[:, a] for a in range(dim)]
-        lin = vc[0].astype(np.int64)
-        mul = 1
-        for a in range(1, dim):
-            mul *= n[a - 1]
-            lin = lin + vc[a] * mul
-        out.append(lin)
-    return np.concatenate(out).astype(np.int32) if out else np.zeros(0, np.int32)
-
-
-def sample_pairs(scene, n_pairs: int, seed: int):
-    """Seeded (probe voxel, direction) pairs, probes uniform over active voxels."""
-    rng = np.random.default_rng(np.random.SeedSequence(seed))
-    probes = probe_voxels(scene)
-    pi = rng.integers(0, probes.size, size=n_pairs)
-    di = rng.integers(0, scene["dirs"].shape[0], size=n_pairs)
-    return probes[pi].astype(np.int32), di.astype(np.int32)
-
-
 def _mask_from_blocks(n, dim, B, block_active):
     nb = _blocks_shape(n, dim, B)
     act = block_active.reshape(tuple(reversed(nb)))

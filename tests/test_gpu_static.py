@@ -12,7 +12,8 @@ import pytest
 
 import oracle as orc
 from oracle.exact import adapted_cells_exact
-from synth import brick_morton_order, make_cfg1
+from oracle.order import morton_order, probe_voxels
+from synth import make_cfg1
 
 pytestmark = pytest.mark.gpu
 
@@ -54,9 +55,10 @@ def all_pairs(scene, n_dir):
 def test_classification_and_morton_slots(rt, cfg1):
     scene = rt.Scene.from_dict(cfg1)
     assert scene.info["n_active"] == int(cfg1["block_active"].sum()) == 45
-    order = [b for b in brick_morton_order((8, 8)) if cfg1["block_active"][b]]
+    order = [b for b in morton_order((8, 8)) if cfg1["block_active"][b]]
     assert list(scene.active_blocks()) == order
     assert scene.info["n_probes"] == 45 * 64
+    assert np.array_equal(scene.probe_voxels(), probe_voxels(cfg1))
 
 
 @pytest.mark.parametrize("T", [1e-2, 1.0])

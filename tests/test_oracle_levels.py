@@ -167,3 +167,15 @@ def test_zero_in_active_block_is_clamped_and_counted(orc):
     c[5] = 0.0
     lv, _, _, clamped = orc.levels_one(s, e, c, np.ones(1, np.uint8), T=1.0, want_values=True)
     assert clamped == 1  # flagged; a zero child makes the log mean tiny (thin), so no level is asserted
+
+
+def test_morton_order_pins():
+    """Sect. 2.3.1 orders active blocks by Morton code: the z-order of a 4 x 4 and a 2 x 2 x 2 block grid
+    written out by hand, and the probe order of an all-probes trace (blocks in that order, voxels x fastest)."""
+    from oracle.order import morton_order, probe_voxels
+    assert list(morton_order((4, 4))) == [0, 1, 4, 5, 2, 3, 6, 7, 8, 9, 12, 13, 10, 11, 14, 15]
+    assert list(morton_order((2, 2, 2))) == [0, 1, 2, 3, 4, 5, 6, 7]
+    # 4 x 2: x has two bits, y one; codes x0 | y0 << 1 | x1 << 2
+    assert list(morton_order((4, 2))) == [0, 1, 4, 5, 2, 3, 6, 7]
+    sc = dict(dim=2, n=(4, 4, 1), brick=2, block_active=np.array([0, 1, 1, 1], np.uint8))
+    assert list(probe_voxels(sc)) == [2, 3, 6, 7, 8, 9, 12, 13, 10, 11, 14, 15]
