@@ -474,6 +474,26 @@ rt_status rt_trace_j_workspace_bytes(const rt_scene* scene, int32_t n_dir, int64
                                      size_t* h_bytes);
 
 /*
+ * rt_trace_j_noalloc -- rt_trace_j for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the direction-chunk partials live in a device array of
+ * the library (64 MiB, one per device, held until the process ends) instead
+ * of a caller workspace.  Same arguments as rt_trace_j without d_work; the
+ * result equals rt_trace_j's with a workspace of rt_trace_j_workspace_bytes
+ * bit for bit (same chunks, same fixed-order reduction).
+ * Limit: the partials, rt_trace_j_workspace_bytes with the batch's wavelength
+ * count, must fit 64 MiB (e.g. at most 16,384 probes at 64 directions with
+ * psi); larger requests fail with RT_E_ARG before any device work.  Calls
+ * that overlap on one device (concurrent streams or threads) share the array
+ * and race; the caller serialises them.  Calls nothing that allocates.
+ * Asynchronous.  Errors as rt_trace_j, RT_E_HIP if the array's address cannot
+ * be looked up.
+ */
+rt_status rt_trace_j_noalloc(const rt_scene* scene, const rt_trace_params* params, const float* d_dirs,
+                             const float* d_weights, int32_t n_dir, const int32_t* d_probes, int64_t n_probes,
+                             float* d_J, float* d_psi, void* stream);
+
+/*
  * ------------------------------------------------- neural radiance cache
  * Truncated march: every ray is marched to path length t_trunc (index units);
  * the part beyond is the far field, to be supplied by a learned cache (the

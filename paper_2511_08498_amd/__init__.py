@@ -35,7 +35,7 @@ EXPORTS = (
     "rt_graph_destroy", "rt_trace_truncated", "rt_nrc_num_params", "rt_nrc_create", "rt_nrc_destroy",
     "rt_nrc_get_weights", "rt_nrc_set_weights", "rt_nrc_pack", "rt_nrc_train", "rt_nrc_loss", "rt_nrc_gradients",
     "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate", "rt_scene_workspace_bytes", "rt_nrc_workspace_bytes",
-    "rt_trace_j", "rt_trace_j_workspace_bytes", "rt_trace_interval", "rt_nrc_get_state", "rt_nrc_set_state",
+    "rt_trace_j", "rt_trace_j_workspace_bytes", "rt_trace_j_noalloc", "rt_trace_interval", "rt_nrc_get_state", "rt_nrc_set_state",
 )
 _VOID = ("rt_scene_destroy", "rt_last_error", "rt_version", "rt_batch_destroy", "rt_graph_destroy", "rt_nrc_destroy")
 
@@ -147,6 +147,7 @@ def lib():
     L.rt_trace_truncated.argtypes = [_P, _P, ctypes.c_float, i32, _P, _P, i32, _P, i64, _P, _P, _P, _P, _P, _P]
     L.rt_scene_workspace_bytes.argtypes = [_P, i64, ctypes.POINTER(ctypes.c_size_t)]
     L.rt_trace_j.argtypes = [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P, ctypes.c_size_t, _P]
+    L.rt_trace_j_noalloc.argtypes = [_P, _P, _P, _P, i32, _P, i64, _P, _P, _P]
     L.rt_trace_j_workspace_bytes.argtypes = [_P, i32, i64, i32, ctypes.POINTER(ctypes.c_size_t)]
     L.rt_nrc_workspace_bytes.argtypes = [_P, ctypes.POINTER(ctypes.c_size_t)]
     L.rt_nrc_num_params.argtypes = [_P]
@@ -508,6 +509,19 @@ class Scene:
                                 int(wb), _stream(stream)))
         self._last_j = (td, tw, tp, work)
         return J, (psi if with_psi else None)
+
+    def trace_j_noalloc(self, dirs, weights, J, psi=None, probes=None, mode="vlm", I0=0.0, max_level=-1,
+                        step_cap=0, level_dist=None, grade="entry", stream=None):
+        """rt_trace_j_noalloc: rt_trace_j with the library's own device scratch for the chunk partials.
+        Every argument is a device tensor the caller already holds (dirs [n_dir][dim], weights [n_dir],
+        probes int32 or None, J / psi [batch][n_probes]); nothing is allocated here or in the library."""
+        nd = int(dirs.shape[0])
+        n_probes = self.info["n_probes"] if probes is None else probes.numel()
+        p = self._tparams(mode, max_level, I0, step_cap, None, level_dist, grade)
+        _check(lib().rt_trace_j_noalloc(self.h, ctypes.byref(p), dirs.data_ptr(), weights.data_ptr(), nd,
+                                        probes.data_ptr() if probes is not None else None, int(n_probes),
+                                        J.data_ptr(), psi.data_ptr() if psi is not None else None, _stream(stream)))
+        return J, psi
 
     def active_blocks(self):
         out = np.zeros(self.info["n_active"], np.int32)

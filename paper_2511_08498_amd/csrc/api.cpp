@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -509,14 +510,13 @@ rt_status rt_trace_j_workspace_bytes(const rt_scene* sc, int32_t n_dir, int64_t 
     return RT_OK;
 }
 
-rt_status rt_trace_j(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, const float* d_weights,
-                     int32_t n_dir, const int32_t* d_probes, int64_t n_probes, float* d_J, float* d_psi, float* d_work,
-                     size_t work_bytes, void* stream)
+}  // extern "C"
+
+// rt_trace_j with the chunk partials in d_work (nullable: one chunk).
+static rt_status trace_j_impl(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, const float* d_weights,
+                              int32_t n_dir, const int32_t* d_probes, int64_t n_probes, float* d_J, float* d_psi,
+                              float* d_work, size_t work_bytes, hipStream_t s)
 {
-    g_err.clear();
-    if (!sc || !p || !d_dirs || !d_weights || (!d_J && n_probes != 0)) return fail(RT_E_ARG, "null argument");
-    rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace_j");
-    if (st != RT_OK || n_probes == 0) return st;
     const int nl = sc->batch_end - sc->batch_begin;
     const long long per_chunk = (long long)nl * n_probes * (d_psi ? 2 : 1);
     long long chunks = j_target_chunks(n_dir, n_probes);
@@ -538,7 +538,6 @@ rt_status rt_trace_j(const rt_scene* sc, const rt_trace_params* p, const float* 
     t.jmode = 1;
     t.dirs_per_chunk = dpc;
     t.weights = d_weights;
-    hipStream_t s = (hipStream_t)stream;
     if (chunks == 1) {
         t.part_J = d_J;
         t.part_psi = d_psi;
@@ -552,6 +551,70 @@ rt_status rt_trace_j(const rt_scene* sc, const rt_trace_params* p, const float* 
     RT_HIP(launch_reduce_chunks(t.part_J, (int)chunks, n, d_J, s));
     if (d_psi) RT_HIP(launch_reduce_chunks(t.part_psi, (int)chunks, n, d_psi, s));
     return RT_OK;
+}
+
+// Device scratch of rt_trace_j_noalloc: the direction-chunk partials of J and
+// psi.  One copy per device, held until the process ends; host code uses only
+// the address hipGetSymbolAddress returns for the current device.
+static constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
+
+static constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[kMaxDevices];
+
+// Address of the current device's scratch, looked up once per device.
+static rt_status scratch_address(float** out)
+{
+    int dev = -1;
+    RT_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(RT_E_UNSUPPORTED, "device ordinal %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) return fail(RT_E_HIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = (float*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return RT_OK;
+}
+
+extern "C" {
+
+rt_status rt_trace_j(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs, const float* d_weights,
+                     int32_t n_dir, const int32_t* d_probes, int64_t n_probes, float* d_J, float* d_psi, float* d_work,
+                     size_t work_bytes, void* stream)
+{
+    g_err.clear();
+    if (!sc || !p || !d_dirs || !d_weights || (!d_J && n_probes != 0)) return fail(RT_E_ARG, "null argument");
+    rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace_j");
+    if (st != RT_OK || n_probes == 0) return st;
+    return trace_j_impl(sc, p, d_dirs, d_weights, n_dir, d_probes, n_probes, d_J, d_psi, d_work, work_bytes,
+                        (hipStream_t)stream);
+}
+
+rt_status rt_trace_j_noalloc(const rt_scene* sc, const rt_trace_params* p, const float* d_dirs,
+                             const float* d_weights, int32_t n_dir, const int32_t* d_probes, int64_t n_probes,
+                             float* d_J, float* d_psi, void* stream)
+{
+    g_err.clear();
+    if (!sc || !p || !d_dirs || !d_weights || (!d_J && n_probes != 0)) return fail(RT_E_ARG, "null argument");
+    rt_status st = check_trace(sc, p, n_dir, d_probes, n_probes, "rt_trace_j_noalloc");
+    if (st != RT_OK || n_probes == 0) return st;
+    // the chunking rt_trace_j takes with a workspace of rt_trace_j_workspace_bytes
+    const long long chunks = j_target_chunks(n_dir, n_probes);
+    const size_t nl = (size_t)(sc->batch_end - sc->batch_begin);
+    const size_t need = chunks <= 1 ? 0 : (size_t)chunks * nl * (size_t)n_probes * sizeof(float) * (d_psi ? 2 : 1);
+    if (need > kNoAllocScratchBytes)
+        return fail(RT_E_ARG,
+                    "rt_trace_j_noalloc: %lld probes x %d directions need %zu bytes of chunk partials, more than "
+                    "its %zu-byte device scratch (use rt_trace_j with a workspace)",
+                    (long long)n_probes, n_dir, need, kNoAllocScratchBytes);
+    float* work = nullptr;
+    if (need > 0) RT_TRY(scratch_address(&work));
+    return trace_j_impl(sc, p, d_dirs, d_weights, n_dir, d_probes, n_probes, d_J, d_psi, work,
+                        work ? kNoAllocScratchBytes : 0, (hipStream_t)stream);
 }
 
 rt_status rt_trace_truncated(const rt_scene* sc, const rt_trace_params* p, float t_trunc, int32_t gen,
