@@ -28,7 +28,16 @@
  *   - Pointers named d_* are device pointers (HIP device memory) owned by
  *     the caller; pointers named h_* are host pointers.  `stream` is a
  *     hipStream_t passed as void*.  Every device-side call is asynchronous on
- *     that stream unless documented as synchronising.
+ *     that stream unless documented as synchronising; a synchronising call
+ *     waits for that stream only.
+ *   - Ownership: the caller allocates all device memory -- inputs, outputs
+ *     and every workspace (scene, batch, cache), each sized by a host-only
+ *     *_workspace_bytes query and at least 256-byte aligned.  The library
+ *     sub-allocates inside a workspace and never calls hipMalloc on these
+ *     paths; a handle owns only host memory, and the workspace must outlive
+ *     it and any work still in flight on the stream.  Only the debugging
+ *     helpers rt_scene_cell_values and rt_debug_visited allocate (and free)
+ *     small temporary device buffers.
  *   - Errors: every call returns rt_status; no C++ exception crosses the
  *     ABI; rt_last_error() gives a thread-local message for the last failure.
  *     Arguments are validated on the host before any device work.  Device
@@ -259,28 +268,48 @@ typedef struct rt_device_err {
 typedef struct rt_scene rt_scene;
 
 /*
- * rt_scene_create -- classify blocks, order the active ones in Morton order,
- * assign storage slots (Sect. 2.3.1 offset table) and allocate the scene's
- * device storage for one wavelength batch.  For the lines model it also
- * builds the wavelength-independent level chains (velocity grid parameters,
- * Core-and-Voigt line parameters).  Synchronises `stream` (the active-block
- * count sizes the allocation).  On success *out owns device memory released
- * by rt_scene_destroy.  Every input value is checked on the device first:
- * eta, chi, line strengths, damping, Doppler widths and background must be
- * finite and >= 0, velocities finite.
- * Errors: RT_E_ARG (shape/enum/pointer, or negative / non-finite input
- * values, counted in the message), RT_E_HIP.
- */
-rt_status rt_scene_create(const rt_scene_desc* desc, const rt_scene_inputs* inputs, void* stream, rt_scene** out);
-
-/*
- * rt_scene_workspace_bytes -- device bytes rt_scene_create allocates for this
- * descriptor when n_active blocks are active (n_active = the block count gives
- * the upper bound; after creation rt_scene_info.storage_bytes is the same
- * figure).  Host only: no device work, inputs not needed.  Errors: RT_E_ARG,
- * RT_E_UNSUPPORTED as for rt_scene_create.
+ * rt_scene_workspace_bytes -- size of the device workspace a scene with
+ * n_active active blocks needs (the scene's whole device storage: block
+ * tables, level structure, and the stored values of one wavelength batch).
+ * n_active = the block count gives the upper bound for any inputs;
+ * n_active = 0 gives at least what rt_scene_count_active needs.  After
+ * creation rt_scene_info.storage_bytes is the same figure.  Host only: no
+ * device work, inputs not needed.  Errors: RT_E_ARG, RT_E_UNSUPPORTED as for
+ * rt_scene_create.
  */
 rt_status rt_scene_workspace_bytes(const rt_scene_desc* desc, int64_t n_active, size_t* h_bytes);
+
+/*
+ * rt_scene_count_active -- the first phase of a two-phase creation: checks
+ * every input value, classifies the blocks (a block is active when any of its
+ * inputs is nonzero, or as d_block_mask says; Sect. 2.3.1) and returns the
+ * number of active blocks, so that the caller can size the workspace of
+ * rt_scene_create exactly.  d_ws: device workspace of at least
+ * rt_scene_workspace_bytes(desc, 0) bytes, used as scratch only (its contents
+ * are not needed afterwards).  Synchronises `stream`.  Errors as
+ * rt_scene_create.
+ */
+rt_status rt_scene_count_active(const rt_scene_desc* desc, const rt_scene_inputs* inputs, void* d_ws, size_t ws_bytes,
+                                void* stream, int64_t* h_n_active);
+
+/*
+ * rt_scene_create -- classify blocks, order the active ones in Morton order,
+ * assign storage slots (Sect. 2.3.1 offset table) and lay the scene's device
+ * storage out in the caller's workspace d_ws (ws_bytes at least
+ * rt_scene_workspace_bytes(desc, n_active) for the inputs' active-block
+ * count, from rt_scene_count_active, or the upper bound).  For the lines
+ * model it also builds the wavelength-independent level chains (velocity grid
+ * parameters, Core-and-Voigt line parameters).  Synchronises `stream` (the
+ * active-block count decides the layout).  Every input value is checked on
+ * the device first: eta, chi, line strengths, damping, Doppler widths and
+ * background must be finite and >= 0, velocities finite.  The workspace must
+ * stay allocated and untouched by the caller until rt_scene_destroy.
+ * Errors: RT_E_ARG (shape/enum/pointer, negative / non-finite input values
+ * counted in the message, a null, misaligned or too small workspace, with the
+ * size needed in the message), RT_E_UNSUPPORTED, RT_E_HIP.
+ */
+rt_status rt_scene_create(const rt_scene_desc* desc, const rt_scene_inputs* inputs, void* d_ws, size_t ws_bytes,
+                          void* stream, rt_scene** out);
 
 /*
  * rt_scene_build -- for wavelengths [lam_begin, lam_end) (at most
@@ -337,24 +366,27 @@ rt_status rt_trace_interval(const rt_scene* scene, const rt_trace_params* params
 /* Scene facts (host only, no device work). */
 rt_status rt_scene_get_info(const rt_scene* scene, rt_scene_info* h_info);
 
-/* Active blocks in Morton (storage) order: host int32 [n_active].  Synchronising. */
-rt_status rt_scene_active_blocks(const rt_scene* scene, int32_t* h_blocks);
+/* Active blocks in Morton (storage) order: host int32 [n_active].  Ordered on `stream`, synchronises it. */
+rt_status rt_scene_active_blocks(const rt_scene* scene, int32_t* h_blocks, void* stream);
 
-/* VLM level of every block for the current batch, -1 = empty: host int8 [n_blocks].  Synchronising. */
-rt_status rt_scene_levels(const rt_scene* scene, int8_t* h_levels);
+/* VLM level of every block for the current batch, -1 = empty: host int8 [n_blocks].  Ordered on `stream`,
+ * synchronises it. */
+rt_status rt_scene_levels(const rt_scene* scene, int8_t* h_levels, void* stream);
 
 /* Packed block states (state = level + 1, 0 = empty; 3 bits, 21 per word): host uint64 [n_state_words].
- * Synchronising. */
-rt_status rt_scene_states(const rt_scene* scene, uint64_t* h_words);
+ * Ordered on `stream`, synchronises it. */
+rt_status rt_scene_states(const rt_scene* scene, uint64_t* h_words, void* stream);
 
 /*
  * Stored values of given cells for the current batch (parity checks).
  *   h_cells  host int32 [n][4]: x, y, z (any voxel inside the cell) and level.
  *   h_out    host float [n][RT_LAM_BATCH][2]: eta, chi per batch wavelength,
  *            decoded to float32; static emission only.
- * Synchronising.  Errors: RT_E_ARG (cell in an empty block, level out of range).
+ * Ordered on `stream`, synchronises it; allocates temporary device buffers (a debugging helper).
+ * Errors: RT_E_ARG (cell in an empty block, level out of range).
  */
-rt_status rt_scene_cell_values(const rt_scene* scene, int32_t n, const int32_t* h_cells, float* h_out);
+rt_status rt_scene_cell_values(const rt_scene* scene, int32_t n, const int32_t* h_cells, float* h_out,
+                               void* stream);
 
 /*
  * Adapted-grid cells visited by one ray, using the trace kernel's own
@@ -413,13 +445,20 @@ typedef struct rt_batch_params {
 
 typedef struct rt_batch rt_batch;
 
-/* Validates the jobs, uploads the job table (synchronises `stream`) and sizes
+/* Device workspace of a batch of n_jobs jobs (job table, queue counters,
+ * error counters).  Host only. */
+rt_status rt_batch_workspace_bytes(int32_t n_jobs, size_t* h_bytes);
+
+/* Validates the jobs, uploads the job table into the caller's workspace d_ws
+ * (at least rt_batch_workspace_bytes(n_jobs); synchronises `stream`) and sizes
  * the queue.  The scenes must have a built batch; their storage is read at
  * every rt_batch_run, so rebuilding a scene for another batch of the same
- * size and storage dtype is picked up by the next run.  Errors: RT_E_ARG, RT_E_STATE, RT_E_UNSUPPORTED
- * (non-static emission), RT_E_HIP. */
-rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_batch_params* params, void* stream,
-                          rt_batch** out);
+ * size and storage dtype is picked up by the next run.  The workspace must
+ * outlive the batch handle.  Errors: RT_E_ARG (also a null, misaligned or too
+ * small workspace), RT_E_STATE, RT_E_UNSUPPORTED (non-static emission),
+ * RT_E_HIP. */
+rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_batch_params* params, void* d_ws,
+                          size_t ws_bytes, void* stream, rt_batch** out);
 
 /* Runs the batch: a queue-reset kernel and the persistent kernel.  Kernels
  * only (no allocation, copy or memset), so it can be captured in a graph. */
@@ -428,8 +467,8 @@ rt_status rt_batch_run(const rt_batch* batch, void* stream);
 /* Total 64-probe tiles of the batch (the queue length). */
 rt_status rt_batch_tiles(const rt_batch* batch, int64_t* h_tiles);
 
-/* Step-cap hits of the batch's runs (synchronising). */
-rt_status rt_batch_device_error(const rt_batch* batch, rt_device_err* h_err);
+/* Step-cap hits of the batch's runs (ordered on `stream`, synchronises it). */
+rt_status rt_batch_device_error(const rt_batch* batch, rt_device_err* h_err, void* stream);
 
 void rt_batch_destroy(rt_batch* batch);
 
@@ -437,10 +476,12 @@ void rt_batch_destroy(rt_batch* batch);
  * Autotuner: times every launch shape of a small candidate grid (waves per
  * workgroup x workgroups per CU x tiles per pop) on the given jobs, `reps`
  * runs each after one warm-up, and returns the fastest in *h_best with its
- * mean time in *h_best_ms.  Synchronising; writes the jobs' outputs.
+ * mean time in *h_best_ms.  d_ws: a batch workspace for these jobs
+ * (rt_batch_workspace_bytes), reused by every candidate.  Synchronises
+ * `stream`; writes the jobs' outputs.
  */
-rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t reps, void* stream,
-                            rt_batch_params* h_best, float* h_best_ms);
+rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t reps, void* d_ws, size_t ws_bytes,
+                            void* stream, rt_batch_params* h_best, float* h_best_ms);
 
 /*
  * Graph capture of work issued on `stream` (e.g. builds + rt_batch_run for a
@@ -547,22 +588,29 @@ typedef struct rt_nrc_desc {
 
 typedef struct rt_nrc rt_nrc;
 
-/* Device bytes rt_nrc_create allocates for this descriptor (host only, no device work). */
+/* Device workspace of the cache for this descriptor: weights, Adam moments,
+ * gradients and the training activations of max_batch rows (host only, no
+ * device work). */
 rt_status rt_nrc_workspace_bytes(const rt_nrc_desc* desc, size_t* h_bytes);
 rt_status rt_nrc_num_params(int32_t* h_n);
-rt_status rt_nrc_create(const rt_nrc_desc* desc, void* stream, rt_nrc** out);
+/* Lays the cache out in the caller's workspace d_ws (at least
+ * rt_nrc_workspace_bytes, 256-byte aligned, outliving the handle) and
+ * initialises the weights (synchronises `stream`).  Errors: RT_E_ARG (also a
+ * null, misaligned or too small workspace), RT_E_HIP. */
+rt_status rt_nrc_create(const rt_nrc_desc* desc, void* d_ws, size_t ws_bytes, void* stream, rt_nrc** out);
+/* Releases the host handle (the workspace is the caller's).  NULL is ignored. */
 void rt_nrc_destroy(rt_nrc* nrc);
-/* FP32 master weights, host float [num_params] (checkpoint / restore). */
-rt_status rt_nrc_get_weights(const rt_nrc* nrc, float* h_w);
+/* FP32 master weights, host float [num_params] (checkpoint / restore); ordered on `stream`, synchronises it. */
+rt_status rt_nrc_get_weights(const rt_nrc* nrc, float* h_w, void* stream);
 rt_status rt_nrc_set_weights(rt_nrc* nrc, const float* h_w, void* stream);
 /* Whole training state, for resuming training: FP32 master weights, Adam's first
  * and second moments (host float [num_params] each) and the step count (which
  * also keys the counter-based batch sampling).  Training is deterministic, so
  * steps run after rt_nrc_set_state on a cache created with the same descriptor
  * repeat those run after the matching rt_nrc_get_state bit for bit.
- * get synchronises; set is ordered on `stream` and synchronises it.
+ * Both are ordered on `stream` and synchronise it.
  * Errors: RT_E_ARG (null pointer, negative step), RT_E_HIP. */
-rt_status rt_nrc_get_state(const rt_nrc* nrc, float* h_w, float* h_m, float* h_v, int32_t* h_step);
+rt_status rt_nrc_get_state(const rt_nrc* nrc, float* h_w, float* h_m, float* h_v, int32_t* h_step, void* stream);
 rt_status rt_nrc_set_state(rt_nrc* nrc, const float* h_w, const float* h_m, const float* h_v, int32_t step,
                            void* stream);
 /* Packs generation-mode outputs of one batch into training rows starting at row0
@@ -574,8 +622,8 @@ rt_status rt_nrc_pack(const rt_scene* scene, const float* d_dirs, int32_t n_dir,
  * from the n rows (mean squared error on the target). */
 rt_status rt_nrc_train(rt_nrc* nrc, const float* d_raw, const float* d_target, int64_t n, int32_t steps, int32_t batch,
                        float lr, void* stream);
-/* Mean loss of the last training batch (synchronising). */
-rt_status rt_nrc_loss(const rt_nrc* nrc, float* h_loss);
+/* Mean loss of the last training batch (ordered on `stream`, synchronises it). */
+rt_status rt_nrc_loss(const rt_nrc* nrc, float* h_loss, void* stream);
 /* Gradients of the mean squared error over the first n rows (n multiple of 256,
  * <= max_batch) into d_grad [num_params]; for checking the backward pass. */
 rt_status rt_nrc_gradients(rt_nrc* nrc, const float* d_raw, const float* d_target, int64_t n, float* d_grad,
@@ -596,11 +644,12 @@ rt_status rt_nrc_validate(const rt_nrc* nrc, const rt_scene* scene, const float*
                           const float* d_T_near, const float* d_I_far, float thresh, float* d_I_pred,
                           uint8_t* d_fallback, float* d_err, void* stream);
 
-/* Device error counters accumulated by traces of this scene (synchronising); reset clears them. */
-rt_status rt_scene_device_error(const rt_scene* scene, rt_device_err* h_err);
+/* Device error counters accumulated by traces of this scene (ordered on `stream`, synchronises it); reset
+ * clears them. */
+rt_status rt_scene_device_error(const rt_scene* scene, rt_device_err* h_err, void* stream);
 rt_status rt_scene_reset_device_error(rt_scene* scene, void* stream);
 
-/* Releases the scene's device memory and handle.  NULL is ignored. */
+/* Releases the scene's host handle (its device storage is the caller's workspace).  NULL is ignored. */
 void rt_scene_destroy(rt_scene* scene);
 
 /* Thread-local description of the last failure in this thread ("" if none). */

@@ -150,28 +150,136 @@ static void make_geo(const rt_scene_desc* d, Geo& g)
 // Direction classes of the velocity-interpolation grids.
 static int vclasses(const rt_scene_desc* d) { return d->vgrid == RT_VGRID_ORTHANT ? 1 << d->dim : 1; }
 
-// Bytes of one allocation as rt_scene::alloc makes it.
-static size_t alloc_bytes(size_t count, size_t elem) { return std::max<size_t>(count * elem, 256); }
-
-// Device bytes of a scene with na active blocks: the same list of buffers rt_scene_create allocates.
-static size_t scene_bytes(const rt_scene_desc* d, const Geo& g, long long na)
+// The scene's workspace in the order it is carved.  First the pieces sized by
+// the block count: Morton order, occupancy, slot table, active list and count,
+// levels, packed states, device error counters and the input-check counter.
+static bool carve_fixed(const Geo& g, Carver& c, SceneBufs& B, unsigned long long** d_bad)
 {
-    const size_t nb = (size_t)g.nblocks, cells = (size_t)na * g.cells;
-    size_t b = alloc_bytes(nb, 4) + alloc_bytes(nb, 1) + alloc_bytes(nb, 4) + alloc_bytes(nb, 4) + alloc_bytes(1, 4) +
-               alloc_bytes(nb, 1) + alloc_bytes((size_t)g.n_state_words, 8) + alloc_bytes(4, 8) +
-               alloc_bytes(1, 8);  // the last: the input-validation counter
-    b += alloc_bytes(((size_t)na << (d->dim * (g.log2B - g.feat_level))) * kLam, 16);
-    if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) b += alloc_bytes(cells * kLam * 2, 4);
+    const size_t nb = (size_t)g.nblocks;
+    return c.take(&B.morton, nb) && c.take(&B.active, nb) && c.take(&B.slot, nb) && c.take(&B.active_list, nb) &&
+           c.take(&B.n_active, 1) && c.take(&B.levels, nb) && c.take(&B.states, (size_t)g.n_state_words) &&
+           c.take(&B.err, 4) && c.take(d_bad, 1);
+}
+
+// Then the pieces sized by the active-block count: level statistics of the
+// cache features, and the stored values of the emission mode (static values,
+// velocity grids and node values, or the Core-and-Voigt chain and its
+// reduced-precision copy).
+static bool carve_active(const rt_scene_desc* d, const Geo& g, long long na, Carver& c, SceneBufs& B)
+{
+    const size_t cells = (size_t)na * g.cells;
+    if (!c.take(&B.fstats, ((size_t)na << (d->dim * (g.log2B - g.feat_level))) * kLam)) return false;
+    if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC)
+        if (!c.take((float**)&B.vals, cells * kLam * 2)) return false;
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP) {
         const size_t nq = (size_t)vclasses(d);
-        b += alloc_bytes(nq * cells, 16) + alloc_bytes(nq * cells, 8) +
-             alloc_bytes(nq * cells * (size_t)d->n_v * kLam * 2, 4);
+        if (!c.take(&B.vgrid, nq * cells) || !c.take(&B.vrange, nq * cells) ||
+            !c.take(&B.vnodes, nq * cells * (size_t)d->n_v * kLam * 2))
+            return false;
     }
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
         const size_t rec = (size_t)cav_rec_floats(d->n_lines);
-        b += alloc_bytes(cells * rec, 4) + alloc_bytes(cells * rec, 2);
+        if (!c.take(&B.cav, cells * rec) || !c.take((uint16_t**)&B.cav_lp, cells * rec)) return false;
     }
-    return b;
+    return true;
+}
+
+// Workspace bytes of a scene with na active blocks (the carving above, dry run).
+static size_t scene_bytes(const rt_scene_desc* d, const Geo& g, long long na)
+{
+    Carver c;
+    SceneBufs B;
+    unsigned long long* bad = nullptr;
+    carve_fixed(g, c, B, &bad);
+    carve_active(d, g, na, c, B);
+    return c.used;
+}
+
+// Bytes of the block-count part alone (what rt_scene_count_active needs).
+static size_t fixed_bytes(const Geo& g)
+{
+    Carver c;
+    SceneBufs B;
+    unsigned long long* bad = nullptr;
+    carve_fixed(g, c, B, &bad);
+    return c.used;
+}
+
+static void bind_inputs(const rt_scene_inputs* inp, const Geo& g, Inputs& in)
+{
+    in.eta = inp->d_eta;
+    in.chi = inp->d_chi;
+    in.eta_star = inp->d_eta_star;
+    in.chi_star = inp->d_chi_star;
+    in.damp = inp->d_damp;
+    in.inv_dld = inp->d_inv_dld;
+    in.eta_bg = inp->d_eta_bg;
+    in.chi_bg = inp->d_chi_bg;
+    in.vel = inp->d_vel;
+    in.mask = inp->d_block_mask;
+    in.nvox = (long long)g.n[0] * g.n[1] * g.n[2];
+}
+
+// Input check, block classification, Morton order and slots (Sect. 2.3.1) into
+// the block-count pieces of B; reads the active count back (synchronises s).
+static rt_status classify_blocks(const rt_scene_desc* d, const Geo& g, const Inputs& in, SceneBufs& B,
+                                 unsigned long long* d_bad, hipStream_t s, int32_t* h_na)
+{
+    // Morton order of all blocks (geometry only)
+    std::vector<std::pair<uint64_t, int32_t>> mo((size_t)g.nblocks);
+    for (long long b = 0; b < g.nblocks; ++b) {
+        uint32_t bc[3] = {(uint32_t)(b % g.nb[0]), (uint32_t)((b / g.nb[0]) % g.nb[1]),
+                          (uint32_t)(b / ((long long)g.nb[0] * g.nb[1]))};
+        uint64_t code = 0;
+        for (int bit = 0; bit < 21; ++bit)
+            for (int a = 0; a < g.dim; ++a) code |= (uint64_t)((bc[a] >> bit) & 1u) << (bit * g.dim + a);
+        mo[(size_t)b] = {code, (int32_t)b};
+    }
+    std::sort(mo.begin(), mo.end());
+    std::vector<int32_t> morton((size_t)g.nblocks);
+    for (size_t i = 0; i < mo.size(); ++i) morton[i] = mo[i].second;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(B.morton, morton.data(), morton.size() * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
+        hipSuccess)
+        return fail(RT_E_HIP, "upload: %s", hipGetErrorString(e));
+    // step-cap hits, first ray that hit the cap, probe indices outside the grid, unused; input-check count
+    unsigned long long err0[5] = {0ull, ~0ull, 0ull, 0ull, 0ull};
+    if ((e = hipMemcpyAsync(B.err, err0, 4 * sizeof(unsigned long long), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_bad, err0 + 4, sizeof(unsigned long long), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return fail(RT_E_HIP, "upload: %s", hipGetErrorString(e));
+    if ((e = launch_validate(in, d->model, d->n_lam, d->n_lines, d->dim, d_bad, s)) != hipSuccess)
+        return fail(RT_E_HIP, "validate: %s", hipGetErrorString(e));
+    if ((e = launch_classify(g, in, d->model, d->n_lam, d->n_lines, d->dense, B.active, s)) != hipSuccess)
+        return fail(RT_E_HIP, "classify: %s", hipGetErrorString(e));
+    if ((e = launch_slots(g, B.morton, B.active, B.slot, B.active_list, B.n_active, s)) != hipSuccess)
+        return fail(RT_E_HIP, "slots: %s", hipGetErrorString(e));
+    if ((e = launch_fill_levels(g, B.levels, s)) != hipSuccess) return fail(RT_E_HIP, "levels: %s", hipGetErrorString(e));
+    int32_t na = 0;
+    unsigned long long n_bad = 0;
+    if ((e = hipMemcpyAsync(&na, B.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(&n_bad, d_bad, sizeof(n_bad), hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return fail(RT_E_HIP, "readback: %s", hipGetErrorString(e));
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return fail(RT_E_HIP, "synchronize: %s", hipGetErrorString(e));
+    if (n_bad) return fail(RT_E_ARG, "inputs hold %llu negative or non-finite values", n_bad);
+    *h_na = na;
+    return RT_OK;
+}
+
+// Device-to-host copy ordered on the caller's stream, then that stream synchronised.
+static rt_status copy_back(void* h, const void* d, size_t bytes, hipStream_t s)
+{
+    hipError_t e = hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(RT_E_HIP, "device-to-host copy: %s", hipGetErrorString(e));
+    return RT_OK;
+}
+
+static rt_status check_ws(const void* d_ws, size_t ws_bytes, size_t need, const char* who)
+{
+    if (!d_ws) return fail(RT_E_ARG, "%s: null workspace", who);
+    if ((uintptr_t)d_ws % 256 != 0) return fail(RT_E_ARG, "%s: workspace must be 256-byte aligned", who);
+    if (ws_bytes < need) return fail(RT_E_ARG, "%s: workspace of %zu bytes, %zu needed", who, ws_bytes, need);
+    return RT_OK;
 }
 
 extern "C" {
@@ -188,121 +296,92 @@ rt_status rt_scene_workspace_bytes(const rt_scene_desc* d, int64_t n_active, siz
     return RT_OK;
 }
 
-rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, void* stream, rt_scene** out)
+rt_status rt_scene_count_active(const rt_scene_desc* d, const rt_scene_inputs* inp, void* d_ws, size_t ws_bytes,
+                                void* stream, int64_t* h_n_active)
+{
+    g_err.clear();
+    if (!d || !inp || !h_n_active) return fail(RT_E_ARG, "null argument");
+    RT_TRY(check_desc(d, inp));
+    Geo g;
+    make_geo(d, g);
+    RT_TRY(check_ws(d_ws, ws_bytes, fixed_bytes(g), "rt_scene_count_active"));
+    Inputs in;
+    std::memset(&in, 0, sizeof(in));
+    bind_inputs(inp, g, in);
+    Carver c;
+    c.base = (char*)d_ws;
+    c.cap = ws_bytes;
+    SceneBufs B;
+    std::memset(&B, 0, sizeof(B));
+    unsigned long long* d_bad = nullptr;
+    carve_fixed(g, c, B, &d_bad);
+    int32_t na = 0;
+    RT_TRY(classify_blocks(d, g, in, B, d_bad, (hipStream_t)stream, &na));
+    *h_n_active = na;
+    return RT_OK;
+}
+
+rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, void* d_ws, size_t ws_bytes,
+                          void* stream, rt_scene** out)
 {
     g_err.clear();
     if (!d || !inp || !out) return fail(RT_E_ARG, "null argument");
     *out = nullptr;
     hipStream_t s = (hipStream_t)stream;
     RT_TRY(check_desc(d, inp));
-    const int log2B = ilog2(d->brick);
+    Geo g0;
+    make_geo(d, g0);
+    RT_TRY(check_ws(d_ws, ws_bytes, fixed_bytes(g0), "rt_scene_create"));
 
     rt_scene* sc = new (std::nothrow) rt_scene();
     if (!sc) return fail(RT_E_ARG, "out of host memory");
+    auto cleanup = [&](rt_status st) {
+        delete sc;
+        return st;
+    };
     sc->desc = *d;
+    sc->desc.h_lam = nullptr;  // the handle keeps its own copies
+    sc->desc.h_lam0 = nullptr;
     Geo& g = sc->g;
-    make_geo(d, g);
+    g = g0;
     if (d->model == RT_MODEL_LINES) {
         sc->lam.assign(d->h_lam, d->h_lam + d->n_lam);
         sc->lam0.assign(d->h_lam0, d->h_lam0 + d->n_lines);
     }
     Inputs& in = sc->in;
-    in.eta = inp->d_eta;
-    in.chi = inp->d_chi;
-    in.eta_star = inp->d_eta_star;
-    in.chi_star = inp->d_chi_star;
-    in.damp = inp->d_damp;
-    in.inv_dld = inp->d_inv_dld;
-    in.eta_bg = inp->d_eta_bg;
-    in.chi_bg = inp->d_chi_bg;
-    in.vel = inp->d_vel;
-    in.mask = inp->d_block_mask;
-    in.nvox = (long long)g.n[0] * g.n[1] * g.n[2];
-
-    // Morton order of all blocks (geometry only)
-    std::vector<std::pair<uint64_t, int32_t>> mo((size_t)g.nblocks);
-    for (long long b = 0; b < g.nblocks; ++b) {
-        uint32_t bc[3] = {(uint32_t)(b % g.nb[0]), (uint32_t)((b / g.nb[0]) % g.nb[1]),
-                          (uint32_t)(b / ((long long)g.nb[0] * g.nb[1]))};
-        uint64_t code = 0;
-        for (int bit = 0; bit < 21; ++bit)
-            for (int a = 0; a < g.dim; ++a) code |= (uint64_t)((bc[a] >> bit) & 1u) << (bit * g.dim + a);
-        mo[(size_t)b] = {code, (int32_t)b};
-    }
-    std::sort(mo.begin(), mo.end());
-    std::vector<int32_t> morton((size_t)g.nblocks);
-    for (size_t i = 0; i < mo.size(); ++i) morton[i] = mo[i].second;
-
+    std::memset(&in, 0, sizeof(in));
+    bind_inputs(inp, g, in);
     SceneBufs& B = sc->b;
     std::memset(&B, 0, sizeof(B));
-    auto cleanup = [&](rt_status st) {
-        delete sc;
-        return st;
-    };
-    rt_status st;
-    if ((st = sc->alloc(&B.morton, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.active, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.slot, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.active_list, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.n_active, 1)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.levels, (size_t)g.nblocks)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.states, (size_t)g.n_state_words)) != RT_OK) return cleanup(st);
-    if ((st = sc->alloc(&B.err, 4)) != RT_OK) return cleanup(st);
-    hipError_t e;
-    if ((e = hipMemcpyAsync(B.morton, morton.data(), morton.size() * sizeof(int32_t), hipMemcpyHostToDevice, s)) !=
-        hipSuccess)
-        return cleanup(fail(RT_E_HIP, "upload: %s", hipGetErrorString(e)));
-    // step-cap hits, first ray that hit the cap, probe indices outside the grid, unused
-    unsigned long long err0[4] = {0ull, ~0ull, 0ull, 0ull};
-    if ((e = hipMemcpyAsync(B.err, err0, sizeof(err0), hipMemcpyHostToDevice, s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "upload: %s", hipGetErrorString(e)));
+    Carver c;
+    c.base = (char*)d_ws;
+    c.cap = ws_bytes;
     unsigned long long* d_bad = nullptr;
-    if ((st = sc->alloc(&d_bad, 1)) != RT_OK) return cleanup(st);
-    if ((e = hipMemsetAsync(d_bad, 0, sizeof(unsigned long long), s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "clear: %s", hipGetErrorString(e)));
-    if ((e = launch_validate(in, d->model, d->n_lam, d->n_lines, d->dim, d_bad, s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "validate: %s", hipGetErrorString(e)));
-    if ((e = launch_classify(g, in, d->model, d->n_lam, d->n_lines, d->dense, B.active, s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "classify: %s", hipGetErrorString(e)));
-    if ((e = launch_slots(g, B.morton, B.active, B.slot, B.active_list, B.n_active, s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "slots: %s", hipGetErrorString(e)));
-    if ((e = launch_fill_levels(g, B.levels, s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "levels: %s", hipGetErrorString(e)));
+    carve_fixed(g, c, B, &d_bad);
     int32_t na = 0;
-    unsigned long long n_bad = 0;
-    if ((e = hipMemcpyAsync(&na, B.n_active, sizeof(int32_t), hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "readback: %s", hipGetErrorString(e)));
-    if ((e = hipMemcpyAsync(&n_bad, d_bad, sizeof(n_bad), hipMemcpyDeviceToHost, s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "readback: %s", hipGetErrorString(e)));
-    if ((e = hipStreamSynchronize(s)) != hipSuccess)
-        return cleanup(fail(RT_E_HIP, "synchronize: %s", hipGetErrorString(e)));
-    if (n_bad) return cleanup(fail(RT_E_ARG, "inputs hold %llu negative or non-finite values", n_bad));
+    rt_status st;
+    if ((st = classify_blocks(d, g, in, B, d_bad, s, &na)) != RT_OK) return cleanup(st);
     sc->n_active = na;
     const size_t cells = (size_t)na * g.cells;
-    {
-        size_t fcells = (size_t)na << (d->dim * (log2B - g.feat_level));
-        if ((st = sc->alloc(&B.fstats, fcells * kLam)) != RT_OK) return cleanup(st);
-    }
-    if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC) {
-        if ((st = sc->alloc((float**)&B.vals, cells * kLam * 2)) != RT_OK) return cleanup(st);
-    }
+    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP &&
+        cells * (size_t)d->n_v * kLam * 2 >= (size_t)1 << 31)  // per class, node offsets in the trace are 32-bit
+        return cleanup(fail(RT_E_UNSUPPORTED, "velocity-node storage of one direction class exceeds 2^31 floats"));
+    if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV &&
+        sizeof(double) * (size_t)(4 * d->n_lines + 2 + d->dim) * g.cells > 160 * 1024)
+        return cleanup(fail(RT_E_UNSUPPORTED, "too many lines for the LDS chain"));
+    const size_t need = scene_bytes(d, g, na);
+    if (ws_bytes < need)
+        return cleanup(fail(RT_E_ARG, "rt_scene_create: %d active blocks need a workspace of %zu bytes (got %zu)", na,
+                            need, ws_bytes));
+    carve_active(d, g, na, c, B);
+    sc->bytes = c.used;
+    hipError_t e;
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP) {
-        // per class, node offsets inside the trace kernels are 32-bit
-        if (cells * (size_t)d->n_v * kLam * 2 >= (size_t)1 << 31)
-            return cleanup(fail(RT_E_UNSUPPORTED, "velocity-node storage of one direction class exceeds 2^31 floats"));
-        const size_t nq = (size_t)vclasses(d);
-        if ((st = sc->alloc(&B.vgrid, nq * cells)) != RT_OK) return cleanup(st);
-        if ((st = sc->alloc(&B.vrange, nq * cells)) != RT_OK) return cleanup(st);
-        if ((st = sc->alloc(&B.vnodes, nq * cells * (size_t)d->n_v * kLam * 2)) != RT_OK) return cleanup(st);
-        if ((e = launch_vgrid(g, in, B, na, d->n_v, (int)nq, s)) != hipSuccess)
+        if ((e = launch_vgrid(g, in, B, na, d->n_v, vclasses(d), s)) != hipSuccess)
             return cleanup(fail(RT_E_HIP, "velocity grid: %s", hipGetErrorString(e)));
     }
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_CAV) {
         sc->cav_rec = cav_rec_floats(d->n_lines);
-        if ((st = sc->alloc(&B.cav, cells * (size_t)sc->cav_rec)) != RT_OK) return cleanup(st);
-        if ((st = sc->alloc((uint16_t**)&B.cav_lp, cells * (size_t)sc->cav_rec)) != RT_OK) return cleanup(st);
-        size_t shm = sizeof(double) * (size_t)(4 * d->n_lines + 2 + d->dim) * g.cells;
-        if (shm > 160 * 1024) return cleanup(fail(RT_E_UNSUPPORTED, "too many lines for the LDS chain"));
         if ((e = launch_cav_chain(g, in, B, na, d->n_lines, d->ds0, RT_AVG_LINEAR, s)) != hipSuccess)
             return cleanup(fail(RT_E_HIP, "core-and-voigt chain: %s", hipGetErrorString(e)));
         sc->cav_mode = RT_AVG_LINEAR;
@@ -310,6 +389,7 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     *out = sc;
     return RT_OK;
 }
+
 
 static LamBatch make_batch(const rt_scene* sc, int lam_begin, int lam_end)
 {
@@ -668,33 +748,28 @@ rt_status rt_scene_get_info(const rt_scene* sc, rt_scene_info* h)
     return RT_OK;
 }
 
-rt_status rt_scene_active_blocks(const rt_scene* sc, int32_t* h)
+rt_status rt_scene_active_blocks(const rt_scene* sc, int32_t* h, void* stream)
 {
     if (!sc || !h) return fail(RT_E_ARG, "null argument");
     if (sc->n_active == 0) return RT_OK;
-    RT_HIP(hipMemcpy(h, sc->b.active_list, sizeof(int32_t) * (size_t)sc->n_active, hipMemcpyDeviceToHost));
-    return RT_OK;
+    return copy_back(h, sc->b.active_list, sizeof(int32_t) * (size_t)sc->n_active, (hipStream_t)stream);
 }
 
-rt_status rt_scene_levels(const rt_scene* sc, int8_t* h)
+rt_status rt_scene_levels(const rt_scene* sc, int8_t* h, void* stream)
 {
     if (!sc || !h) return fail(RT_E_ARG, "null argument");
     if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
-    RT_HIP(hipDeviceSynchronize());
-    RT_HIP(hipMemcpy(h, sc->b.levels, (size_t)sc->g.nblocks, hipMemcpyDeviceToHost));
-    return RT_OK;
+    return copy_back(h, sc->b.levels, (size_t)sc->g.nblocks, (hipStream_t)stream);
 }
 
-rt_status rt_scene_states(const rt_scene* sc, uint64_t* h)
+rt_status rt_scene_states(const rt_scene* sc, uint64_t* h, void* stream)
 {
     if (!sc || !h) return fail(RT_E_ARG, "null argument");
     if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
-    RT_HIP(hipDeviceSynchronize());
-    RT_HIP(hipMemcpy(h, sc->b.states, sizeof(uint64_t) * (size_t)sc->g.n_state_words, hipMemcpyDeviceToHost));
-    return RT_OK;
+    return copy_back(h, sc->b.states, sizeof(uint64_t) * (size_t)sc->g.n_state_words, (hipStream_t)stream);
 }
 
-rt_status rt_scene_cell_values(const rt_scene* sc, int32_t n, const int32_t* h_cells, float* h_out)
+rt_status rt_scene_cell_values(const rt_scene* sc, int32_t n, const int32_t* h_cells, float* h_out, void* stream)
 {
     if (!sc || !h_cells || !h_out || n < 0) return fail(RT_E_ARG, "bad argument");
     if (sc->batch_begin < 0) return fail(RT_E_STATE, "no batch built");
@@ -714,9 +789,11 @@ rt_status rt_scene_cell_values(const rt_scene* sc, int32_t n, const int32_t* h_c
         (void)hipFree(dc);
         return fail(RT_E_HIP, "hipMalloc: %s", hipGetErrorString(e));
     }
-    e = hipMemcpy(dc, h_cells, sizeof(int32_t) * 4 * (size_t)n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_read_cells(sc->g, sc->b, sc->storage, n, dc, dout, 0);
-    if (e == hipSuccess) e = hipMemcpy(h_out, dout, sizeof(float) * 2 * kLam * (size_t)n, hipMemcpyDeviceToHost);
+    hipStream_t s = (hipStream_t)stream;
+    e = hipMemcpyAsync(dc, h_cells, sizeof(int32_t) * 4 * (size_t)n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_read_cells(sc->g, sc->b, sc->storage, n, dc, dout, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h_out, dout, sizeof(float) * 2 * kLam * (size_t)n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     (void)hipFree(dc);
     (void)hipFree(dout);
     if (e != hipSuccess) return fail(RT_E_HIP, "cell values: %s", hipGetErrorString(e));
@@ -741,12 +818,14 @@ rt_status rt_debug_visited(const rt_scene* sc, const rt_trace_params* p, int32_t
     if (e == hipSuccess) e = hipMalloc(&dn, sizeof(int32_t));
     float w[3] = {h_dir[0], sc->g.dim > 1 ? h_dir[1] : 0.f, sc->g.dim > 2 ? h_dir[2] : 0.f};
     if (e == hipSuccess) e = launch_debug_visited(t, probe_vox, w[0], w[1], w[2], cap, dc, dt, dn, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     int32_t n = 0;
-    if (e == hipSuccess) e = hipMemcpy(&n, dn, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpyAsync(&n, dn, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     int ncp = std::min(std::max(n, 0), cap);
-    if (e == hipSuccess && ncp > 0) e = hipMemcpy(h_cells, dc, sizeof(int32_t) * 4 * (size_t)ncp, hipMemcpyDeviceToHost);
-    if (e == hipSuccess && ncp > 0) e = hipMemcpy(h_t, dt, sizeof(double) * 2 * (size_t)ncp, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && ncp > 0)
+        e = hipMemcpyAsync(h_cells, dc, sizeof(int32_t) * 4 * (size_t)ncp, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess && ncp > 0) e = hipMemcpyAsync(h_t, dt, sizeof(double) * 2 * (size_t)ncp, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (dc) (void)hipFree(dc);
     if (dt) (void)hipFree(dt);
     if (dn) (void)hipFree(dn);
@@ -757,12 +836,11 @@ rt_status rt_debug_visited(const rt_scene* sc, const rt_trace_params* p, int32_t
     return RT_OK;
 }
 
-rt_status rt_scene_device_error(const rt_scene* sc, rt_device_err* h)
+rt_status rt_scene_device_error(const rt_scene* sc, rt_device_err* h, void* stream)
 {
     if (!sc || !h) return fail(RT_E_ARG, "null argument");
     unsigned long long v[4];
-    RT_HIP(hipDeviceSynchronize());
-    RT_HIP(hipMemcpy(v, sc->b.err, sizeof(v), hipMemcpyDeviceToHost));
+    RT_TRY(copy_back(v, sc->b.err, sizeof(v), (hipStream_t)stream));
     h->step_cap_hits = v[0];
     h->first_ray = v[0] ? (long long)v[1] : -1;
     h->bad_probes = v[2];
@@ -778,7 +856,7 @@ rt_status rt_scene_reset_device_error(rt_scene* sc, void* stream)
     return RT_OK;
 }
 
-void rt_scene_destroy(rt_scene* sc) { delete sc; }
+void rt_scene_destroy(rt_scene* sc) { delete sc; }  // the device memory is the caller's workspace
 
 }  // extern "C"
 
@@ -792,13 +870,14 @@ struct rt_batch {
     unsigned total_tiles = 0;
     int wg_waves = 4, n_wgs = 0, tiles_per_pop = 1;
     std::vector<BatchSeg> segs;  // one persistent launch per dimension present
-    ~rt_batch()
-    {
-        if (d_jobs) (void)hipFree(d_jobs);
-        if (counter) (void)hipFree(counter);
-        if (err) (void)hipFree(err);
-    }
 };
+
+// The batch's workspace: the job table, the queue counters (one per launch),
+// the error counters.
+static bool carve_batch(size_t n_jobs, Carver& c, BatchJob** jobs, unsigned** counter, unsigned long long** err)
+{
+    return c.take(jobs, n_jobs) && c.take(counter, 64) && c.take(err, 4);
+}
 
 struct rt_graph {
     hipGraph_t graph = nullptr;
@@ -815,12 +894,28 @@ static int device_cus()
 
 extern "C" {
 
-rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_batch_params* p, void* stream,
-                          rt_batch** out)
+rt_status rt_batch_workspace_bytes(int32_t n_jobs, size_t* h_bytes)
+{
+    g_err.clear();
+    if (!h_bytes || n_jobs < 1) return fail(RT_E_ARG, "need at least one job");
+    Carver c;
+    BatchJob* j;
+    unsigned* q;
+    unsigned long long* e;
+    carve_batch((size_t)n_jobs, c, &j, &q, &e);
+    *h_bytes = c.used;
+    return RT_OK;
+}
+
+rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_batch_params* p, void* d_ws,
+                          size_t ws_bytes, void* stream, rt_batch** out)
 {
     g_err.clear();
     if (!jobs || !out || n_jobs < 1) return fail(RT_E_ARG, "need at least one job");
     *out = nullptr;
+    size_t need = 0;
+    RT_TRY(rt_batch_workspace_bytes(n_jobs, &need));
+    RT_TRY(check_ws(d_ws, ws_bytes, need, "rt_batch_create"));
     rt_batch_params bp = p ? *p : rt_batch_params{0, 0, 0, 0, nullptr};
     int wg_waves = bp.wg_waves ? bp.wg_waves : 4;
     int wgs_per_cu = bp.wgs_per_cu ? bp.wgs_per_cu : 2;
@@ -903,12 +998,13 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
     bt->n_wgs = device_cus() * wgs_per_cu;
     bt->claims = bp.d_claims;
     hipStream_t s = (hipStream_t)stream;
-    hipError_t e = hipMalloc(&bt->d_jobs, sizeof(BatchJob) * bt->jobs.size());
-    if (e == hipSuccess) e = hipMalloc(&bt->counter, 256);
-    if (e == hipSuccess) e = hipMalloc(&bt->err, 256);
+    Carver c;
+    c.base = (char*)d_ws;
+    c.cap = ws_bytes;
+    carve_batch(bt->jobs.size(), c, &bt->d_jobs, &bt->counter, &bt->err);
     unsigned long long err0[2] = {0ull, ~0ull};
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(bt->d_jobs, bt->jobs.data(), sizeof(BatchJob) * bt->jobs.size(), hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(bt->d_jobs, bt->jobs.data(), sizeof(BatchJob) * bt->jobs.size(),
+                                  hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(bt->err, err0, sizeof(err0), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
@@ -934,22 +1030,21 @@ rt_status rt_batch_tiles(const rt_batch* bt, int64_t* h)
     return RT_OK;
 }
 
-rt_status rt_batch_device_error(const rt_batch* bt, rt_device_err* h)
+rt_status rt_batch_device_error(const rt_batch* bt, rt_device_err* h, void* stream)
 {
     if (!bt || !h) return fail(RT_E_ARG, "null argument");
     unsigned long long v[2];
-    RT_HIP(hipDeviceSynchronize());
-    RT_HIP(hipMemcpy(v, bt->err, sizeof(v), hipMemcpyDeviceToHost));
+    RT_TRY(copy_back(v, bt->err, sizeof(v), (hipStream_t)stream));
     h->step_cap_hits = v[0];
     h->first_ray = v[0] ? (long long)v[1] : -1;
     h->bad_probes = 0;  // batched jobs trace every probe of their scenes
     return RT_OK;
 }
 
-void rt_batch_destroy(rt_batch* bt) { delete bt; }
+void rt_batch_destroy(rt_batch* bt) { delete bt; }  // the device memory is the caller's workspace
 
-rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t reps, void* stream,
-                            rt_batch_params* best, float* best_ms)
+rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t reps, void* d_ws, size_t ws_bytes,
+                            void* stream, rt_batch_params* best, float* best_ms)
 {
     if (!jobs || !best || !best_ms || reps < 1) return fail(RT_E_ARG, "bad argument");
     hipStream_t s = (hipStream_t)stream;
@@ -967,7 +1062,7 @@ rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t re
             for (int q : pops) {
                 rt_batch_params p = {w, c, q, 0, nullptr};
                 rt_batch* bt = nullptr;
-                if ((st = rt_batch_create(jobs, n_jobs, &p, stream, &bt)) != RT_OK) goto done;
+                if ((st = rt_batch_create(jobs, n_jobs, &p, d_ws, ws_bytes, stream, &bt)) != RT_OK) goto done;
                 if ((st = rt_batch_run(bt, stream)) != RT_OK) {
                     rt_batch_destroy(bt);
                     goto done;

@@ -15,7 +15,9 @@
 // k-slots for A and B), and D[4 (i / 16) + j][i % 16], j = 0..3.
 #include <cmath>
 #include <cstring>
+#include <initializer_list>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "scene_impl.h"
@@ -542,23 +544,32 @@ struct rt_nrc {
     float* dH = nullptr;
     float* scratch = nullptr;
     float* loss_part = nullptr;
-    std::vector<void*> allocs;
-    ~rt_nrc()
-    {
-        for (void* p : allocs) (void)hipFree(p);
-    }
-    template <typename T>
-    hipError_t alloc(T** p, size_t n)
-    {
-        void* q = nullptr;
-        hipError_t e = hipMalloc(&q, std::max<size_t>(n * sizeof(T), 256));
-        if (e == hipSuccess) {
-            allocs.push_back(q);
-            *p = (T*)q;
-        }
-        return e;
-    }
 };
+
+// The cache's workspace in the order it is carved: FP32 master weights, Adam
+// moments, gradients, BF16 weights, then the training activations of a batch
+// of B rows (encoded inputs, pre-activations and activations of the 4 hidden
+// layers, output gradient, layer gradients), the split-K partials of the
+// weight gradients and the per-workgroup loss partials.
+static bool carve_nrc(rt_nrc* nn, size_t B, Carver& c)
+{
+    return c.take(&nn->w, kParamsPadded) && c.take(&nn->m, kParamsPadded) && c.take(&nn->v, kParamsPadded) &&
+           c.take(&nn->grad, kParamsPadded) && c.take(&nn->wb, kParamsPadded) && c.take(&nn->X, B * kFeat) &&
+           c.take(&nn->Z, 4 * B * kHid) && c.take(&nn->H, 4 * B * kHid) && c.take(&nn->dy, B) &&
+           c.take(&nn->dZ, B * kHid) && c.take(&nn->dH, B * kHid) && c.take(&nn->scratch, 64 * (size_t)kHid * kFeat) &&
+           c.take(&nn->loss_part, (size_t)nn->n_wgs);
+}
+
+// Device-to-host copies ordered on the caller's stream, then that stream synchronised.
+static hipError_t nrc_copy_back(hipStream_t s, std::initializer_list<std::pair<void*, const void*>> dst_src,
+                                size_t bytes)
+{
+    for (const auto& p : dst_src) {
+        hipError_t e = hipMemcpyAsync(p.first, p.second, bytes, hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipStreamSynchronize(s);
+}
 
 #define NRC_HIP(call)                                                                                      \
     do {                                                                                                   \
@@ -643,12 +654,13 @@ static hipError_t nrc_backward(rt_nrc* nn, long long rows, hipStream_t s)
     return hipGetLastError();
 }
 
-// Device bytes of the cache's buffers for a maximum batch B (the list rt_nrc_create allocates).
-static size_t nrc_bytes(size_t B, int n_wgs)
+// Workspace bytes of the cache for a maximum batch B (the carving above, dry run).
+static size_t nrc_bytes(size_t B)
 {
-    auto a = [](size_t count, size_t elem) { return std::max<size_t>(count * elem, 256); };
-    return 4 * a(kParamsPadded, 4) + a(kParamsPadded, 2) + a(B * kFeat, 2) + a(4 * B * kHid, 4) + a(4 * B * kHid, 2) +
-           a(B, 4) + a(B * kHid, 2) + a(B * kHid, 4) + a(64 * (size_t)kHid * kFeat, 4) + a((size_t)n_wgs, 4);
+    rt_nrc nn;
+    Carver c;
+    carve_nrc(&nn, B, c);
+    return c.used;
 }
 
 extern "C" {
@@ -658,7 +670,7 @@ rt_status rt_nrc_workspace_bytes(const rt_nrc_desc* d, size_t* h_bytes)
     if (!d || !h_bytes) return set_error(RT_E_ARG, "null argument");
     if (d->max_batch < 256 || d->max_batch % 256 != 0 || d->max_batch > (1 << 19))
         return set_error(RT_E_ARG, "max_batch must be a multiple of 256 in [256, 2^19]");
-    *h_bytes = nrc_bytes((size_t)d->max_batch, 512);
+    *h_bytes = nrc_bytes((size_t)d->max_batch);
     return RT_OK;
 }
 
@@ -669,38 +681,28 @@ rt_status rt_nrc_num_params(int32_t* n)
     return RT_OK;
 }
 
-rt_status rt_nrc_create(const rt_nrc_desc* d, void* stream, rt_nrc** out)
+rt_status rt_nrc_create(const rt_nrc_desc* d, void* d_ws, size_t ws_bytes, void* stream, rt_nrc** out)
 {
     if (!d || !out) return set_error(RT_E_ARG, "null argument");
     *out = nullptr;
     if (d->max_batch < 256 || d->max_batch % 256 != 0 || d->max_batch > (1 << 19))
         return set_error(RT_E_ARG, "max_batch must be a multiple of 256 in [256, 2^19]");
     if (!(d->freq_max >= 1.f)) return set_error(RT_E_ARG, "freq_max must be >= 1");
+    const size_t B = (size_t)d->max_batch;
+    const size_t need = nrc_bytes(B);
+    if (!d_ws) return set_error(RT_E_ARG, "rt_nrc_create: null workspace");
+    if ((uintptr_t)d_ws % 256 != 0) return set_error(RT_E_ARG, "rt_nrc_create: workspace must be 256-byte aligned");
+    if (ws_bytes < need) return set_error(RT_E_ARG, "rt_nrc_create: workspace of %zu bytes, %zu needed", ws_bytes, need);
     rt_nrc* nn = new (std::nothrow) rt_nrc();
     if (!nn) return set_error(RT_E_ARG, "out of host memory");
     nn->max_batch = d->max_batch;
     nn->lg2fmax = std::log2(d->freq_max);
     nn->seed = d->seed;
-    const size_t B = (size_t)d->max_batch;
+    Carver c;
+    c.base = (char*)d_ws;
+    c.cap = ws_bytes;
+    carve_nrc(nn, B, c);
     hipError_t e = hipSuccess;
-    auto A = [&](hipError_t x) { if (e == hipSuccess) e = x; };
-    A(nn->alloc(&nn->w, kParamsPadded));
-    A(nn->alloc(&nn->m, kParamsPadded));
-    A(nn->alloc(&nn->v, kParamsPadded));
-    A(nn->alloc(&nn->grad, kParamsPadded));
-    A(nn->alloc(&nn->wb, kParamsPadded));
-    A(nn->alloc(&nn->X, B * kFeat));
-    A(nn->alloc(&nn->Z, 4 * B * kHid));
-    A(nn->alloc(&nn->H, 4 * B * kHid));
-    A(nn->alloc(&nn->dy, B));
-    A(nn->alloc(&nn->dZ, B * kHid));
-    A(nn->alloc(&nn->dH, B * kHid));
-    A(nn->alloc(&nn->scratch, 64 * (size_t)kHid * kFeat));
-    A(nn->alloc(&nn->loss_part, (size_t)nn->n_wgs));
-    if (e != hipSuccess) {
-        delete nn;
-        return set_error(RT_E_HIP, "nrc allocation: %s", hipGetErrorString(e));
-    }
     // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) for every weight and bias (seeded splitmix64)
     std::vector<float> w0(kParamsPadded, 0.f);
     unsigned long long st = d->seed;
@@ -732,13 +734,12 @@ rt_status rt_nrc_create(const rt_nrc_desc* d, void* stream, rt_nrc** out)
     return RT_OK;
 }
 
-void rt_nrc_destroy(rt_nrc* nn) { delete nn; }
+void rt_nrc_destroy(rt_nrc* nn) { delete nn; }  // the device memory is the caller's workspace
 
-rt_status rt_nrc_get_weights(const rt_nrc* nn, float* h)
+rt_status rt_nrc_get_weights(const rt_nrc* nn, float* h, void* stream)
 {
     if (!nn || !h) return set_error(RT_E_ARG, "null argument");
-    NRC_HIP(hipDeviceSynchronize());
-    NRC_HIP(hipMemcpy(h, nn->w, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    NRC_HIP(nrc_copy_back((hipStream_t)stream, {{h, nn->w}}, sizeof(float) * kNParams));
     return RT_OK;
 }
 
@@ -753,13 +754,10 @@ rt_status rt_nrc_set_weights(rt_nrc* nn, const float* h, void* stream)
     return RT_OK;
 }
 
-rt_status rt_nrc_get_state(const rt_nrc* nn, float* h_w, float* h_m, float* h_v, int32_t* h_step)
+rt_status rt_nrc_get_state(const rt_nrc* nn, float* h_w, float* h_m, float* h_v, int32_t* h_step, void* stream)
 {
     if (!nn || !h_w || !h_m || !h_v || !h_step) return set_error(RT_E_ARG, "null argument");
-    NRC_HIP(hipDeviceSynchronize());
-    NRC_HIP(hipMemcpy(h_w, nn->w, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
-    NRC_HIP(hipMemcpy(h_m, nn->m, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
-    NRC_HIP(hipMemcpy(h_v, nn->v, sizeof(float) * kNParams, hipMemcpyDeviceToHost));
+    NRC_HIP(nrc_copy_back((hipStream_t)stream, {{h_w, nn->w}, {h_m, nn->m}, {h_v, nn->v}}, sizeof(float) * kNParams));
     *h_step = nn->step;
     return RT_OK;
 }
@@ -801,13 +799,12 @@ rt_status rt_nrc_train(rt_nrc* nn, const float* d_raw, const float* d_target, in
     return RT_OK;
 }
 
-rt_status rt_nrc_loss(const rt_nrc* nn, float* h_loss)
+rt_status rt_nrc_loss(const rt_nrc* nn, float* h_loss, void* stream)
 {
     if (!nn || !h_loss) return set_error(RT_E_ARG, "null argument");
     if (nn->last_rows == 0) return set_error(RT_E_STATE, "no training step yet");
     std::vector<float> part((size_t)nn->n_wgs);
-    NRC_HIP(hipDeviceSynchronize());
-    NRC_HIP(hipMemcpy(part.data(), nn->loss_part, sizeof(float) * part.size(), hipMemcpyDeviceToHost));
+    NRC_HIP(nrc_copy_back((hipStream_t)stream, {{part.data(), nn->loss_part}}, sizeof(float) * part.size()));
     double t = 0;
     for (float p : part) t += p;
     *h_loss = (float)(t / nn->last_rows);

@@ -14,6 +14,31 @@ namespace rt {
 rt_status set_error(rt_status st, const char* fmt, ...);
 }  // namespace rt
 
+namespace rt {
+// Sub-allocation of a caller-owned device workspace: pieces are taken in a
+// fixed order, each rounded up to 256 bytes (so every piece is 256-byte
+// aligned when the base is).  With a null base nothing is handed out and
+// `used` is the size the same sequence needs (the size queries run it so).
+struct Carver {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    template <typename T>
+    bool take(T** p, size_t count)
+    {
+        const size_t nbytes = ((std::max<size_t>(count * sizeof(T), 1) + 255) / 256) * 256;
+        if (base) {
+            if (used + nbytes > cap) return false;
+            *p = (T*)(base + used);
+        } else {
+            *p = nullptr;
+        }
+        used += nbytes;
+        return true;
+    }
+};
+}  // namespace rt
+
 struct rt_scene {
     rt_scene_desc desc;
     rt::Geo g;
@@ -22,32 +47,13 @@ struct rt_scene {
     int n_active = 0;
     std::vector<double> lam;
     std::vector<double> lam0;
-    std::vector<void*> allocs;
-    size_t bytes = 0;
+    size_t bytes = 0;  // workspace bytes the scene uses (from the caller's d_ws)
     int batch_begin = -1, batch_end = -1;
     int storage = RT_F32;
     int cav_rec = 0;
     int cav_lp_dtype = -1;  // dtype currently encoded in b.cav_lp (-1: none)
     int cav_mode = -1;      // rt_avg the Core-and-Voigt chain was built with (-1: none)
-
-    ~rt_scene()
-    {
-        for (void* p : allocs) (void)hipFree(p);
-    }
-    template <typename T>
-    rt_status alloc(T** p, size_t count)
-    {
-        size_t nbytes = std::max<size_t>(count * sizeof(T), 256);
-        void* q = nullptr;
-        hipError_t e = hipMalloc(&q, nbytes);
-        if (e != hipSuccess) return rt::set_error(RT_E_HIP, "hipMalloc(%zu) failed: %s", nbytes, hipGetErrorString(e));
-        allocs.push_back(q);
-        bytes += nbytes;
-        *p = (T*)q;
-        return RT_OK;
-    }
 };
-
 
 namespace rt {
 TraceLaunch make_trace(const rt_scene* sc, const rt_trace_params* p);

@@ -13,10 +13,11 @@ def rt():
 
 
 def _layout_bytes(nb, n_state_words, na, cells, feat_cells, n_lam_batch=8):
-    """Device layout of a static scene, each buffer at least 256 B: morton, active, slot, active list,
-    active count, levels, states, error counters, input-validation counter, level statistics
-    [na][feat cells][8] float4, values [na][cells][8][eta, chi] float."""
-    a = lambda n: max(n, 256)  # noqa: E731
+    """Device layout of a static scene in its workspace, each piece rounded up to a multiple of 256 B (so
+    every piece stays 256-byte aligned): morton, active, slot, active list, active count, levels, states,
+    error counters, input-validation counter, level statistics [na][feat cells][8] float4, values
+    [na][cells][8][eta, chi] float."""
+    a = lambda n: (max(n, 1) + 255) // 256 * 256  # noqa: E731
     return (a(4 * nb) + a(nb) + a(4 * nb) + a(4 * nb) + a(4) + a(nb) + a(8 * n_state_words) + a(32) + a(8)
             + a(16 * na * feat_cells * n_lam_batch) + a(4 * 2 * n_lam_batch * na * cells))
 
@@ -79,3 +80,31 @@ def test_velocity_grid_ratio():
     np.testing.assert_allclose(r, [1.5 * np.sqrt(2.0), 0.15 * np.sqrt(2.0)], rtol=1e-5)
     for vg in ("full", "orthant"):
         assert np.all(rt.velocity_grid_ratio(np.zeros((2, nvox), np.float32), idl, lam0, 21, vgrid=vg) == 0)
+
+
+def test_create_refuses_a_bad_workspace(rt):
+    """Scene creation takes a caller-owned workspace: a null, misaligned or too small one is refused on the
+    host before any device work (the input pointers are never dereferenced here)."""
+    import ctypes
+    sc = make_cfg1()
+    d, _, _ = rt._scene_desc(sc["dim"], sc["n"], sc["brick"], sc["n_levels"], "static", "static", "gauss", 21,
+                             False, 1.0, 16, None, None)
+    inp = rt.RtSceneInputs()
+    inp.d_eta, inp.d_chi = 0x100000, 0x200000  # not dereferenced: the workspace check comes first
+    need = ctypes.c_size_t(0)
+    rt._check(rt.lib().rt_scene_workspace_bytes(ctypes.byref(d), 0, ctypes.byref(need)))
+    na = ctypes.c_int64(-1)
+    h = ctypes.c_void_p()
+    for ws, nbytes, msg in ((None, need.value, b"null workspace"), (0x300010, need.value, b"aligned"),
+                            (0x300000, 256, b"needed")):
+        st = rt.lib().rt_scene_count_active(ctypes.byref(d), ctypes.byref(inp), ws, nbytes, None, ctypes.byref(na))
+        assert st == rt.RT_E_ARG and msg in rt.lib().rt_last_error(), rt.lib().rt_last_error()
+        st = rt.lib().rt_scene_create(ctypes.byref(d), ctypes.byref(inp), ws, nbytes, None, ctypes.byref(h))
+        assert st == rt.RT_E_ARG and msg in rt.lib().rt_last_error()
+    assert na.value == -1 and not h.value
+    for bad in (0, -1):
+        v = ctypes.c_size_t(0)
+        assert rt.lib().rt_batch_workspace_bytes(bad, ctypes.byref(v)) == rt.RT_E_ARG
+    v = ctypes.c_size_t(0)
+    rt._check(rt.lib().rt_batch_workspace_bytes(3, ctypes.byref(v)))
+    assert v.value % 256 == 0 and v.value >= 3 * 64
