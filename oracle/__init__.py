@@ -24,6 +24,12 @@ Parity status per function (pins live in tests/test_oracle_*.py):
                             mean velocity vbar, the node frame and the orthant
                             ranges of both grid modes)
   march (cav)               pinned: level 0 equals Classic; CaV wavelength scalings
+  prefilter / march (PREFILTER)  pinned: homogeneous field is its own prefilter;
+                            the worked example's voxel pair reproduces the
+                            two-slab solution in each propagation order; axis
+                            rays through a stratified merged block equal the
+                            MIP-0 march (2D, 3D, both signs); all levels 0 =
+                            static march bit for bit
   VLM approximation error   parity unpinned (no closed form; judged against
                             the dense march at the p99.9 bound)
 """
@@ -37,7 +43,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
-STATIC, CLASSIC, VELINTERP, CAV = 0, 1, 2, 3
+STATIC, CLASSIC, VELINTERP, CAV, PREFILTER = 0, 1, 2, 3, 4
 GAUSS, VOIGT = 0, 1
 AVG_LOG, AVG_LINEAR = 0, 1
 VGRID = {"full": 0, "orthant": 1}
@@ -53,7 +59,7 @@ class OrcScene(ctypes.Structure):
         ("grade_mode", ctypes.c_int32), ("ds0", ctypes.c_double), ("I0", ctypes.c_double),
         ("st_eta", _P), ("st_chi", _P), ("lam", _P), ("lam0", _P), ("eta_star", _P),
         ("chi_star", _P), ("damp", _P), ("inv_dld", _P), ("eta_bg", _P), ("chi_bg", _P),
-        ("vel", _P), ("level_dist", _P), ("vgrid_mode", ctypes.c_int32),
+        ("vel", _P), ("level_dist", _P), ("vgrid_mode", ctypes.c_int32), ("pf_eta", _P), ("pf_chi", _P),
     ]
 
 
@@ -83,6 +89,8 @@ def lib():
         L.orc_lines_mip0.argtypes = [_P, ctypes.c_int, ctypes.c_int, _P, _P]
         L.orc_levels.restype = ctypes.c_int64
         L.orc_levels.argtypes = [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, _P, _P, _P]
+        L.orc_prefilter.restype = None
+        L.orc_prefilter.argtypes = [_P, _P, _P, _P, _P]
         L.orc_march.restype = ctypes.c_int
         L.orc_march.argtypes = [_P, ctypes.c_int32, _P, _P, ctypes.c_int64, _P, _P, _P, ctypes.c_int32, _P]
         L.orc_march_interval.restype = ctypes.c_int
@@ -163,6 +171,15 @@ class Scene:
         self._keep["st_eta"], self._keep["st_chi"] = st_eta, st_chi
         self.s.st_eta, self.s.st_chi = _ptr(st_eta), _ptr(st_chi)
         self.s.n_lam = st_eta.shape[0]
+
+    def set_prefilter(self, pf_eta, pf_chi):
+        """Prefiltered level cells [n_lam][level_total][2 dim] FP64 (levels >= 1 read by the PREFILTER march,
+        which takes level 0 from set_static_levels)."""
+        pf_eta = _c(pf_eta, np.float64)
+        pf_chi = _c(pf_chi, np.float64)
+        assert pf_eta.shape == pf_chi.shape and pf_eta.shape[1:] == (self.level_total, 2 * self.dim)
+        self._keep["pf_eta"], self._keep["pf_chi"] = pf_eta, pf_chi
+        self.s.pf_eta, self.s.pf_chi = _ptr(pf_eta), _ptr(pf_chi)
 
     @property
     def ref(self):
@@ -316,6 +333,23 @@ def static_level_values(scene: Scene, eta, chi, block_active, T, tau_thin=0.25, 
         st_e[il], st_c[il] = oe, oc
         lvs.append(lv)
     return lvs, st_e, st_c
+
+
+def prefilter_values(scene: Scene, eta, chi):
+    """Prefiltered cells (Sect. 5.1) of every level for each wavelength of [n_lam][nvox] MIP-0 values:
+    equivalent eta, chi per signed axis, [n_lam][level_total][2 dim]."""
+    nl = eta.shape[0]
+    K = 2 * scene.dim
+    pe = np.zeros((nl, scene.level_total, K))
+    pc = np.zeros((nl, scene.level_total, K))
+    for il in range(nl):
+        e = _c(eta[il], np.float64)
+        c = _c(chi[il], np.float64)
+        oe = np.zeros((scene.level_total, K))
+        oc = np.zeros((scene.level_total, K))
+        lib().orc_prefilter(scene.ref, _ptr(e), _ptr(c), _ptr(oe), _ptr(oc))
+        pe[il], pc[il] = oe, oc
+    return pe, pc
 
 
 # ----------------------------------------------------------------------

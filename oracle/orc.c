@@ -38,6 +38,14 @@
  *                     started from 0 (or from I0 when the ray leaves the
  *                     grid inside the interval), plus the interval's
  *                     transmittance T = prod exp(-tau).
+ *   orc_prefilter     prefiltered level cells (Sect. 5.1: the transfer
+ *                     equation precomputed along the +-x, y, z axes and
+ *                     interpolated between these): for every merged cell and
+ *                     signed axis, the exact transfer (I, T) of each MIP-0 row
+ *                     of the cell along that axis, averaged over the rows, and
+ *                     the homogeneous cell with the same (I, T) over the
+ *                     cell's side; the march blends the axes of a ray's
+ *                     direction with weights w_a^2.
  *   orc_voigt_h       H(a,x) = Re w(x + i a) by Weideman's rational series
  *                     with N = 64 terms in FP64 (an independent method from
  *                     the single-precision profile of the GPU path).
@@ -56,7 +64,7 @@
 /* ------------------------------------------------------------------ */
 /* scene description                                                   */
 /* ------------------------------------------------------------------ */
-enum { ORC_STATIC = 0, ORC_CLASSIC = 1, ORC_VELINTERP = 2, ORC_CAV = 3 };
+enum { ORC_STATIC = 0, ORC_CLASSIC = 1, ORC_VELINTERP = 2, ORC_CAV = 3, ORC_PREFILTER = 4 };
 enum { ORC_GAUSS = 0, ORC_VOIGT = 1 };
 enum { ORC_AVG_LOG = 0, ORC_AVG_LINEAR = 1 };
 enum { ORC_GRADE_ENTRY = 0, ORC_GRADE_PATH = 1 };
@@ -95,6 +103,10 @@ typedef struct orc_scene {
      * for every direction) or ORC_VGRID_ORTHANT (one grid per orthant of
      * directions, over the projections reachable from it) */
     int32_t vgrid_mode;
+    /* prefiltered cells: [n_lam][level_total][2 dim] equivalent eta, chi per
+     * signed axis k = 2 a + (propagation towards -a); levels >= 1 are read */
+    const double* pf_eta;
+    const double* pf_chi;
 } orc_scene;
 
 static int64_t nvox_of(const orc_scene* s) { return (int64_t)s->n[0] * s->n[1] * s->n[2]; }
@@ -809,6 +821,108 @@ static void cell_cav(const orc_scene* s, const int32_t c[3], int size, const dou
 /* ------------------------------------------------------------------ */
 /* the march                                                           */
 /* ------------------------------------------------------------------ */
+/* ------------------------------------------------------------------ */
+/* prefiltering (Sect. 5.1)                                            */
+/* ------------------------------------------------------------------ */
+/*
+ * Prefiltered values of every cell of every level for one wavelength, from
+ * the MIP-0 values eta0, chi0 [nvox].  For a level-m cell (side 2^m voxels)
+ * and a signed axis (a, sign), radiation propagating along sign * e_a crosses
+ * the cell along each of its (2^m)^(D-1) rows of MIP-0 voxels parallel to a.
+ * Each row is solved exactly, voxel by voxel in the direction of propagation,
+ * from I = 0 at its entry face: I <- I exp(-tau) + S (1 - exp(-tau)),
+ * tau = chi ds0, and T_row = exp(-sum tau).  The cell's beam-averaged
+ * transfer is Ibar = mean_rows I_row and 1 - Tbar = mean_rows (1 - T_row).
+ * The equivalent homogeneous cell of side L = 2^m ds0 has the same transfer:
+ * tau_eff = -ln(Tbar), chi_eff = tau_eff / L and, since its emergent
+ * intensity is S_eff (1 - Tbar), eta_eff = S_eff chi_eff =
+ * Ibar tau_eff / ((1 - Tbar) L), or Ibar / L when Tbar = 1.  Output index:
+ * (level offset + cell) * 2D + k, k = 2 a + (sign < 0).  Empty (inactive)
+ * regions give zeros like the other level values.
+ */
+void orc_prefilter(const orc_scene* s, const double* eta0, const double* chi0, double* pf_eta, double* pf_chi)
+{
+    const int D = s->dim;
+    const int K = 2 * D;
+    for (int m = 0; m < s->n_levels; ++m) {
+        const int side = 1 << m;
+        const int32_t nc[3] = {s->n[0] >> m, D > 1 ? s->n[1] >> m : 1, D > 2 ? s->n[2] >> m : 1};
+        const int64_t off = level_offset(s, m);
+        for (int32_t cz = 0; cz < nc[2]; ++cz)
+            for (int32_t cy = 0; cy < nc[1]; ++cy)
+                for (int32_t cx = 0; cx < nc[0]; ++cx) {
+                    const int32_t corner[3] = {cx * side, cy * side, cz * side};
+                    const int64_t ci = cx + (int64_t)nc[0] * (cy + (int64_t)nc[1] * cz);
+                    for (int a = 0; a < D; ++a)
+                        for (int neg = 0; neg < 2; ++neg) {
+                            /* the two axes across the rows (unused ones have extent 1) */
+                            int b0 = -1, b1 = -1;
+                            for (int b = 0; b < D; ++b)
+                                if (b != a) {
+                                    if (b0 < 0) b0 = b;
+                                    else b1 = b;
+                                }
+                            const int e0 = b0 >= 0 ? side : 1, e1 = b1 >= 0 ? side : 1;
+                            double sumI = 0.0, sumA = 0.0;
+                            for (int r1 = 0; r1 < e1; ++r1)
+                                for (int r0 = 0; r0 < e0; ++r0) {
+                                    double I = 0.0, tau_row = 0.0;
+                                    for (int j = 0; j < side; ++j) {
+                                        int32_t c[3] = {corner[0], corner[1], corner[2]};
+                                        if (b0 >= 0) c[b0] += r0;
+                                        if (b1 >= 0) c[b1] += r1;
+                                        c[a] += neg ? side - 1 - j : j; /* entry face first */
+                                        const int64_t v = vox_index(s, c);
+                                        const double tau = chi0[v] * s->ds0;
+                                        if (tau == 0.0) {
+                                            I += eta0[v] * s->ds0;
+                                        } else {
+                                            I = I * exp(-tau) + (eta0[v] / chi0[v]) * (-expm1(-tau));
+                                        }
+                                        tau_row += tau;
+                                    }
+                                    sumI += I;
+                                    sumA += -expm1(-tau_row);
+                                }
+                            const double rows = (double)e0 * (double)e1;
+                            const double Ibar = sumI / rows, absorbed = sumA / rows;
+                            const double L = side * s->ds0;
+                            double ce = 0.0, ee = 0.0;
+                            if (absorbed > 0.0) {
+                                const double tau_eff = -log1p(-absorbed);
+                                ce = tau_eff / L;
+                                ee = Ibar * tau_eff / (absorbed * L);
+                            } else {
+                                ee = Ibar / L;
+                            }
+                            const int k = 2 * a + neg;
+                            pf_eta[(off + ci) * K + k] = ee;
+                            pf_chi[(off + ci) * K + k] = ce;
+                        }
+                }
+    }
+}
+
+/* Direction blend of a prefiltered cell: weights w_a^2 over the signed axes the
+ * ray propagates along (normalised by their sum). */
+static void cell_prefilter(const orc_scene* s, int il, int m, const int32_t c[3], const double* wd, double* eta,
+                           double* chi)
+{
+    const int D = s->dim, K = 2 * D;
+    const int64_t tot = orc_level_total(D, s->n, s->n_levels);
+    const int64_t o = ((int64_t)il * tot + level_offset(s, m) + level_index(s, m, c)) * K;
+    double e = 0.0, x = 0.0, ws = 0.0;
+    for (int a = 0; a < D; ++a) {
+        const double wa = wd[a] * wd[a];
+        const int k = 2 * a + (wd[a] < 0.0);
+        e += wa * s->pf_eta[o + k];
+        x += wa * s->pf_chi[o + k];
+        ws += wa;
+    }
+    *eta = e / ws;
+    *chi = x / ws;
+}
+
 /*
  * For each ray r (probe voxel ray_vox[r], direction dirs[ray_dir[r]]) and each
  * wavelength il: I_out[r * n_lam + il] over the path interval [t1, t2] of the
@@ -893,10 +1007,12 @@ static int march_rays(const orc_scene* s, int32_t emis, const int8_t* levels, co
                     const int32_t* c = cell + 3 * i;
                     int m = lv[i], size = 1 << m;
                     double e = 0.0, x = 0.0;
-                    if (emis == ORC_STATIC) {
+                    if (emis == ORC_STATIC || (emis == ORC_PREFILTER && m == 0)) {
                         int64_t o = (int64_t)il * tot + level_offset(s, m) + level_index(s, m, c);
                         e = s->st_eta[o];
                         x = s->st_chi[o];
+                    } else if (emis == ORC_PREFILTER) {
+                        cell_prefilter(s, il, m, c, wd, &e, &x);
                     } else if (emis == ORC_CLASSIC) {
                         double u = 0.0;
                         int64_t vv = vox_index(s, c);
