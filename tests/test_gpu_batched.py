@@ -4,10 +4,16 @@ Per-scene outputs of the persistent work-stealing kernel must equal the
 single-scene launches bit for bit, every 64-probe tile must be claimed
 exactly once, other launch shapes must give the same bits, graph replays
 must match the eager result, and the autotuner must return a valid shape.
+The kernels the batched workload runs (line model evaluated at rest and
+stored as static emission, BF16 storage, 2D and 3D, path-graded levels) are
+checked against the FP64 oracle on the same adapted cells, with the BF16
+rounding of the stored level values emulated on the oracle's side.
 """
 import numpy as np
 import pytest
 
+import oracle as orc
+from oracle.nrc import bf16_round
 from synth import cfg4_specs, make_cfg4_scene
 
 pytestmark = pytest.mark.gpu
@@ -156,3 +162,51 @@ def test_cfg4_specs_shapes():
     assert sum(s["dim"] == 2 for s in specs) == 24
     assert all(64 <= s["N"] <= 1024 for s in specs if s["dim"] == 2)
     assert all(64 <= s["N"] <= 192 for s in specs if s["dim"] == 3)
+
+
+def oracle_static_bf16(sc, lam_idx, T, lv_gpu):
+    """Oracle side of a line-model scene stored as static emission in BF16: MIP-0 values at rest (FP64), the
+    level chain and per-wavelength levels (their batch minimum must equal the device's map: Gaussian lines,
+    FP64 statistics in the same order), then the stored level values rounded as the device stores them
+    (FP64 -> FP32 -> BF16, ties to even)."""
+    s = orc.Scene(sc, lam_idx=lam_idx)
+    E = np.zeros((len(lam_idx), s.nvox))
+    C = np.zeros_like(E)
+    for il in range(len(lam_idx)):
+        E[il], C[il] = orc.lines_mip0(s, il, 0)
+    lvs, st_e, st_c = orc.static_level_values(s, E, C, sc["block_active"], T)
+    lv = orc.batch_levels(lvs)
+    assert np.array_equal(lv, lv_gpu), "level maps differ: blocks %s" % np.nonzero(lv != lv_gpu)[0][:8]
+    s.set_static_levels(bf16_round(st_e), bf16_round(st_c))
+    return s, lv
+
+
+@pytest.mark.parametrize("batch", [0, 1])
+def test_batched_workload_kernels_match_oracle(rt, scenes, batch):
+    """Every scene of the small uneven batch (2D and 3D, 2-5 levels), path-graded VLM, BF16 storage: the
+    persistent launch gives the single-scene bits, and both match the FP64 oracle marching the same levels and
+    the same BF16-rounded values to FP32 accumulation (relative error < 2e-5 on sampled rays)."""
+    import torch
+    T = 1e-2
+    for _, s, _ in scenes:
+        s.build(8 * batch, 8 * batch + 8, iod_threshold=T, storage="bf16")
+    ref = eager(scenes, rt.CASCADE_LEVEL_DIST, "path")
+    outs = [torch.full_like(r, float("nan")) for r in ref]
+    b = rt.Batch(jobs_for(scenes, outs, rt.CASCADE_LEVEL_DIST, "path"))
+    b.run()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(41 + batch)
+    for (sc, s, d), r, o in zip(scenes, ref, outs):
+        assert torch.equal(r, o)
+        print("scene %s: %dD N=%d L=%d" % (sc["name"], sc["dim"], sc["n"][0], sc["n_levels"]), flush=True)
+        os_, lv = oracle_static_bf16(sc, list(range(8 * batch, 8 * batch + 8)), T, s.levels())
+        os_.set_level_dist(rt.CASCADE_LEVEL_DIST, "path")
+        probes = s.probe_voxels()
+        k = rng.choice(probes.size, min(512, probes.size), replace=False)
+        dd = rng.integers(0, d.shape[0], k.size).astype(np.int32)
+        want = orc.march(os_, orc.STATIC, lv, probes[k], dd)
+        got = o.cpu().numpy()[dd, :, k]
+        st = orc.rel_err_stats(got, want)
+        assert st["n_ref_zero_mismatch"] == 0 and st["p100"] < 2e-5, (sc["name"], st)
+    for _, s, _ in scenes:  # leave the module's scenes on batch 0 as the fixture built them
+        s.build(0, 8, iod_threshold=T, storage="bf16")

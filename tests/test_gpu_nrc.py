@@ -187,9 +187,14 @@ def test_gradients_match_oracle(rt):
     p = _emulated_params(nn.get_weights())
     X = onrc.encode(raw[:, :11].astype(np.float64), 16.0)
     g_ref = onrc.gradients(p, X, tgt.astype(np.float64), raw[:, 11].astype(np.float64), onrc.bf16_round)
+    rel = {}
     for k, (o, n) in onrc.OFF.items():
         a, b = g[o:o + n], g_ref[o:o + n]
-        assert np.linalg.norm(a - b) <= 3e-2 * np.linalg.norm(b) + 1e-7, k
+        rel[k] = np.linalg.norm(a - b) / (np.linalg.norm(b) + 1e-30)
+    print("gradient relative L2 error per tensor:", {k: "%.2e" % v for k, v in rel.items()})
+    for k, (o, n) in onrc.OFF.items():
+        a, b = g[o:o + n], g_ref[o:o + n]
+        assert np.linalg.norm(a - b) <= 1e-2 * np.linalg.norm(b) + 1e-7, (k, rel)
 
 
 def test_checkpoint_resume_is_bit_exact(rt, tmp_path):
