@@ -836,7 +836,12 @@ static void cell_cav(const orc_scene* s, const int32_t c[3], int size, const dou
  * The equivalent homogeneous cell of side L = 2^m ds0 has the same transfer:
  * tau_eff = -ln(Tbar), chi_eff = tau_eff / L and, since its emergent
  * intensity is S_eff (1 - Tbar), eta_eff = S_eff chi_eff =
- * Ibar tau_eff / ((1 - Tbar) L), or Ibar / L when Tbar = 1.  Output index:
+ * Ibar tau_eff / ((1 - Tbar) L), or Ibar / L when Tbar = 1.  Tbar = mean T_row
+ * and 1 - Tbar = mean (1 - T_row) are summed separately (no cancellation at
+ * either end); tau_eff = -ln(1 - (1 - Tbar)) while 1 - Tbar < 1/2, -ln(Tbar)
+ * beyond, and, when every row is opaque enough for T_row to underflow
+ * (Tbar = 0), the mean row optical depth (any such cell transmits nothing).
+ * Output index:
  * (level offset + cell) * 2D + k, k = 2 a + (sign < 0).  Empty (inactive)
  * regions give zeros like the other level values.
  */
@@ -863,7 +868,7 @@ void orc_prefilter(const orc_scene* s, const double* eta0, const double* chi0, d
                                     else b1 = b;
                                 }
                             const int e0 = b0 >= 0 ? side : 1, e1 = b1 >= 0 ? side : 1;
-                            double sumI = 0.0, sumA = 0.0;
+                            double sumI = 0.0, sumA = 0.0, sumT = 0.0, sumTau = 0.0;
                             for (int r1 = 0; r1 < e1; ++r1)
                                 for (int r0 = 0; r0 < e0; ++r0) {
                                     double I = 0.0, tau_row = 0.0;
@@ -883,13 +888,16 @@ void orc_prefilter(const orc_scene* s, const double* eta0, const double* chi0, d
                                     }
                                     sumI += I;
                                     sumA += -expm1(-tau_row);
+                                    sumT += exp(-tau_row);
+                                    sumTau += tau_row;
                                 }
                             const double rows = (double)e0 * (double)e1;
-                            const double Ibar = sumI / rows, absorbed = sumA / rows;
+                            const double Ibar = sumI / rows, absorbed = sumA / rows, Tbar = sumT / rows;
                             const double L = side * s->ds0;
                             double ce = 0.0, ee = 0.0;
                             if (absorbed > 0.0) {
-                                const double tau_eff = -log1p(-absorbed);
+                                const double tau_eff = absorbed < 0.5 ? -log1p(-absorbed)
+                                                       : (Tbar > 0.0 ? -log(Tbar) : sumTau / rows);
                                 ce = tau_eff / L;
                                 ee = Ibar * tau_eff / (absorbed * L);
                             } else {

@@ -8,7 +8,9 @@ interpolated between them by direction).
   * a merged block stratified along one axis, crossed whole by an axis-aligned ray: the prefiltered march
     equals the MIP-0 march (the beam average is exact when every row is the same), for both signs of the
     axis, in 2D and 3D (along z);
-  * all levels 0: the prefiltered march is the static march bit for bit.
+  * all levels 0: the prefiltered march is the static march bit for bit;
+  * an opaque cell (every row's transmittance underflows) stays finite and, crossed whole along an axis,
+    still equals the MIP-0 march (whose last voxel's source function it returns);
 A wrong propagation order, a transposed axis, a missing row average or a wrong equivalent emissivity fails one
 of them.
 """
@@ -157,3 +159,30 @@ def test_level0_prefilter_march_is_static_march(orc):
     vox = vox[act[(vox % 32) // 8 + 4 * ((vox // 32) // 8)] > 0]
     d = rng.integers(0, 7, vox.size).astype(np.int32)
     assert np.array_equal(orc.march(s, orc.PREFILTER, lv, vox, d), orc.march(s, orc.STATIC, lv, vox, d))
+
+
+def test_opaque_cells_stay_finite_and_exact_along_axes(orc):
+    """chi = 100 per voxel: rows of 8 voxels have tau = 800 and T_row = 0 in FP64.  The equivalent cell is finite,
+    and an axis ray crossing the merged block whole returns what the MIP-0 march returns."""
+    B = 8
+    n = (B, 2 * B)
+    eta, chi = stratified(2, list(n), 1, 21)
+    chi *= 100.0 / chi.min()
+    eta *= 100.0 / eta.min()
+    thin = np.arange(n[0] * n[1]) >= n[0] * B  # block 1 (y >= B), which holds the probes, stays optically thin
+    chi[:, thin] *= 1e-4
+    dirs = np.array([[0.0, 1.0], [0.0, -1.0], [0.6, 0.8]], np.float32)
+    sc = scene_dict(2, n, B, 4, eta, chi, dirs, np.ones(2, np.uint8))
+    s = orc.Scene(sc)
+    _, st_e, st_c = orc.static_level_values(s, eta, chi, sc["block_active"], T=1e-2)
+    pe, pc = orc.prefilter_values(s, eta, chi)
+    assert np.all(np.isfinite(pe)) and np.all(np.isfinite(pc)) and np.all(pc > 0)
+    s.set_static_levels(st_e, st_c)
+    s.set_prefilter(pe, pc)
+    lv = np.array([3, 0], np.int8)
+    probes = np.array([9 * B + 3, 12 * B + 5], np.int32)
+    ref = orc.march(s, orc.STATIC, np.zeros(2, np.int8), probes, np.zeros(2, np.int32))
+    got = orc.march(s, orc.PREFILTER, lv, probes, np.zeros(2, np.int32))
+    np.testing.assert_allclose(got, ref, rtol=1e-12)
+    got2 = orc.march(s, orc.PREFILTER, lv, probes, np.full(2, 2, np.int32))
+    assert np.all(np.isfinite(got2))
