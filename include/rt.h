@@ -77,10 +77,21 @@ typedef enum rt_profile {
     RT_PROFILE_VOIGT = 1  /* H(a,x)/(sqrt(pi) dlD) with Sect. 3.2.1 wavelength scalings */
 } rt_profile;
 
+/* PREFILTER (Sect. 5.1, prefiltering: the transfer equation precomputed along
+ * the +-x, y, z axes and interpolated between them) is static emission whose
+ * merged cells (levels >= 1) also store, per signed axis, the homogeneous cell
+ * with the same transfer as the cell's MIP-0 voxels: the exact row transfer
+ * (I, T) along that axis averaged over the cell's rows, tau_eff = -ln(Tbar),
+ * chi_eff = tau_eff / side, eta_eff = Ibar tau_eff / ((1 - Tbar) side)
+ * (Ibar / side when Tbar = 1), computed in FP64 from the MIP-0 values.  A ray
+ * of direction w blends the axes it propagates along with weights w_a^2 / sum;
+ * level 0 uses the stored MIP-0 values.  2 dim times the stored-value storage
+ * of the merged levels. */
 typedef enum rt_emission {
     RT_EMIS_STATIC = 0,    /* stored eta, chi per wavelength (lines model: evaluated at rest, u = 0) */
     RT_EMIS_VELINTERP = 1, /* velocity-grid interpolation (Sect. 3.1), lines model only */
-    RT_EMIS_CAV = 2        /* Core and Voigt (Sect. 3.2): profile evaluated on the fly, lines model only */
+    RT_EMIS_CAV = 2,       /* Core and Voigt (Sect. 3.2): profile evaluated on the fly, lines model only */
+    RT_EMIS_PREFILTER = 3  /* static emission with prefiltered merged cells (Sect. 5.1); both models */
 } rt_emission;
 
 /* Stored level values.  LINEAR is the box filter of Sect. 2.1 and the one the

@@ -21,7 +21,7 @@ LAM_BATCH = 8
 MAX_LINES = 4
 MODEL = {"static": 0, "lines": 1}
 PROFILE = {"gauss": 0, "voigt": 1}
-EMISSION = {"static": 0, "velinterp": 1, "cav": 2}
+EMISSION = {"static": 0, "velinterp": 1, "cav": 2, "prefilter": 3}
 AVG = {"log": 0, "linear": 1}
 DTYPE = {"f32": 0, "bf16": 1, "f16": 2}
 MODE = {"level0": 0, "vlm": 1}
@@ -226,7 +226,7 @@ def scene_workspace_bytes(sc, n_active=None, emission=None, n_v=21, dense=False,
     """Device bytes a scene made from the synthetic scene dict `sc` holds (host only; n_active
     defaults to the dict's active-block count, or every block when dense)."""
     model = sc["model"]
-    emis = "static" if model == "static" else (emission or "static")
+    emis = emission or "static"
     d, lam, lam0 = _scene_desc(sc["dim"], sc["n"], sc["brick"], sc["n_levels"], model, emis,
                                sc.get("profile", "gauss"), n_v, dense, sc.get("ds0", 1.0),
                                sc["eta"].shape[0] if model == "static" else None, sc.get("lam"), sc.get("lam0"),
@@ -345,7 +345,7 @@ class Scene:
         args = dict(dim=sc["dim"], n=sc["n"], brick=sc["brick"], n_levels=sc["n_levels"], model=sc["model"],
                     ds0=sc.get("ds0", 1.0))
         if sc["model"] == "static":
-            args.update(eta=sc["eta"], chi=sc["chi"])
+            args.update(eta=sc["eta"], chi=sc["chi"], emission=emission or "static")
         else:
             args.update(emission=emission or "static", profile=sc.get("profile", "gauss"), lam=sc["lam"],
                         lam0=sc["lam0"], eta_star=sc["eta_star"], chi_star=sc["chi_star"], damp=sc["damp"],

@@ -98,12 +98,13 @@ static rt_status check_desc(const rt_scene_desc* d, const rt_scene_inputs* inp)
     if (!(d->ds0 > 0.0)) return fail(RT_E_ARG, "ds0 must be positive");
     if (d->n_lam < 1) return fail(RT_E_ARG, "n_lam must be >= 1");
     if (d->model == RT_MODEL_STATIC) {
-        if (d->emission != RT_EMIS_STATIC) return fail(RT_E_ARG, "static model supports only RT_EMIS_STATIC");
+        if (d->emission != RT_EMIS_STATIC && d->emission != RT_EMIS_PREFILTER)
+            return fail(RT_E_ARG, "static model supports RT_EMIS_STATIC and RT_EMIS_PREFILTER only");
         if (inp && (!inp->d_eta || !inp->d_chi)) return fail(RT_E_ARG, "static model needs d_eta and d_chi");
     } else if (d->model == RT_MODEL_LINES) {
         if (d->n_lines < 1 || d->n_lines > RT_MAX_LINES) return fail(RT_E_ARG, "n_lines must be in [1, %d]", RT_MAX_LINES);
         if (d->profile != RT_PROFILE_GAUSS && d->profile != RT_PROFILE_VOIGT) return fail(RT_E_ARG, "bad profile");
-        if (d->emission < RT_EMIS_STATIC || d->emission > RT_EMIS_CAV) return fail(RT_E_ARG, "bad emission");
+        if (d->emission < RT_EMIS_STATIC || d->emission > RT_EMIS_PREFILTER) return fail(RT_E_ARG, "bad emission");
         if (d->emission == RT_EMIS_VELINTERP && d->n_v < 2) return fail(RT_E_ARG, "n_v must be >= 2");
         if (d->vgrid != RT_VGRID_FULL && d->vgrid != RT_VGRID_ORTHANT) return fail(RT_E_ARG, "bad vgrid %d", d->vgrid);
         if (!d->h_lam || !d->h_lam0) return fail(RT_E_ARG, "lines model needs h_lam and h_lam0");
@@ -118,6 +119,12 @@ static rt_status check_desc(const rt_scene_desc* d, const rt_scene_inputs* inp)
         return fail(RT_E_ARG, "bad model %d", d->model);
     }
     return RT_OK;
+}
+
+// LDS a trace workgroup stages: the packed block states, and the slot table on grids of <= kSlotLdsMax blocks.
+static long long trace_lds_bytes(const Geo& g)
+{
+    return 8ll * g.n_state_words + (g.nblocks <= kSlotLdsMax ? 4ll * g.nblocks : 0ll);
 }
 
 static void make_geo(const rt_scene_desc* d, Geo& g)
@@ -169,8 +176,10 @@ static bool carve_active(const rt_scene_desc* d, const Geo& g, long long na, Car
 {
     const size_t cells = (size_t)na * g.cells;
     if (!c.take(&B.fstats, ((size_t)na << (d->dim * (g.log2B - g.feat_level))) * kLam)) return false;
-    if (d->model == RT_MODEL_STATIC || d->emission == RT_EMIS_STATIC)
+    if (d->emission == RT_EMIS_STATIC || d->emission == RT_EMIS_PREFILTER)
         if (!c.take((float**)&B.vals, cells * kLam * 2)) return false;
+    if (d->emission == RT_EMIS_PREFILTER)  // one record per signed axis of every cell (level 0 unused)
+        if (!c.take((float**)&B.pf, cells * (size_t)(2 * d->dim) * kLam * 2)) return false;
     if (d->model == RT_MODEL_LINES && d->emission == RT_EMIS_VELINTERP) {
         const size_t nq = (size_t)vclasses(d);
         if (!c.take(&B.vgrid, nq * cells) || !c.take(&B.vrange, nq * cells) ||
@@ -292,6 +301,9 @@ rt_status rt_scene_workspace_bytes(const rt_scene_desc* d, int64_t n_active, siz
     Geo g;
     make_geo(d, g);
     if (n_active < 0 || n_active > g.nblocks) return fail(RT_E_ARG, "n_active must be in [0, %lld]", g.nblocks);
+    if (trace_lds_bytes(g) > kLdsPerCuBytes)
+        return fail(RT_E_UNSUPPORTED, "%lld blocks: their packed states need %lld bytes of LDS per trace workgroup, more "
+                    "than a compute unit holds (%lld)", g.nblocks, trace_lds_bytes(g), kLdsPerCuBytes);
     *h_bytes = scene_bytes(d, g, n_active);
     return RT_OK;
 }
@@ -332,6 +344,16 @@ rt_status rt_scene_create(const rt_scene_desc* d, const rt_scene_inputs* inp, vo
     Geo g0;
     make_geo(d, g0);
     RT_TRY(check_ws(d_ws, ws_bytes, fixed_bytes(g0), "rt_scene_create"));
+    {
+        // the trace kernels stage the packed block states (and small grids' slot tables) in LDS
+        int dev = 0, max_lds = 0;
+        RT_HIP(hipGetDevice(&dev));
+        RT_HIP(hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        const long long need = trace_lds_bytes(g0);
+        if (need > (long long)max_lds)
+            return fail(RT_E_UNSUPPORTED, "%lld blocks: their packed states need %lld bytes of LDS per trace "
+                        "workgroup, the device allows %d", g0.nblocks, need, max_lds);
+    }
 
     rt_scene* sc = new (std::nothrow) rt_scene();
     if (!sc) return fail(RT_E_ARG, "out of host memory");
@@ -426,7 +448,7 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     if (!(p->tau_thin >= 0.0)) return fail(RT_E_ARG, "tau_thin must be >= 0");
     if (p->avg_mode != RT_AVG_LOG && p->avg_mode != RT_AVG_LINEAR) return fail(RT_E_ARG, "bad avg_mode");
     if (p->storage < RT_F32 || p->storage > RT_F16) return fail(RT_E_ARG, "bad storage dtype");
-    const bool static_emis = d.model == RT_MODEL_STATIC || d.emission == RT_EMIS_STATIC;
+    const bool static_emis = d.emission == RT_EMIS_STATIC || d.emission == RT_EMIS_PREFILTER;
     LamBatch lb = make_batch(sc, lam_begin, lam_end);
     const Geo& g = sc->g;
     int cap = p->max_level < 0 ? -1 : p->max_level;
@@ -438,6 +460,8 @@ rt_status rt_scene_build(rt_scene* sc, const rt_build_params* p, int32_t lam_beg
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_VELINTERP)
         RT_HIP(launch_velinterp_nodes(g, sc->in, sc->b, sc->n_active, lb, d.n_v, vclasses(&d), d.ds0, p->avg_mode,
                                       p->storage, s));
+    if (d.emission == RT_EMIS_PREFILTER)
+        RT_HIP(launch_build_prefilter(g, sc->in, sc->b, sc->n_active, d.model, lb, lam_begin, d.ds0, p->storage, s));
     RT_HIP(launch_pack_states(g, sc->b.levels, sc->b.states, s));
     if (d.model == RT_MODEL_LINES && d.emission == RT_EMIS_CAV && p->avg_mode != sc->cav_mode) {
         // the wavelength-independent chain follows the stored-value mode of the build
@@ -467,6 +491,7 @@ TraceLaunch rt::make_trace(const rt_scene* sc, const rt_trace_params* p)
     t.states = sc->b.states;
     t.slot = sc->b.slot;
     t.vals = sc->b.vals;
+    t.pf = sc->b.pf;
     t.vgrid = sc->b.vgrid;
     t.vnodes = sc->b.vnodes;
     t.cav = sc->b.cav;
@@ -484,7 +509,7 @@ TraceLaunch rt::make_trace(const rt_scene* sc, const rt_trace_params* p)
     t.active_list = sc->b.active_list;
     t.I0 = p->I0;
     t.ds0 = (float)sc->desc.ds0;
-    t.emission = sc->desc.model == RT_MODEL_STATIC ? RT_EMIS_STATIC : sc->desc.emission;
+    t.emission = sc->desc.emission;
     t.storage = sc->storage;
     t.n_v = sc->desc.n_v;
     t.n_vclass = vclasses(&sc->desc);
@@ -930,8 +955,8 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
         const rt_scene* sc = J.scene;
         if (!sc || !J.d_dirs || !J.d_I) return fail(RT_E_ARG, "job %d: null scene, directions or output", j);
         if (sc->batch_begin < 0) return fail(RT_E_STATE, "job %d: scene has no built batch", j);
-        if (!(sc->desc.model == RT_MODEL_STATIC || sc->desc.emission == RT_EMIS_STATIC))
-            return fail(RT_E_UNSUPPORTED, "job %d: batched trace supports static emission", j);
+        if (sc->desc.emission != RT_EMIS_STATIC)
+            return fail(RT_E_UNSUPPORTED, "job %d: batched trace supports static emission (not prefiltered)", j);
         if (J.n_dir < 1) return fail(RT_E_ARG, "job %d: n_dir must be >= 1", j);
         const rt_trace_params& tp = J.params;
         if (tp.mode != RT_TRACE_LEVEL0 && tp.mode != RT_TRACE_VLM) return fail(RT_E_ARG, "job %d: bad mode", j);

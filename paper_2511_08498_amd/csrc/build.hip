@@ -360,6 +360,112 @@ hipError_t launch_build_static(const Geo& g, const Inputs& in, const SceneBufs& 
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------- prefiltering
+// Prefiltered merged cells (Sect. 5.1): for a level-m cell and a signed axis
+// k = 2a + (propagation towards -a), every row of MIP-0 voxels parallel to a is
+// solved exactly from I = 0 at its entry face, voxel by voxel in the direction
+// of propagation; the cell keeps the homogeneous cell of its side with the
+// same row-averaged transfer (Ibar, Tbar = mean T_row, 1 - Tbar = mean(1 - T_row),
+// each summed on its own): chi = -ln(Tbar) / side (from 1 - Tbar below 1/2, from
+// Tbar above, the mean row optical depth when every row's T underflows),
+// eta = Ibar chi / (1 - Tbar) (Ibar / side when Tbar = 1).  FP64 from the
+// MIP-0 values (the same values as the level test),
+// rows summed in a fixed order (lowest cross axis fastest).  One workgroup per
+// active block, one thread per MIP-0 voxel; the (cell, axis) pairs of a level
+// are shared out over the threads.
+template <int D, typename T>
+__global__ void k_build_prefilter(Geo g, Inputs in, SceneBufs bufs, int model, LamBatch lb, int lam_begin, double ds0)
+{
+    extern __shared__ double lds[];
+    constexpr int K = 2 * D;
+    const int slot = blockIdx.x;
+    const int blk = bufs.active_list[slot];
+    const int tid = threadIdx.x;
+    const int B = g.B, L = g.n_levels;
+    const int bc[3] = {blk % g.nb[0], (blk / g.nb[0]) % g.nb[1], blk / (g.nb[0] * g.nb[1])};
+    const int lx = tid & (B - 1), ly = (tid >> g.log2B) & (B - 1), lz = D > 2 ? (tid >> (2 * g.log2B)) : 0;
+    const long long v = (long long)(bc[0] * B + lx) +
+                        (long long)g.n[0] * ((long long)(bc[1] * B + ly) + (long long)g.n[1] * (bc[2] * B + lz));
+    double* le = lds;
+    double* lc = lds + g.bvox;
+    T* pf = (T*)bufs.pf;
+    const long long rec0 = (long long)slot * g.cells;
+    for (int l = 0; l < lb.nl; ++l) {
+        double e, c;
+        mip0_value(in, model, 0, D, lb, lam_begin + l, l, v, e, c);
+        le[tid] = e;
+        lc[tid] = c;
+        __syncthreads();
+        for (int m = 1; m < L; ++m) {
+            const int side = 1 << m, ncs = B >> m;
+            const int ncell = D == 2 ? ncs * ncs : ncs * ncs * ncs;
+            for (int task = tid; task < ncell * K; task += blockDim.x) {
+                const int ci = task / K, k = task - ci * K;
+                const int a = k >> 1, neg = k & 1;
+                const int b0 = a == 0 ? 1 : 0;                    // cross axes, lowest first
+                const int b1 = D > 2 ? (a == 2 ? 1 : 2) : -1;
+                const int corner[3] = {(ci % ncs) * side, ((ci / ncs) % ncs) * side, D > 2 ? (ci / (ncs * ncs)) * side : 0};
+                const int e1 = b1 >= 0 ? side : 1;
+                double sumI = 0.0, sumA = 0.0, sumT = 0.0, sumTau = 0.0;
+                for (int r1 = 0; r1 < e1; ++r1)
+                    for (int r0 = 0; r0 < side; ++r0) {
+                        double I = 0.0, tau_row = 0.0;
+                        for (int j = 0; j < side; ++j) {
+                            int p[3] = {corner[0], corner[1], corner[2]};
+                            p[b0] += r0;
+                            if (b1 >= 0) p[b1] += r1;
+                            p[a] += neg ? side - 1 - j : j;  // entry face first
+                            const int q = p[0] + B * (p[1] + B * p[2]);
+                            const double tau = lc[q] * ds0;
+                            if (tau == 0.0) I += le[q] * ds0;
+                            else I = I * exp(-tau) + (le[q] / lc[q]) * (-expm1(-tau));
+                            tau_row += tau;
+                        }
+                        sumI += I;
+                        sumA += -expm1(-tau_row);
+                        sumT += exp(-tau_row);
+                        sumTau += tau_row;
+                    }
+                const double rows = (double)side * (double)e1;
+                const double Ibar = sumI / rows, absorbed = sumA / rows, Tbar = sumT / rows, Lside = side * ds0;
+                double ce = 0.0, ee;
+                if (absorbed > 0.0) {
+                    const double tau_eff = absorbed < 0.5 ? -log1p(-absorbed) : (Tbar > 0.0 ? -log(Tbar) : sumTau / rows);
+                    ce = tau_eff / Lside;
+                    ee = Ibar * tau_eff / (absorbed * Lside);
+                } else {
+                    ee = Ibar / Lside;
+                }
+                T* r = pf + (((rec0 + g.lvl_off[m] + ci) * K + k) * kLam + l) * 2;
+                r[0] = Codec<T>::enc((float)ee);
+                r[1] = Codec<T>::enc((float)ce);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_build_prefilter(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int model,
+                                  const LamBatch& lb, int lam_begin, double ds0, int storage, hipStream_t s)
+{
+    if (n_active == 0 || g.n_levels < 2) return hipSuccess;
+    const size_t shm = sizeof(double) * 2 * (size_t)g.bvox;
+    const dim3 grid((unsigned)n_active), block((unsigned)g.bvox);
+#define RT_LAUNCH_PF(DD, TT) \
+    hipLaunchKernelGGL((k_build_prefilter<DD, TT>), grid, block, shm, s, g, in, b, model, lb, lam_begin, ds0)
+    if (g.dim == 2) {
+        if (storage == RT_F32) RT_LAUNCH_PF(2, float);
+        else if (storage == RT_BF16) RT_LAUNCH_PF(2, __hip_bfloat16);
+        else RT_LAUNCH_PF(2, __half);
+    } else {
+        if (storage == RT_F32) RT_LAUNCH_PF(3, float);
+        else if (storage == RT_BF16) RT_LAUNCH_PF(3, __hip_bfloat16);
+        else RT_LAUNCH_PF(3, __half);
+    }
+#undef RT_LAUNCH_PF
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ states
 __global__ void k_pack_states(long long nb, int nw, const int8_t* levels, uint64_t* states)
 {

@@ -250,7 +250,10 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
             r[2 * l] = oe;
             r[2 * l + 1] = oc;
         }
-        const long long o = (rec * n_v + kn) * (kLam * 2);  // in elements of T
+        // node-major inside a brick: [class][slot][node][cell], so that neighbouring cells' records at one node
+        // are adjacent (rays of a wave and consecutive cells of a ray mostly take the same node)
+        const long long o = (((long long)q_cls * gridDim.x + slot) * n_v * g.cells + (long long)kn * g.cells +
+                             g.lvl_off[m] + cell) * (kLam * 2);  // in elements of T
         if constexpr (std::is_same<T, float>::value) {
             float4* out = (float4*)(bufs.vnodes + o);
 #pragma unroll

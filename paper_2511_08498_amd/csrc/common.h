@@ -15,6 +15,7 @@ constexpr int kLam = RT_LAM_BATCH;   // wavelengths per batch, kept in registers
 constexpr int kMaxLines = RT_MAX_LINES;
 constexpr int kMaxLevels = RT_MAX_LEVELS;
 constexpr long long kSlotLdsMax = 8192;  // blocks whose slot table a trace workgroup keeps in LDS (32 KiB)
+constexpr long long kLdsPerCuBytes = 160 * 1024;  // LDS of one gfx950 compute unit: a workgroup never gets more
 constexpr int kStatesPerWord = 21;   // 3-bit block states per 64-bit word
 constexpr double kCkms = 299792.458; // speed of light, km/s
 
@@ -60,11 +61,12 @@ struct SceneBufs {
     int8_t* levels;         // [nblocks] current batch
     uint64_t* states;       // [n_state_words]
     void* vals;             // [n_active][cells][kLam][2] static emission values (storage dtype)
+    void* pf;               // [n_active][cells][2 dim][kLam][2] prefiltered cells, signed axis k = 2a + (w_a < 0)
     // velocity interpolation, per direction class q (1 class for the full grid, 2^dim orthants):
     float4* vgrid;          // [n_vclass][n_active][cells] (gx, gy, gz, off): node coordinate of direction w
                             // f = g . w + off = (vbar . w - lo) (n_v - 1) / (hi - lo); g = 0, off = 0 if hi = lo
     float2* vrange;         // [n_vclass][n_active][cells] (lo, hi) node range of projected velocities
-    float* vnodes;          // [n_vclass][n_active][cells][n_v][kLam][2] node values
+    float* vnodes;          // [n_vclass][n_active][n_v][cells][kLam][2] node values (node-major in a brick)
     float* cav;             // [n_active][cells][cav_rec] line parameters (Core and Voigt)
     void* cav_lp;           // the same in BF16 or FP16 (reduced-precision storage), 2 bytes per value
     float4* fstats;         // [n_active][cells at feat_level][kLam]: mean, var of ln(chi ds0), mean, var of ln(eta ds0)
@@ -126,6 +128,8 @@ hipError_t launch_build_static(const Geo& g, const Inputs& in, const SceneBufs& 
                                int vrule, const LamBatch& lb, int lam_begin, double ds0, double T, double tau_thin,
                                int cap, int avg_mode, int storage, int write_values, hipStream_t s);
 hipError_t launch_pack_states(const Geo& g, const int8_t* levels, uint64_t* states, hipStream_t s);
+hipError_t launch_build_prefilter(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int model,
+                                  const LamBatch& lb, int lam_begin, double ds0, int storage, hipStream_t s);
 hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, int n_v, int n_vclass,
                         hipStream_t s);
 hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
@@ -144,6 +148,7 @@ struct TraceLaunch {
     const int32_t* slot;
     int slot_lds;  // the trace kernels copy slot[] to LDS after the state words (grids of <= kSlotLdsMax blocks)
     const void* vals;
+    const void* pf;            // prefiltered cells (RT_EMIS_PREFILTER)
     const float4* vgrid;
     const float* vnodes;
     int n_vclass;              // velocity-grid direction classes: 1 (full grid) or 2^dim (orthants)

@@ -692,6 +692,68 @@ struct VisStatic {
     }
 };
 
+// Prefiltered cells (Sect. 5.1): level 0 reads the stored MIP-0 values, a
+// merged cell the records of the signed axes the ray propagates along
+// (k = 2a + (w_a < 0)), blended with weights w_a^2 / sum w^2 fixed per ray.
+template <int D, typename T, class Acc = AccPlain>
+struct VisPrefilter {
+    using AccT = Acc;
+    static constexpr int kMinWaves = (D == 2 && !Acc::kTrunc && !Acc::kJ) ? 4 : 1;
+    const TraceLaunch* tl;
+    const T* vals;
+    const T* pf;
+    long long cur_blk;
+    long long base;
+    float dsf;
+    float wgt[D];
+    int kax[D];
+    Acc acc;
+    __device__ void init(const TraceLaunch* t, const float* wf)
+    {
+        tl = t;
+        vals = (const T*)t->vals;
+        pf = (const T*)t->pf;
+        cur_blk = -1;
+        base = 0;
+        dsf = t->ds0;
+        float s = 0.f;
+#pragma unroll
+        for (int a = 0; a < D; ++a) s = fmaf(wf[a], wf[a], s);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            wgt[a] = wf[a] * wf[a] / s;
+            kax[a] = 2 * a + (wf[a] < 0.f ? 1 : 0);
+        }
+        acc.init(t);
+    }
+    __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
+    {
+        if (blk != cur_blk) {
+            cur_blk = blk;
+            base = block_slot(tl->g, tl->slot, tl->slot_lds, blk) * tl->g.cells;
+        }
+        const long long cell = base + level_offset(tl->g, lvl) + local_index(tl->g, c, lvl, D);
+        float e[kLam], x[kLam];
+        if (lvl == 0) {
+            load_rec<T>(vals + cell * (kLam * 2), e, x);
+        } else {
+#pragma unroll
+            for (int l = 0; l < kLam; ++l) e[l] = x[l] = 0.f;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                float ea[kLam], xa[kLam];
+                load_rec<T>(pf + (cell * (2 * D) + kax[a]) * (kLam * 2), ea, xa);
+#pragma unroll
+                for (int l = 0; l < kLam; ++l) {
+                    e[l] = fmaf(wgt[a], ea[l], e[l]);
+                    x[l] = fmaf(wgt[a], xa[l], x[l]);
+                }
+            }
+        }
+        return acc.add(e, x, c, lvl, blk, t0, t1, dsf);
+    }
+};
+
 // T: storage of the node records (FP32, or BF16 / FP16 at half the record size).
 // The direction class (full grid, or the orthant of w) is fixed per ray, so the
 // class's grid records and node values are selected once at initialisation.
@@ -729,7 +791,8 @@ struct VisVelinterp {
             cur_blk = blk;
             base = block_slot(tl->g, tl->slot, tl->slot_lds, blk) * tl->g.cells;
         }
-        const unsigned cell = (unsigned)(base + level_offset(tl->g, lvl) + local_index(tl->g, c, lvl, D));
+        const unsigned cellin = (unsigned)(level_offset(tl->g, lvl) + local_index(tl->g, c, lvl, D));
+        const unsigned cell = (unsigned)base + cellin;
         // node coordinate f = g . w + off = (vbar . w - lo) (n_v - 1) / (hi - lo) over the cell's range
         // [lo, hi] of projected velocities (g = off = 0 for an empty range: node 0 is used)
         float4 vg = vgrid[cell];
@@ -739,11 +802,13 @@ struct VisVelinterp {
         int kn = (int)floorf(f);
         kn = kn < 0 ? 0 : (kn > nv - 2 ? nv - 2 : kn);
         float wt = f - (float)kn;
-        // the two node records around u are adjacent (128 B in FP32, 64 B in BF16 / FP16)
-        const T* r0 = vnodes + (cell * (unsigned)nv + (unsigned)kn) * (unsigned)(kLam * 2);
+        // node planes of the brick: [node][cell], one record 64 B in FP32 (32 B in BF16 / FP16); the two nodes
+        // around u are one plane apart
+        const unsigned cells = (unsigned)tl->g.cells;
+        const T* r0 = vnodes + ((unsigned)base * (unsigned)nv + (unsigned)kn * cells + cellin) * (unsigned)(kLam * 2);
         float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
         load_rec<T>(r0, e0, x0);
-        load_rec<T>(r0 + kLam * 2, e1, x1);
+        load_rec<T>(r0 + cells * (unsigned)(kLam * 2), e1, x1);
         float ee[kLam], xx[kLam];
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
@@ -1151,6 +1216,16 @@ static hipError_t launch_trace_acc(const TraceLaunch& t, hipStream_t s)
         if (t.storage == RT_F32) return launch_one<3, VisStatic<3, float, Acc>>(t, s);
         if (t.storage == RT_BF16) return launch_one<3, VisStatic<3, __hip_bfloat16, Acc>>(t, s);
         return launch_one<3, VisStatic<3, __half, Acc>>(t, s);
+    }
+    if (t.emission == RT_EMIS_PREFILTER) {
+        if (t.g.dim == 2) {
+            if (t.storage == RT_F32) return launch_one<2, VisPrefilter<2, float, Acc>>(t, s);
+            if (t.storage == RT_BF16) return launch_one<2, VisPrefilter<2, __hip_bfloat16, Acc>>(t, s);
+            return launch_one<2, VisPrefilter<2, __half, Acc>>(t, s);
+        }
+        if (t.storage == RT_F32) return launch_one<3, VisPrefilter<3, float, Acc>>(t, s);
+        if (t.storage == RT_BF16) return launch_one<3, VisPrefilter<3, __hip_bfloat16, Acc>>(t, s);
+        return launch_one<3, VisPrefilter<3, __half, Acc>>(t, s);
     }
     if (t.emission == RT_EMIS_VELINTERP) {
         if (t.g.dim == 2) {

@@ -43,6 +43,13 @@ def test_scene_descriptor_validation(rt):
     with pytest.raises(rt.RtError) as e:
         rt.scene_workspace_bytes(sc, n_active=65)
     assert e.value.status == rt.RT_E_ARG
+    # 8192^2 voxels in 8^2 bricks: 2^20 blocks, whose packed states (399 KB) exceed a compute unit's LDS
+    big = dict(sc, n=(8192, 8192, 1), block_active=np.ones(1 << 20, np.uint8))
+    with pytest.raises(rt.RtError) as e:
+        rt.scene_workspace_bytes(big, n_active=0)
+    assert e.value.status == rt.RT_E_UNSUPPORTED and "LDS" in str(e.value)
+    # the same grid in 16^2 bricks fits (2^18 blocks, 100 KB of states)
+    assert rt.scene_workspace_bytes(dict(big, brick=16, block_active=np.ones(1 << 18, np.uint8)), n_active=0) > 0
 
 
 def test_nrc_workspace_bytes(rt):
