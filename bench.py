@@ -137,10 +137,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "matrix"],
+    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "matrix", "prefilter"],
                     help="cfg2: 2D velocity interpolation (default, the headline line); cfg3: 3D Core and Voigt "
                          "per storage dtype; cfg4: 48-scene batched vs sequential; cfg5: radiance cache on cfg3; "
-                         "matrix: the paper's method matrix on a prominence-like 2D scene")
+                         "matrix: the paper's method matrix on a prominence-like 2D scene; prefilter: box-filtered "
+                         "vs prefiltered merged cells (Sect. 5.1) on cfg2's scene with the lines at rest")
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=None, help="velocity nodes per orthant (default: cfg2 headline 41, "
                                                            "else 21)")
@@ -174,7 +175,9 @@ def main():
     ap.add_argument("--nrc-freq", type=float, default=0.0, help="cfg5: highest encoding frequency (0: grid side / 2)")
     ap.add_argument("--nrc-lr", type=float, default=1e-3, help="cfg5: Adam learning rate")
     ap.add_argument("--nrc-train-probes", type=int, default=1024, help="cfg5: training probes per wavelength batch")
-    ap.add_argument("--nrc-held-probes", type=int, default=128, help="cfg5: held-out probes per wavelength batch")
+    ap.add_argument("--nrc-held-probes", type=int, default=1024, help="cfg5: held-out probes per wavelength batch "
+                                                                         "(x 32 directions x 16 batches = 2^19 rays)")
+    ap.add_argument("--nrc-min-checks", type=int, default=2, help="cfg5: held-out rays a block needs to use the cache")
     ap.add_argument("--scenes", type=int, default=0, help="cfg4: first N scenes only (0 = all 48)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -182,10 +185,14 @@ def main():
               "path would shard by wavelength batch with no exchange." % args.gpus)
         sys.exit(2)
     if args.workload != "cfg2":
-        # cfg2 takes its headline setting (CFG2_HEADLINE) for what is not given; the method matrix mirrors the
-        # deployment of Sect. 4.1 (IoD threshold 1); elsewhere the configurations' own reading
-        for k, v in (("iod", 1.0 if args.workload == "matrix" else 1e-2), ("n_v", 21), ("tau_thin", 0.25),
-                     ("grade_scale", 1.0), ("iod_frame", "rest")):
+        # cfg2 and cfg3 take their headline settings (CFG2_HEADLINE, CFG3_HEADLINE) for what is not given; the
+        # method matrix mirrors the deployment of Sect. 4.1 (IoD threshold 1); elsewhere the configurations' own
+        # reading
+        dflt = {"iod": 1.0 if args.workload == "matrix" else 1e-2, "n_v": 21, "tau_thin": 0.25, "grade_scale": 1.0,
+                "iod_frame": "rest"}
+        if args.workload in ("cfg3", "cfg5"):  # cfg5 runs on cfg3's scene
+            dflt.update(CFG3_HEADLINE)
+        for k, v in dflt.items():
             if getattr(args, k) is None:
                 setattr(args, k, v)
     if args.workload == "cfg3":
@@ -196,7 +203,23 @@ def main():
         return bench_cfg5(args)
     if args.workload == "matrix":
         return bench_matrix(args)
+    if args.workload == "prefilter":
+        return bench_prefilter(args)
     return bench_cfg2(args)
+
+
+def copy_probe(args, torch, dev):
+    """Profiling only: device-to-device copies of a known size, whose FETCH_SIZE / WRITE_SIZE counters scale the
+    march kernels' counters to DRAM bytes."""
+    if not args.copy_probe_mb:
+        return
+    src = torch.ones(args.copy_probe_mb * 2 ** 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log("copy probe: %d MiB read + %d MiB written per copy, 3 copies" % (args.copy_probe_mb, args.copy_probe_mb))
+    del src, dst
 
 
 def host_cpu_info():
@@ -259,14 +282,7 @@ def bench_cfg2(args):
         nb_lam = min(nb_lam, args.batches)
         n_lam = 8 * nb_lam
     spread = list(range(2, nb_lam, 4)) or [0]  # comparator timing: every fourth batch across both lines
-    if args.copy_probe_mb:
-        src = torch.ones(args.copy_probe_mb * 2 ** 18, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        log("copy probe: %d MiB read + %d MiB written per copy, 3 copies" % (args.copy_probe_mb, args.copy_probe_mb))
-        del src, dst
+    copy_probe(args, torch, dev)
     dirs = torch.from_numpy(sc["dirs"]).to(dev)
     n_dir = dirs.shape[0]
 
@@ -600,14 +616,24 @@ def _events(torch):
 
 
 # ----------------------------------------------------------------------------- cfg3
+# The cfg3 headline is, like cfg2's, the fastest setting measured under the 5e-3 bar; on this scene (a dense
+# chromosphere slab with steep vertical gradients, filaments in near-empty fill) the bar leaves almost no cell
+# merged, so the headline runs at the speed of the exact sparse march.  The configuration's literal reading
+# (T = 1e-2 with the thin bypass) is reported beside it.
+CFG3_HEADLINE = {"iod": 3e-4, "tau_thin": 0.0, "grade_scale": 16.0}
+CFG3_AS_STATED = {"iod": 1e-2, "tau_thin": 0.25, "grade_scale": 1.0}
+
+
 def bench_cfg3(args):
-    """3D 256^3 Core-and-Voigt scene, storage FP32 / BF16 / FP16: time per full solve (16 batches),
-    march-kernel roofline, error of each dtype against the FP64 dense Classic oracle."""
+    """3D 256^3 Core-and-Voigt scene at the headline setting, storage FP32 / BF16 / FP16: time per full solve
+    (16 batches), march-kernel roofline, error of each dtype against the FP64 dense Classic oracle; the literal
+    setting and the exact sparse march beside it (pareto)."""
     np, torch, rt, dev = _env()
     from synth import make_cfg3
     tg = time.time()
     sc = make_cfg3()
     log("cfg3 scene generated in %.1fs (%d active bricks)" % (time.time() - tg, int(sc["block_active"].sum())))
+    copy_probe(args, torch, dev)
     nb = sc["lam"].size // 8
     if args.batches:
         nb = min(nb, args.batches)
@@ -661,6 +687,9 @@ def bench_cfg3(args):
         scene.trace(dirs, mode="vlm", level_dist=level_dist, grade=args.grade, out=out, stats=stats)
     torch.cuda.synchronize()
     seglam = int(stats[0].item()) * 8
+    if args.no_compare and args.no_cpu_baseline:  # profiling runs: the timed solves only
+        log("cfg3: %d seg-lambda per solve" % seglam)
+        return
     # dense comparator: Core and Voigt at MIP 0 on the full grid (every brick stored), one batch
     dense = rt.Scene.from_dict(sc, emission="cav", dense=True)
     pv = torch.from_numpy(probe_vox).to(dev)
@@ -697,11 +726,42 @@ def bench_cfg3(args):
         ladder = run_ladder(torch, np, settings, base, dict(mode="vlm", level_dist=level_dist, grade=args.grade),
                             dirs, probe_vox[k], d,
                             ref, nb)
-    out_line = {"workload": "cfg3", "accuracy_ladder": ladder, "config": {
+    # pareto: the literal setting and the exact sparse march (Core and Voigt at MIP 0), timed on every fourth batch
+    spread = list(range(1, nb, 4)) or [0]
+
+    def time_setting(bkw, tkw):
+        scene.build(8 * spread[0], 8 * spread[0] + 8, **bkw)
+        scene.trace(dirs, out=out, **tkw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in spread:
+            scene.build(8 * b, 8 * b + 8, **bkw)
+            scene.trace(dirs, out=out, **tkw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / len(spread)
+
+    st_ = CFG3_AS_STATED
+    psets = [("as_stated", dict(iod_threshold=st_["iod"], avg_mode=args.avg, tau_thin=st_["tau_thin"]),
+              dict(mode="vlm", level_dist=[v * st_["grade_scale"] for v in rt.CASCADE_LEVEL_DIST], grade=args.grade)),
+             ("sparse_classic", dict(iod_threshold=args.iod), dict(mode="level0")),
+             ("headline_f32", dict(iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin),
+              dict(mode="vlm", level_dist=level_dist, grade=args.grade))]
+    perr = run_ladder(torch, np, [(n_, scene, b_, t_) for n_, b_, t_ in psets], {}, {}, dirs, probe_vox[k], d, ref,
+                      nb)
+    pareto = []
+    for n_, b_, t_ in psets:
+        ms_b = time_setting(b_, t_)
+        pareto.append({"name": n_, "ms_per_batch": ms_b, "speedup_vs_dense_classic": dense_ms_batch / ms_b,
+                       "p99.9": perr[n_]["p99.9"], "meets_bar": bool(perr[n_]["p99.9"] <= ACCURACY_BAR)})
+    pareto.sort(key=lambda q: q["ms_per_batch"])
+    out_line = {"workload": "cfg3", "accuracy_ladder": ladder, "accuracy_bar": ACCURACY_BAR, "pareto": pareto,
+                "as_stated": "T=%g, thin bypass %g, cascade grading x%g" % (
+                    st_["iod"], st_["tau_thin"], st_["grade_scale"]),
+                "config": {
         "workload": "3D 256^3, 8^3 bricks, %d active (25%%), slab + %d loops, 2 Voigt lines (Core and Voigt) + "
-                    "grey continuum, |v| <= 30 km/s, 4-level VLM T=%g, %s, 32 Fibonacci directions, %d lambda "
-                    "(%d batches of 8), all %d probes" % (
-                        int(sc["block_active"].sum()), int(sc["n_loops"]), args.iod,
+                    "grey continuum, |v| <= 30 km/s, 4-level VLM T=%g, thin bypass %g, %s, 32 Fibonacci directions, "
+                    "%d lambda (%d batches of 8), all %d probes" % (
+                        int(sc["block_active"].sum()), int(sc["n_loops"]), args.iod, args.tau_thin,
                         _grading(args), nb * 8, nb, n_probes)},
         "seg_lam_per_solve": seglam, "dense_seg_lam_per_solve": dense_seglam,
         "dense_classic_gpu": {"ms_per_batch": dense_ms_batch, "ms_per_solve_extrapolated": dense_ms_batch * nb},
@@ -719,12 +779,96 @@ def bench_cfg3(args):
             "trace_bytes_per_seg_lam": bps,
             "trace_hbm_frac_streamed": bps * seglam / nb / (r["mean_trace_ms"] / 1e3) / HBM_PEAK,
             "error_vs_fp64_classic": _err(r["got"], ref)}
+        out_line["dtypes"][dt]["meets_accuracy_bar"] = bool(
+            out_line["dtypes"][dt]["error_vs_fp64_classic"]["p99.9"] <= ACCURACY_BAR)
     if "f32" in res:
         for dt in res:
             if dt != "f32":
                 out_line["dtypes"][dt]["speedup_vs_f32"] = res["f32"]["ms_per_solve"] / res[dt]["ms_per_solve"]
                 out_line["dtypes"][dt]["error_vs_gpu_f32"] = _err(res[dt]["got"], res["f32"]["got"].astype(np.float64))
+    if "f32" in res:
+        cnt = measured_counters("counters_cav_cfg3", "cfg3 headline f32")
+        if cnt is not None:
+            # counts and launch time from the same profiled run (batches 0-3), as fractions of the peaks
+            t_ = cnt["mean_launch_ms_kernel_trace"] / 1e3
+            out_line["roofline"] = {
+                "bound": "alu", "achieved": cnt["valu_insts_per_launch"] / t_ / 1e9,
+                "peak": VALU_ISSUE_PEAK / 1e9, "unit": "G VALU wave-instructions/s",
+                "frac": cnt["valu_insts_per_launch"] / t_ / VALU_ISSUE_PEAK, "traffic": cnt["hbm_bytes_per_launch"],
+                "hbm_traffic_frac": cnt["hbm_bytes_per_launch"] / t_ / HBM_PEAK,
+                "kernel": "k_trace<3, VisCav<3, float, AccPlain, 2>>", "counters": "profiles/counters_cav_cfg3.json",
+                "mean_launch_ms": cnt["mean_launch_ms_kernel_trace"]}
     print(json.dumps(out_line), flush=True)
+
+
+# ----------------------------------------------------------------------------- prefiltering
+def bench_prefilter(args):
+    """cfg2's scene with every line at rest, stored as static emission: VLM with box-filtered merged cells against
+    VLM with prefiltered merged cells (Sect. 5.1) on the same level maps, for several level settings.  Error against
+    the FP64 dense march of the same static emission (MIP-0 values at rest, every cell at MIP 0) on a seeded ray
+    sample; time per batch over every fourth batch."""
+    np, torch, rt, dev = _env()
+    import oracle as orc
+    from synth import make_cfg2
+    sc = make_cfg2()
+    nb = sc["lam"].size // 8
+    if args.batches:
+        nb = min(nb, args.batches)
+    spread = list(range(2, nb, 4)) or [0]
+    dirs = torch.from_numpy(sc["dirs"]).to(dev)
+    n_dir = dirs.shape[0]
+    box = rt.Scene.from_dict(sc, emission="static")
+    pf = rt.Scene.from_dict(sc, emission="prefilter")
+    n_probes = box.info["n_probes"]
+    probes = box.probe_voxels()
+    rng = np.random.default_rng(2027)
+    k = rng.choice(probes.size, min(args.pairs, probes.size), replace=False)
+    d = rng.integers(0, n_dir, k.size).astype(np.int32)
+    cpu = host_cpu_info()
+    ta = time.perf_counter()
+    ref = np.zeros((k.size, nb * 8))
+    lv0 = np.zeros(sc["block_active"].size, np.int8)
+    for b in range(nb):
+        s = orc.Scene(sc, lam_idx=list(range(8 * b, 8 * b + 8)))
+        st_e = np.zeros((8, s.level_total))
+        st_c = np.zeros((8, s.level_total))
+        for il in range(8):
+            st_e[il, :s.nvox], st_c[il, :s.nvox] = orc.lines_mip0(s, il, 0)
+        s.set_static_levels(st_e, st_c)
+        ref[:, 8 * b:8 * b + 8] = orc.march(s, orc.STATIC, lv0, probes[k], d, n_threads=cpu["threads"])
+    log("prefilter: oracle reference (%d pairs x %d lambda) in %.1f s" % (k.size, nb * 8, time.perf_counter() - ta))
+    tmp = torch.empty((n_dir, 8, n_probes), dtype=torch.float32, device=dev)
+
+    def time_setting(scn, bkw, tkw):
+        scn.build(8 * spread[0], 8 * spread[0] + 8, **bkw)
+        scn.trace(dirs, out=tmp, **tkw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for b in spread:
+            scn.build(8 * b, 8 * b + 8, **bkw)
+            scn.trace(dirs, out=tmp, **tkw)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / len(spread)
+
+    settings = [("MIP 0 (no merging)", box, dict(iod_threshold=1e-2), dict(mode="level0"))]
+    for T, thin, g in ((1e-2, 0.25, 1.0), (1e-2, 0.0, 4.0), (1e-3, 0.0, 4.0), (3e-4, 0.0, 16.0)):
+        ld = [v * g for v in rt.CASCADE_LEVEL_DIST]
+        for name, scn in (("box", box), ("prefiltered", pf)):
+            settings.append(("%s T=%g thin %g grading x%g" % (name, T, thin, g), scn,
+                             dict(iod_threshold=T, tau_thin=thin), dict(mode="vlm", level_dist=ld, grade="path")))
+    errs = run_ladder(torch, np, settings, {}, {}, dirs, probes[k], d, ref, nb)
+    for name, scn, b_, t_ in settings:
+        errs[name]["ms_per_batch"] = time_setting(scn, b_, t_)
+        errs[name]["meets_bar"] = bool(errs[name]["p99.9"] <= ACCURACY_BAR)
+        log("prefilter: %-45s %.2f ms p99.9 %.3e" % (name, errs[name]["ms_per_batch"], errs[name]["p99.9"]))
+    out = {"workload": "prefilter", "config": {
+        "workload": "cfg2's scene (2D 1024^2, 16^2 bricks, 40%% active) with both lines at rest, static emission, "
+                    "4-level mip chain, 64 dirs, %d lambda, all %d probes; merged cells box-filtered (Sect. 2.1) or "
+                    "prefiltered (Sect. 5.1) on the same level maps" % (nb * 8, n_probes)},
+        "error_vs": "FP64 dense march of the same static emission (every cell at MIP 0), %d seeded (probe, direction) "
+                    "pairs" % k.size,
+        "settings": errs, "cpu": cpu}
+    print(json.dumps(out), flush=True)
 
 
 # ----------------------------------------------------------------------------- cfg4
@@ -922,20 +1066,26 @@ def bench_cfg5(args):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - ta
     loss1 = nn.loss()
-    # held-out check -> fallback map
-    fb = torch.zeros(scene.info["n_blocks"], dtype=torch.uint8, device=dev)
+    # held-out check -> one fallback map per wavelength batch: a block uses the cache in a batch only where its
+    # held-out queries (at least --nrc-min-checks rays) all pass the threshold, so a line core where the near field
+    # is thick can use the cache while its wings fall back, and no block uses it unchecked
+    fbs = [torch.zeros(scene.info["n_blocks"], dtype=torch.uint8, device=dev) for _ in range(nb)]
     held_err = []
     for b in range(nb):
+        fb = fbs[b]
+        cnt = torch.zeros(scene.info["n_blocks"], dtype=torch.int32, device=dev)
         scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage="bf16")
         tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=hd_probes[b], level_dist=level_dist,
                                    grade=args.grade)
-        _, err = nn.validate(scene, tr, THRESH, fb)
+        _, err = nn.validate(scene, tr, THRESH, fb, count=cnt)
+        nn.fallback_unverified(scene, cnt, 8 * args.nrc_min_checks, fb)
         q = (tr["feat"][..., 3] > 0)[:, None, :].expand_as(err)
         held_err.append(err[q].cpu().numpy())
     torch.cuda.synchronize()
     held_err = np.concatenate(held_err) if held_err else np.zeros(1)
-    n_flag = int(fb.sum().item())
-    log("cfg5 held-out: median %.3e p99.9 %.3e; %d blocks flagged" % (
+    act = torch.from_numpy(scene.active_blocks().astype(np.int64)).to(dev)
+    n_flag = float(np.mean([int(f[act].sum().item()) for f in fbs]))  # active blocks falling back, per batch
+    log("cfg5 held-out: median %.3e p99.9 %.3e; %.1f blocks flagged per batch" % (
         np.median(held_err), np.percentile(held_err, 99.9, method="higher"), n_flag))
     # timed solves on all probes
     kk_np = rng.choice(n_probes, min(args.pairs, n_probes), replace=False)
@@ -954,15 +1104,15 @@ def bench_cfg5(args):
 
     nrc_ev = []
 
-    def cached(gather=None, gather_cut=None, fallback=fb, record=False):
+    def cached(gather=None, gather_cut=None, fallback=fbs, record=False):
         qsum = 0
         for b in range(nb):
             scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin, storage="bf16")
             if record:
                 e0, e1 = _events(torch)
                 e0.record(stream)
-            tr = scene.trace_truncated(dirs, T_TRUNC, gen=False, fallback=fallback, level_dist=level_dist,
-                                       grade=args.grade)
+            tr = scene.trace_truncated(dirs, T_TRUNC, gen=False, fallback=None if fallback is None else fallback[b],
+                                       level_dist=level_dist, grade=args.grade)
             if record:
                 e1.record(stream)
             nn.compose(scene, tr, out=outc)
@@ -1019,7 +1169,7 @@ def bench_cfg5(args):
         "held_out_rel_err": {"n": int(held_err.size), "p50": float(np.median(held_err)),
                              "p99": float(np.percentile(held_err, 99, method="higher")),
                              "p99.9": float(np.percentile(held_err, 99.9, method="higher"))},
-        "fallback_blocks": n_flag, "fallback_block_frac": n_flag / int(sc["block_active"].sum()),
+        "fallback_active_blocks_per_batch": n_flag, "fallback_block_frac": n_flag / int(act.numel()),
         "query_ray_frac": queries / (rays * nb), "query_ray_frac_without_fallback": queries0 / (rays * nb),
         "error_vs_fp64_classic": {"plain_f32": _err(f32_np, ref), "plain_bf16": _err(g_bf16.cpu().numpy(), ref),
                                   "cache": _err(g_nrc.cpu().numpy(), ref),
@@ -1032,6 +1182,13 @@ def bench_cfg5(args):
         "cpu_baseline": {**cpu, "value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
                          "kind": "oracle", "sample": "%d pairs x %d wavelengths, FP64 dense Classic, %.1f s" % (
                              kk_np.size, nb * 8, cpu_s)}}
+    cnt = measured_counters("counters_nrc_mfma_cfg5")
+    if cnt is not None:
+        f = cnt["k_nrc_forward"]
+        out_line["roofline_nrc_forward"] = {
+            "bound": "mfma", "achieved": f["achieved_tflops"], "peak": f["peak_tflops_bf16_dense"], "unit": "TFLOP/s",
+            "frac": f["mfma_frac_of_peak"], "mfma_busy_frac": f["mfma_busy_frac"], "valu_issue_frac": f["valu_issue_frac"],
+            "counters": "profiles/counters_nrc_mfma_cfg5.json"}
     print(json.dumps(out_line), flush=True)
 
 

@@ -649,11 +649,18 @@ rt_status rt_nrc_compose(const rt_nrc* nrc, const rt_scene* scene, const float* 
 /* Held-out check on a generation-mode trace: composed prediction into d_I_pred,
  * relative error against I_near + T_near I_far into d_err (nullable), and
  * d_fallback[block of the truncation point] = 1 wherever it exceeds thresh
- * (the map is not cleared first). */
+ * (the map is not cleared first); d_count (uint32 [n_blocks], nullable, not
+ * cleared) counts the checked (query, wavelength) pairs per block.  The map
+ * drives rt_trace_truncated's per-ray fallback (nonzero = march on). */
 rt_status rt_nrc_validate(const rt_nrc* nrc, const rt_scene* scene, const float* d_dirs, int32_t n_dir,
                           int64_t n_probes, const float* d_feat, const float* d_fstat, const float* d_I_near,
                           const float* d_T_near, const float* d_I_far, float thresh, float* d_I_pred,
-                          uint8_t* d_fallback, float* d_err, void* stream);
+                          uint8_t* d_fallback, uint32_t* d_count, float* d_err, void* stream);
+/* Flags in d_fallback every block with fewer than min_queries checked pairs in
+ * d_count (from rt_nrc_validate calls): the cache is then used only where the
+ * held-out check has evidence that it passes.  Asynchronous. */
+rt_status rt_nrc_fallback_unverified(const rt_scene* scene, const uint32_t* d_count, int32_t min_queries,
+                                     uint8_t* d_fallback, void* stream);
 
 /* Device error counters accumulated by traces of this scene (ordered on `stream`, synchronises it); reset
  * clears them. */

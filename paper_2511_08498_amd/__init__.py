@@ -36,7 +36,7 @@ EXPORTS = (
     "rt_nrc_get_weights", "rt_nrc_set_weights", "rt_nrc_pack", "rt_nrc_train", "rt_nrc_loss", "rt_nrc_gradients",
     "rt_nrc_predict", "rt_nrc_compose", "rt_nrc_validate", "rt_scene_workspace_bytes", "rt_nrc_workspace_bytes",
     "rt_trace_j", "rt_trace_j_workspace_bytes", "rt_trace_j_noalloc", "rt_trace_interval", "rt_nrc_get_state", "rt_nrc_set_state",
-    "rt_scene_count_active", "rt_batch_workspace_bytes",
+    "rt_scene_count_active", "rt_batch_workspace_bytes", "rt_nrc_fallback_unverified",
 )
 _VOID = ("rt_scene_destroy", "rt_last_error", "rt_version", "rt_batch_destroy", "rt_graph_destroy", "rt_nrc_destroy")
 
@@ -167,7 +167,8 @@ def lib():
     L.rt_nrc_gradients.argtypes = [_P, _P, _P, i64, _P, _P]
     L.rt_nrc_predict.argtypes = [_P, _P, i64, _P, _P]
     L.rt_nrc_compose.argtypes = [_P, _P, _P, i32, i64, _P, _P, _P, _P, _P, _P]
-    L.rt_nrc_validate.argtypes = [_P, _P, _P, i32, i64, _P, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P]
+    L.rt_nrc_validate.argtypes = [_P, _P, _P, i32, i64, _P, _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P, _P]
+    L.rt_nrc_fallback_unverified.argtypes = [_P, _P, i32, _P, _P]
     L.rt_last_error.restype = ctypes.c_char_p
     L.rt_version.restype = ctypes.c_char_p
     for name in EXPORTS:
@@ -818,17 +819,25 @@ class Nrc:
                                     _stream(stream)))
         return out
 
-    def validate(self, scene, tr, thresh, fallback, stream=None):
+    def validate(self, scene, tr, thresh, fallback, count=None, stream=None):
         """Held-out check of a generation-mode trace: (prediction, relative error); flags
-        fallback[block] for blocks whose queries exceed thresh."""
+        fallback[block] for blocks whose queries exceed thresh and counts the checks per block
+        (count: device int32/uint32 [n_blocks], optional)."""
         pred = self.torch.empty_like(tr["I_near"])
         err = self.torch.empty_like(tr["I_near"])
         _check(lib().rt_nrc_validate(self.h, scene.h, tr["dirs"].data_ptr(), int(tr["dirs"].shape[0]),
                                      int(tr["n_probes"]), tr["feat"].data_ptr(), tr["fstat"].data_ptr(),
                                      tr["I_near"].data_ptr(), tr["T_near"].data_ptr(), tr["I_far"].data_ptr(),
-                                     float(thresh), pred.data_ptr(), fallback.data_ptr(), err.data_ptr(),
+                                     float(thresh), pred.data_ptr(), fallback.data_ptr(),
+                                     count.data_ptr() if count is not None else None, err.data_ptr(),
                                      _stream(stream)))
         return pred, err
+
+    @staticmethod
+    def fallback_unverified(scene, count, min_queries, fallback, stream=None):
+        """Flags the blocks with fewer than min_queries held-out checks (rt_nrc_fallback_unverified)."""
+        _check(lib().rt_nrc_fallback_unverified(scene.h, count.data_ptr(), int(min_queries), fallback.data_ptr(),
+                                                _stream(stream)))
 
 
 def nrc_workspace_bytes(max_batch=65536, freq_max=64.0, seed=0):

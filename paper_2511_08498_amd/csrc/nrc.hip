@@ -505,7 +505,7 @@ __global__ void k_nrc_pack(NrcPack a)
 // blocks whose rows exceed the threshold fall back to the full march
 __global__ void k_nrc_validate(const float* I_pred, const float* I_near, const float* T_near, const float* I_far,
                                const float4* feat, long long n_dir, int nl, long long np, long long n_blocks,
-                               float thresh, uint8_t* fallback, float* err_out)
+                               float thresh, uint8_t* fallback, unsigned* count, float* err_out)
 {
     long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     long long rows = n_dir * nl * np;
@@ -516,10 +516,21 @@ __global__ void k_nrc_validate(const float* I_pred, const float* I_near, const f
     float Itrue = fmaf(T_near[q], I_far[q], I_near[q]);
     float e = f.w > 0.f ? fabsf(I_pred[q] - Itrue) / fmaxf(fabsf(Itrue), 1e-37f) : 0.f;
     if (err_out) err_out[q] = e;
-    if (f.w > 0.f && e > thresh) {
-        long long blk = (long long)f.w - 1;  // block of the truncation point, recorded by the march
-        if (blk >= 0 && blk < n_blocks) fallback[blk] = 1;
+    if (f.w > 0.f) {
+        const long long blk = (long long)f.w - 1;  // block of the truncation point, recorded by the march
+        if (blk >= 0 && blk < n_blocks) {
+            if (e > thresh) fallback[blk] = 1;
+            if (count) atomicAdd(&count[blk], 1u);  // one per (query, wavelength)
+        }
     }
+}
+
+// Blocks with fewer than min_queries held-out checks fall back too: the cache is
+// used only where the check has evidence that it passes.
+__global__ void k_nrc_unverified(const unsigned* count, unsigned min_queries, long long n_blocks, uint8_t* fallback)
+{
+    const long long b = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n_blocks && count[b] < min_queries) fallback[b] = 1;
 }
 
 }  // namespace rt
@@ -911,8 +922,8 @@ rt_status rt_nrc_compose(const rt_nrc* nn, const rt_scene* sc, const float* d_di
 
 rt_status rt_nrc_validate(const rt_nrc* nn, const rt_scene* sc, const float* d_dirs, int32_t n_dir, int64_t n_probes,
                           const float* d_feat, const float* d_fstat, const float* d_I_near, const float* d_T_near,
-                          const float* d_I_far, float thresh, float* d_I_pred, uint8_t* d_fallback, float* d_err,
-                          void* stream)
+                          const float* d_I_far, float thresh, float* d_I_pred, uint8_t* d_fallback, uint32_t* d_count,
+                          float* d_err, void* stream)
 {
     if (!nn || !sc || !d_I_far || !d_I_pred || !d_fallback) return set_error(RT_E_ARG, "null argument");
     rt_status st = rt_nrc_compose(nn, sc, d_dirs, n_dir, n_probes, d_feat, d_fstat, d_I_near, d_T_near, d_I_pred, stream);
@@ -921,7 +932,19 @@ rt_status rt_nrc_validate(const rt_nrc* nn, const rt_scene* sc, const float* d_d
     long long rows = (long long)n_dir * nl * n_probes;
     hipLaunchKernelGGL(k_nrc_validate, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, (hipStream_t)stream, d_I_pred,
                        d_I_near, d_T_near, d_I_far, (const float4*)d_feat, (long long)n_dir, nl, (long long)n_probes,
-                       (long long)sc->g.nblocks, thresh, d_fallback, d_err);
+                       (long long)sc->g.nblocks, thresh, d_fallback, d_count, d_err);
+    NRC_HIP(hipGetLastError());
+    return RT_OK;
+}
+
+rt_status rt_nrc_fallback_unverified(const rt_scene* sc, const uint32_t* d_count, int32_t min_queries,
+                                     uint8_t* d_fallback, void* stream)
+{
+    if (!sc || !d_count || !d_fallback) return set_error(RT_E_ARG, "null argument");
+    if (min_queries < 1) return set_error(RT_E_ARG, "min_queries must be >= 1");
+    const long long nb = sc->g.nblocks;
+    hipLaunchKernelGGL(k_nrc_unverified, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       d_count, (unsigned)min_queries, nb, d_fallback);
     NRC_HIP(hipGetLastError());
     return RT_OK;
 }

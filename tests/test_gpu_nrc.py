@@ -297,3 +297,14 @@ def test_cache_compose_validate_and_gain(rt, setup):
     e = err.cpu().numpy()
     bad = (e > 5e-3) & np.broadcast_to((ft[..., 3] > 0)[:, None, :], full.shape)
     assert np.all(np.broadcast_to(flagged[blk][:, None, :], full.shape)[bad])
+    # checks per block are counted, and blocks with fewer than min_queries checks fall back too
+    cnt = torch.zeros(scene.info["n_blocks"], dtype=torch.int32, device="cuda")
+    fb2 = torch.zeros_like(fb)
+    nn.validate(scene, gen, 5e-3, fb2, count=cnt)
+    q = ft[..., 3] > 0
+    want = np.bincount(blk[q], minlength=scene.info["n_blocks"]) * full.shape[1]  # one per (query, wavelength)
+    assert np.array_equal(cnt.cpu().numpy(), want)
+    assert torch.equal(fb2, fb)
+    k = 3 * full.shape[1]
+    nn.fallback_unverified(scene, cnt, k, fb2)
+    assert np.array_equal(fb2.cpu().numpy().astype(bool), flagged | (want < k))
