@@ -53,27 +53,28 @@ HBM_PEAK = 8.0e12  # B/s
 CPU_SHARE = 16  # host cores allotted to one GPU's job
 VALU_ISSUE_PEAK = 256 * 2.4e9  # wave64 VALU instructions per second: 256 CUs x 1 per clock (4 SIMD16, non-packed)
 MARCH_SOURCES = ("march.hip", "common.h", "profile.h")
+NRC_SOURCES = ("nrc.hip", "scene_impl.h", "common.h")
 
 
-def march_source_hash():
-    """SHA-256 over the sources the march kernels are compiled from."""
+def march_source_hash(sources=MARCH_SOURCES):
+    """SHA-256 over the sources the march kernels (or the given ones) are compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for f in MARCH_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, "paper_2511_08498_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_counters(name, setting=None):
-    """Counter summary profiles/<name>.json if it was taken on the current march sources (and, when given, the
-    same workload setting), else None."""
+def measured_counters(name, setting=None, sources=MARCH_SOURCES):
+    """Counter summary profiles/<name>.json if it was taken on the current sources of its kernel (and, when
+    given, the same workload setting), else None."""
     path = os.path.join(ROOT, "profiles", name + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         c = json.load(fh)
-    if c.get("march_source_sha256") != march_source_hash():
+    if c.get("source_sha256", c.get("march_source_sha256")) != march_source_hash(sources):
         return None
     if setting is not None and c.get("setting") != setting:
         return None
@@ -1182,7 +1183,7 @@ def bench_cfg5(args):
         "cpu_baseline": {**cpu, "value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
                          "kind": "oracle", "sample": "%d pairs x %d wavelengths, FP64 dense Classic, %.1f s" % (
                              kk_np.size, nb * 8, cpu_s)}}
-    cnt = measured_counters("counters_nrc_mfma_cfg5")
+    cnt = measured_counters("counters_nrc_mfma_cfg5", sources=NRC_SOURCES)
     if cnt is not None:
         f = cnt["k_nrc_forward"]
         out_line["roofline_nrc_forward"] = {

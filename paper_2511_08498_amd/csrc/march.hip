@@ -66,25 +66,48 @@ struct Counters {
     unsigned segs, empty, lvlchg;
 };
 
+// The level_dist table of a traversal, held in registers (the traversal reads it at
+// every block change; a memory read there would wait for every load in flight).
+struct LevelDist {
+    float v[kMaxLevels];
+    __device__ __forceinline__ explicit LevelDist(const float* ld)
+    {
+#pragma unroll
+        for (int m = 0; m < kMaxLevels; ++m) v[m] = ld[m];
+    }
+    // v[k] for 0 <= k < nlev, else +inf (a select chain: no indexed register access)
+    __device__ __forceinline__ float at(int k, int nlev) const
+    {
+        float r = INFINITY;
+#pragma unroll
+        for (int m = 0; m < kMaxLevels; ++m) r = (k == m && m < nlev) ? v[m] : r;
+        return r;
+    }
+};
+
 // Distance-graded cap at a block entered at t = d2 / (2 |w_s|): the largest m
 // with level_dist[1..m] <= t, decided exactly as d2/2 >= level_dist[m] |w_s|.
-__device__ __forceinline__ int graded_cap(const float* ld, int nlev, double d2, double aws)
+__device__ __forceinline__ int graded_cap(const LevelDist& ld, int nlev, double d2, double aws)
 {
     int cap = 0;
-    for (int m = 1; m < nlev; ++m) {
-        if (!(d2 * 0.5 >= (double)ld[m] * aws)) break;
-        cap = m;
+    bool go = true;
+#pragma unroll
+    for (int m = 1; m < kMaxLevels; ++m) {
+        go = go && m < nlev && d2 * 0.5 >= (double)ld.v[m] * aws;
+        cap = go ? m : cap;
     }
     return cap;
 }
 
 // Path-graded cap at path length t: the largest m with ld[1..m] <= t.
-__device__ __forceinline__ int path_cap(const float* ld, int nlev, double t)
+__device__ __forceinline__ int path_cap(const LevelDist& ld, int nlev, double t)
 {
     int cap = 0;
-    for (int m = 1; m < nlev; ++m) {
-        if (!((double)ld[m] <= t)) break;
-        cap = m;
+    bool go = true;
+#pragma unroll
+    for (int m = 1; m < kMaxLevels; ++m) {
+        go = go && m < nlev && (double)ld.v[m] <= t;
+        cap = go ? m : cap;
     }
     return cap;
 }
@@ -124,9 +147,10 @@ __device__ __forceinline__ bool mip0_coord(int pva, int st, double aw, double t,
 // grid and 4 when the ray had left the grid by t_lo (no segment).
 template <int D, bool Iv = false, class Vis>
 __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode, int maxl, int graded,
-                                    const float* ld, const int* pv, const float* wf, int step_cap, Vis& vis,
+                                    const float* ldp, const int* pv, const float* wf, int step_cap, Vis& vis,
                                     Counters& cnt, double t_lo = 0.0, double t_hi = 0.0)
 {
+    const LevelDist ld(ldp);
     // Per axis: the doubled centre p2 = 2 p (odd), the step sign st, the cell c at the current
     // level (size vs); the next plane is k = c + (st > 0 ? vs : 0), and dd = |p2 - 2 k| (twice the
     // distance to it) is kept exactly.  |w_a| is kept in FP32 (exact when widened to FP64).
@@ -164,7 +188,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
     float tb = INFINITY;  // a level_dist value (FP32, exact in FP64)
     if (graded == 2) {
         capp = path_cap(ld, g.n_levels, t);
-        tb = capp + 1 < g.n_levels ? ld[capp + 1] : INFINITY;
+        tb = ld.at(capp + 1, g.n_levels);
     }
     long long blk = block_of<D>(g, c0);
     int cap0 = maxl;
@@ -189,10 +213,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             }
             cg = graded_cap(ld, g.n_levels, dn, an);
         } else {
-            for (int m = 1; m < g.n_levels; ++m) {
-                if (!(ld[m] <= 0.f)) break;
-                cg = m;
-            }
+            cg = path_cap(ld, g.n_levels, 0.0);
         }
         cap0 = cg < maxl ? cg : maxl;
     }
@@ -267,7 +288,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             // which lies in the current cell
             t = te;
             capp = path_cap(ld, g.n_levels, t);
-            tb = capp + 1 < g.n_levels ? ld[capp + 1] : INFINITY;
+            tb = ld.at(capp + 1, g.n_levels);
             const int nl = lraw < capp ? lraw : capp;
             ++cnt.lvlchg;
             const int nvs = 1 << nl;
@@ -302,7 +323,7 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             if (graded == 2) {
                 // the path cap at the crossing (exact), and the new block's level under it
                 capp = graded_cap(ld, g.n_levels, d2s0, aws);
-                tb = capp + 1 < g.n_levels ? ld[capp + 1] : INFINITY;
+                tb = ld.at(capp + 1, g.n_levels);
                 lraw = block_level(sts, blk, mode, maxl);
                 nl = lraw < capp ? lraw : capp;
             } else {
@@ -364,20 +385,36 @@ __device__ __forceinline__ float rte_step(float& I, float& Tr, float eta, float 
     return e;
 }
 
+// A node record as loaded (kLam (eta, chi) pairs: 64 B in FP32, 32 B in BF16 / FP16), decoded to
+// FP32 separately so a pipelined visitor can keep the raw words in flight.
 template <typename T>
-__device__ __forceinline__ void load_rec(const T* r, float* e, float* c);
+struct RawRec {
+    uint4 q[kLam * 2 * sizeof(T) / 16];
+};
+
+template <typename T>
+__device__ __forceinline__ RawRec<T> fetch_rec(const T* r)
+{
+    RawRec<T> o;
+    const uint4* r4 = (const uint4*)r;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(o.q) / sizeof(uint4)); ++i) o.q[i] = r4[i];
+    return o;
+}
+
+template <typename T>
+__device__ __forceinline__ void decode_rec(const RawRec<T>& raw, float* e, float* c);
 
 template <>
-__device__ __forceinline__ void load_rec<float>(const float* r, float* e, float* c)
+__device__ __forceinline__ void decode_rec<float>(const RawRec<float>& raw, float* e, float* c)
 {
-    const float4* r4 = (const float4*)r;
 #pragma unroll
     for (int q = 0; q < kLam / 2; ++q) {
-        float4 v = r4[q];
-        e[2 * q] = v.x;
-        c[2 * q] = v.y;
-        e[2 * q + 1] = v.z;
-        c[2 * q + 1] = v.w;
+        const uint4 v = raw.q[q];
+        e[2 * q] = __uint_as_float(v.x);
+        c[2 * q] = __uint_as_float(v.y);
+        e[2 * q + 1] = __uint_as_float(v.z);
+        c[2 * q + 1] = __uint_as_float(v.w);
     }
 }
 
@@ -385,13 +422,12 @@ __device__ __forceinline__ float bf16_lo(unsigned u) { return __uint_as_float(u 
 __device__ __forceinline__ float bf16_hi(unsigned u) { return __uint_as_float(u & 0xffff0000u); }
 
 template <>
-__device__ __forceinline__ void load_rec<__hip_bfloat16>(const __hip_bfloat16* r, float* e, float* c)
+__device__ __forceinline__ void decode_rec<__hip_bfloat16>(const RawRec<__hip_bfloat16>& raw, float* e, float* c)
 {
-    const uint4* r4 = (const uint4*)r;
 #pragma unroll
     for (int q = 0; q < kLam / 4; ++q) {
-        uint4 v = r4[q];
-        unsigned u[4] = {v.x, v.y, v.z, v.w};
+        const uint4 v = raw.q[q];
+        const unsigned u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             e[4 * q + j] = bf16_lo(u[j]);
@@ -401,12 +437,11 @@ __device__ __forceinline__ void load_rec<__hip_bfloat16>(const __hip_bfloat16* r
 }
 
 template <>
-__device__ __forceinline__ void load_rec<__half>(const __half* r, float* e, float* c)
+__device__ __forceinline__ void decode_rec<__half>(const RawRec<__half>& raw, float* e, float* c)
 {
-    const uint4* r4 = (const uint4*)r;
 #pragma unroll
     for (int q = 0; q < kLam / 4; ++q) {
-        uint4 v = r4[q];
+        const uint4 v = raw.q[q];
         unsigned u[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -416,6 +451,12 @@ __device__ __forceinline__ void load_rec<__half>(const __half* r, float* e, floa
             c[4 * q + j] = f.y;
         }
     }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rec(const T* r, float* e, float* c)
+{
+    decode_rec<T>(fetch_rec<T>(r), e, c);
 }
 
 // First cell of level lvl inside a block record, unpacked from the launch's
@@ -430,11 +471,20 @@ __device__ __forceinline__ int level_offset(const Geo& g, int lvl)
 // table (placed after the state words) on small grids, else from global memory.
 __device__ __forceinline__ long long block_slot(const Geo& g, const int32_t* slot, int lds, long long blk)
 {
+    // Each branch completes its own read (the empty asm takes the value as an operand), so the LDS
+    // branch never waits on vector-memory loads in flight (the node records a pipelined visitor has
+    // issued); the explicit LDS pointer keeps the two reads from merging into one generic read.
+    int32_t v;
     if (lds) {
         extern __shared__ uint64_t lds_words[];
-        return ((const int32_t*)(lds_words + g.n_state_words))[blk];
+        typedef __attribute__((address_space(3))) const int32_t LdsI32;
+        v = ((const LdsI32*)(lds_words + g.n_state_words))[blk];
+        asm volatile("; slot from LDS" : "+v"(v));
+    } else {
+        v = slot[blk];
+        asm volatile("; slot from global memory" : "+v"(v));
     }
-    return slot[blk];
+    return v;
 }
 
 // Copies the block-state words, and on small grids the slot table, to LDS.
@@ -501,10 +551,15 @@ struct AccPlain {
     __device__ __forceinline__ bool add(const float* e, const float* x, const int*, int, long long, double t0,
                                         double t1, float dsf)
     {
-        const SegK k((float)(t1 - t0) * dsf);
+        add_dt(e, x, (float)(t1 - t0) * dsf);
+        return false;
+    }
+    // the same update for a segment of length dt (in units of ds0 already applied)
+    __device__ __forceinline__ void add_dt(const float* e, const float* x, float dt)
+    {
+        const SegK k(dt);
 #pragma unroll
         for (int l = 0; l < kLam; ++l) rte_step(I[l], Tr[l], e[l], x[l], k);
-        return false;
     }
 };
 
@@ -655,6 +710,9 @@ template <int D, typename T, class Acc = AccPlain>
 struct VisStatic {
     using AccT = Acc;
     static constexpr int kMinWaves = (!Acc::kTrunc && !Acc::kJ) ? 4 : 1;
+    // the same one-segment software pipeline as the velocity-interpolation visitor (plain and interval
+    // accumulators): a cell's record is loaded at its visit and applied at the next one or in finish()
+    static constexpr bool kPipe = !Acc::kTrunc && !Acc::kJ;
     const Geo* g;
     const int32_t* slot;
     const T* vals;
@@ -662,6 +720,8 @@ struct VisStatic {
     long long base;
     float dsf;
     int slot_lds;
+    RawRec<T> pr;  // pending segment's record, as loaded
+    float pdt;     // its length
     Acc acc;
     __device__ void init_src(const Geo* geo, const int32_t* sl, const void* v, float ds0)
     {
@@ -672,12 +732,25 @@ struct VisStatic {
         base = 0;
         dsf = ds0;
         slot_lds = 0;
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(pr.q) / sizeof(uint4)); ++i) pr.q[i] = make_uint4(0u, 0u, 0u, 0u);
+        pdt = 0.f;
     }
     __device__ void init(const TraceLaunch* t, const float*)
     {
         init_src(&t->g, t->slot, t->vals, t->ds0);
         slot_lds = t->slot_lds;
         acc.init(t);
+    }
+    __device__ __forceinline__ void apply_pending()
+    {
+        float e[kLam], x[kLam];
+        decode_rec<T>(pr, e, x);
+        acc.add_dt(e, x, pdt);
+    }
+    __device__ __forceinline__ void finish()
+    {
+        if constexpr (kPipe) apply_pending();
     }
     __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
     {
@@ -686,9 +759,16 @@ struct VisStatic {
             base = block_slot(*g, slot, slot_lds, blk) * g->cells;
         }
         const T* r = vals + (base + level_offset(*g, lvl) + local_index(*g, c, lvl, D)) * (kLam * 2);
-        float e[kLam], x[kLam];
-        load_rec<T>(r, e, x);
-        return acc.add(e, x, c, lvl, blk, t0, t1, dsf);
+        if constexpr (kPipe) {
+            apply_pending();
+            pr = fetch_rec<T>(r);
+            pdt = (float)(t1 - t0) * dsf;
+            return false;
+        } else {
+            float e[kLam], x[kLam];
+            load_rec<T>(r, e, x);
+            return acc.add(e, x, c, lvl, blk, t0, t1, dsf);
+        }
     }
 };
 
@@ -761,6 +841,13 @@ template <int D, typename T = float, class Acc = AccPlain>
 struct VisVelinterp {
     using AccT = Acc;
     static constexpr int kMinWaves = (D == 2 && !Acc::kTrunc && !Acc::kJ) ? 4 : 1;
+    // Plain and interval accumulators take a one-segment software pipeline: a segment's node records
+    // are loaded when it is visited and applied at the next visit (or in finish()), so their latency
+    // overlaps the traversal step in between, and the next cell's node coordinate is read before the
+    // pending update, which overlaps that read.  Segments are applied in order with the same
+    // arithmetic; the pipeline starts with a zero-length, zero-valued segment, which leaves I and T
+    // unchanged bit for bit (tau = 0 takes the series branch: h = 0, exp(-0) = 1).
+    static constexpr bool kPipe = !Acc::kTrunc && !Acc::kJ;
     const TraceLaunch* tl;
     const float4* vgrid;
     const T* vnodes;
@@ -768,6 +855,8 @@ struct VisVelinterp {
     long long base;
     float dsf;
     float w[3];
+    RawRec<T> pr0, pr1;  // pending segment's two node records, as loaded
+    float pwt, pdt;      // its interpolation weight and length
     Acc acc;
     __device__ void init(const TraceLaunch* t, const float* wf)
     {
@@ -783,7 +872,27 @@ struct VisVelinterp {
         const long long ncell_all = (long long)t->n_active * t->g.cells;
         vgrid = t->vgrid + q * ncell_all;
         vnodes = (const T*)t->vnodes + q * ncell_all * t->n_v * (kLam * 2);
+#pragma unroll
+        for (int i = 0; i < (int)(sizeof(pr0.q) / sizeof(uint4)); ++i) pr0.q[i] = pr1.q[i] = make_uint4(0u, 0u, 0u, 0u);
+        pwt = pdt = 0.f;
         acc.init(t);
+    }
+    __device__ __forceinline__ void apply_pending()
+    {
+        float e0[kLam], x0[kLam], e1[kLam], x1[kLam], ee[kLam], xx[kLam];
+        decode_rec<T>(pr0, e0, x0);
+        decode_rec<T>(pr1, e1, x1);
+#pragma unroll
+        for (int l = 0; l < kLam; ++l) {
+            ee[l] = fmaf(pwt, e1[l] - e0[l], e0[l]);
+            xx[l] = fmaf(pwt, x1[l] - x0[l], x0[l]);
+        }
+        acc.add_dt(ee, xx, pdt);
+    }
+    // applies the last pending segment (called once the traversal has ended)
+    __device__ __forceinline__ void finish()
+    {
+        if constexpr (kPipe) apply_pending();
     }
     __device__ __forceinline__ bool seg(const int* c, int lvl, long long blk, double t0, double t1)
     {
@@ -796,6 +905,7 @@ struct VisVelinterp {
         // node coordinate f = g . w + off = (vbar . w - lo) (n_v - 1) / (hi - lo) over the cell's range
         // [lo, hi] of projected velocities (g = off = 0 for an empty range: node 0 is used)
         float4 vg = vgrid[cell];
+        if constexpr (kPipe) apply_pending();
         float f = fmaf(vg.x, w[0], fmaf(vg.y, w[1], vg.w));
         if (D > 2) f = fmaf(vg.z, w[2], f);
         const int nv = tl->n_v;
@@ -806,18 +916,37 @@ struct VisVelinterp {
         // around u are one plane apart
         const unsigned cells = (unsigned)tl->g.cells;
         const T* r0 = vnodes + ((unsigned)base * (unsigned)nv + (unsigned)kn * cells + cellin) * (unsigned)(kLam * 2);
-        float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
-        load_rec<T>(r0, e0, x0);
-        load_rec<T>(r0 + cells * (unsigned)(kLam * 2), e1, x1);
-        float ee[kLam], xx[kLam];
+        if constexpr (kPipe) {
+            pr0 = fetch_rec<T>(r0);
+            pr1 = fetch_rec<T>(r0 + cells * (unsigned)(kLam * 2));
+            pwt = wt;
+            pdt = (float)(t1 - t0) * dsf;
+            return false;
+        } else {
+            float e0[kLam], x0[kLam], e1[kLam], x1[kLam];
+            load_rec<T>(r0, e0, x0);
+            load_rec<T>(r0 + cells * (unsigned)(kLam * 2), e1, x1);
+            float ee[kLam], xx[kLam];
 #pragma unroll
-        for (int l = 0; l < kLam; ++l) {
-            ee[l] = fmaf(wt, e1[l] - e0[l], e0[l]);
-            xx[l] = fmaf(wt, x1[l] - x0[l], x0[l]);
+            for (int l = 0; l < kLam; ++l) {
+                ee[l] = fmaf(wt, e1[l] - e0[l], e0[l]);
+                xx[l] = fmaf(wt, x1[l] - x0[l], x0[l]);
+            }
+            return acc.add(ee, xx, c, lvl, blk, t0, t1, dsf);
         }
-        return acc.add(ee, xx, c, lvl, blk, t0, t1, dsf);
     }
 };
+
+// Ends a traversal: visitors with a pending (software-pipelined) segment apply it.
+template <class V>
+__device__ __forceinline__ auto finish_visit(V& v, int) -> decltype(v.finish(), void())
+{
+    v.finish();
+}
+template <class V>
+__device__ __forceinline__ void finish_visit(V&, long)
+{
+}
 
 // NL: lines the kernel is compiled for (2 or kMaxLines); scenes with up to two
 // lines use NL = 2, which halves the per-segment line state and code.
@@ -961,6 +1090,7 @@ __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* 
     constexpr bool kIv = Vis::AccT::kIv;
     int rc = hdda<D, kIv>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt,
                           t.t_lo, t.t_hi);
+    finish_visit(vis, 0);
     int capped = rc == 1;
     const int nl = t.lb.nl;
     if constexpr (kIv) {
@@ -1126,6 +1256,7 @@ __global__ void __launch_bounds__(256) k_trace_j(TraceLaunch t)
         vis.init(&t, wf);
         Counters cnt = {0, 0, 0};
         const int rc = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+        finish_visit(vis, 0);
         if (rc == 1) {
             atomicAdd(&t.err[0], 1ull);
             atomicMin(&t.err[1], (unsigned long long)(dir * t.n_probes + probe));
@@ -1325,6 +1456,7 @@ __device__ __forceinline__ void batched_ray(const BatchJob& J, long long dir, lo
     vis.acc.init(nullptr);
     Counters cnt = {0, 0, 0};
     int capped = hdda<D>(J.g, J.states, J.mode, J.max_level, J.graded, J.level_dist, pv, wf, J.step_cap, vis, cnt) == 1;
+    finish_visit(vis, 0);
 #pragma unroll
     for (int l = 0; l < kLam; ++l)
         if (l < J.nl) J.I[((long long)dir * J.nl + l) * J.n_probes + probe] = fmaf(vis.acc.Tr[l], J.I0, vis.acc.I[l]);

@@ -46,27 +46,36 @@ constexpr int kParamsPadded = (kNParams + 255) & ~255;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float silu(float z) { return z / (1.0f + __expf(-z)); }
+// SiLU and its derivative with the hardware reciprocal (1 ulp): the activations are rounded to BF16
+// (2^-8) before every use, so a correctly rounded division would buy nothing but instructions.
+__device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 __device__ __forceinline__ float silu_grad(float z)
 {
-    float s = 1.0f / (1.0f + __expf(-z));
+    float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
     return s * (1.0f + z * (1.0f - s));
 }
 
-// Encoded input value k of a query with raw features r (pos 3, dir 3, lam, stats 4).
-__device__ __forceinline__ float encode(const float* r, int k, float lg2fmax)
+// Encoded inputs k0 .. k0 + 7 (k0 = 32 ks + 8 g) of a query with raw features r (pos 3, dir 3, lam,
+// stats 4): for ks < 7 the sine and cosine of 2 pi f_j r[ks] at the four frequencies j = 4 g + p
+// (fr[p] = f_j, the lane's own, computed once), interleaved sin, cos; for ks = 7 the raw statistics,
+// then zeros.  The angle is reduced to whole turns, and the hardware sine and cosine take turns.
+__device__ __forceinline__ bf16x8 encode8(const float* r, int ks, int g, const float* fr, bool valid)
 {
-    if (k < 224) {
-        int q = k >> 5, j = (k & 31) >> 1;
-        float f = exp2f((float)j * lg2fmax * (1.0f / 15.0f));
-        // reduce to whole turns before the (fast) sine and cosine
-        float turns = f * r[q];
-        turns -= rintf(turns);
-        float arg = 6.283185307179586f * turns;
-        return (k & 1) ? __cosf(arg) : __sinf(arg);
+    bf16x8 av;
+    if (ks < 7) {
+        const float x = r[ks];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            float turns = fr[p] * x;
+            turns -= rintf(turns);
+            av[2 * p] = (__bf16)(valid ? __builtin_amdgcn_sinf(turns) : 0.f);
+            av[2 * p + 1] = (__bf16)(valid ? __builtin_amdgcn_cosf(turns) : 0.f);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) av[j] = (__bf16)((valid && g == 0 && j < 4) ? r[7 + j] : 0.f);
     }
-    if (k < 228) return r[7 + (k - 224)];
-    return 0.0f;
+    return av;
 }
 
 // ----------------------------------------------------------- forward pass
@@ -177,11 +186,15 @@ __device__ __forceinline__ bool row_queried(const NrcFwd& a, long long row)
     return a.feat[d * a.np + p].w > 0.f;
 }
 
-__global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
+// Eight waves per workgroup share one LDS copy of the hidden weights (72 KiB with the per-wave
+// activation tiles), so two workgroups fit a CU: four waves per SIMD.
+constexpr int kFwdWaves = 8;
+
+__global__ void __launch_bounds__(64 * kFwdWaves) k_nrc_forward(NrcFwd a)
 {
     __shared__ __attribute__((aligned(16))) __bf16 sW1[kHid * kFeat];
     __shared__ __attribute__((aligned(16))) __bf16 sW[3][kHid * kHid];
-    __shared__ __attribute__((aligned(16))) __bf16 sH[4][16 * kHid];
+    __shared__ __attribute__((aligned(16))) __bf16 sH[kFwdWaves][16 * kHid];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     {
         const uint4* src = (const uint4*)(a.wb + kOffW1);
@@ -206,14 +219,17 @@ __global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
         w5[nt] = a.wf[kOffW5 + c];
     }
     const float b5 = a.wf[kOffB5];
+    // the lane's four encoding frequencies f_j = fmax^(j / 15), j = 4 g + p
+    float fr[4];
+    for (int p = 0; p < 4; ++p) fr[p] = exp2f((float)(4 * g + p) * a.lg2fmax * (1.0f / 15.0f));
     float lsum = 0.f;
     const long long n_tiles = (a.rows + 15) / 16;
-    const long long wstride = (long long)gridDim.x * 4;
+    const long long wstride = (long long)gridDim.x * kFwdWaves;
     // inference-compose: a wave first checks 64 rows (one per lane); a group without any query
     // (rays that left the grid or fell back) is copied whole, a group with one runs its 4 tiles
     const bool grouped = a.mode == 1;
     const long long n_items = grouped ? (a.rows + 63) / 64 : n_tiles;
-    for (long long item = (long long)blockIdx.x * 4 + wv; item < n_items; item += wstride) {
+    for (long long item = (long long)blockIdx.x * kFwdWaves + wv; item < n_items; item += wstride) {
         int n_sub = 1;
         long long tile0 = item;
         if (grouped) {
@@ -240,9 +256,8 @@ __global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
             f32x4 acc[4];
             for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int ks = 0; ks < kFeat / 32; ++ks) {
-                bf16x8 av;
                 const int k0 = 32 * ks + 8 * g;
-                for (int j = 0; j < 8; ++j) av[j] = (__bf16)(valid ? encode(r, k0 + j, a.lg2fmax) : 0.f);
+                const bf16x8 av = encode8(r, ks, g, fr, valid);
                 if (a.mode == 0 && a.x_out && valid) *(bf16x8*)(a.x_out + row_a * kFeat + k0) = av;
                 for (int nt = 0; nt < 4; ++nt) {
                     bf16x8 bv = *(const bf16x8*)(sW1 + (16 * nt + r16) * kFeat + k0);
@@ -323,13 +338,17 @@ __global__ void __launch_bounds__(256) k_nrc_forward(NrcFwd a)
         float* wsum = (float*)&sH[0][0];
         if (lane == 0) wsum[wv] = lsum;
         __syncthreads();
-        if (tid == 0) a.loss_part[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        if (tid == 0) {
+            float t = 0.f;
+            for (int i = 0; i < kFwdWaves; ++i) t += wsum[i];
+            a.loss_part[blockIdx.x] = t;
+        }
     }
 }
 
 hipError_t launch_nrc_forward(const NrcFwd& a, int n_wgs, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_nrc_forward, dim3((unsigned)n_wgs), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_nrc_forward, dim3((unsigned)n_wgs), dim3(64 * kFwdWaves), 0, s, a);
     return hipGetLastError();
 }
 
