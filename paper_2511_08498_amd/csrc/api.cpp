@@ -124,7 +124,7 @@ static rt_status check_desc(const rt_scene_desc* d, const rt_scene_inputs* inp)
 // LDS a trace workgroup stages: the packed block states, and the slot table on grids of <= kSlotLdsMax blocks.
 static long long trace_lds_bytes(const Geo& g)
 {
-    return 8ll * g.n_state_words + (g.nblocks <= kSlotLdsMax ? 4ll * g.nblocks : 0ll);
+    return 8ll * g.n_state_words + (g.nblocks <= kSlotLdsMax ? 4ll * g.nblocks : 0ll) + 4ll * kMaxLevels;
 }
 
 static void make_geo(const rt_scene_desc* d, Geo& g)

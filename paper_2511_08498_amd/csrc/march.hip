@@ -145,12 +145,19 @@ __device__ __forceinline__ bool mip0_coord(int pva, int st, double aw, double t,
 // ray moves into), the last segment ends at t_hi, and a plane crossed exactly
 // at t_hi belongs to this interval.  Returns 3 when t_hi was reached inside the
 // grid and 4 when the ray had left the grid by t_lo (no segment).
-template <int D, bool Iv = false, class Vis>
+// LdDemand: ldp is the workgroup's LDS copy of level_dist, read where it is needed (start, cap rises,
+// block changes) rather than held in registers for the whole traversal.
+template <int D, bool Iv = false, bool LdDemand = false, class Vis>
 __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode, int maxl, int graded,
                                     const float* ldp, const int* pv, const float* wf, int step_cap, Vis& vis,
                                     Counters& cnt, double t_lo = 0.0, double t_hi = 0.0)
 {
-    const LevelDist ld(ldp);
+    const float kZeroLd[kMaxLevels] = {};
+    const LevelDist ldr(LdDemand ? kZeroLd : ldp);
+    auto LD = [&]() -> LevelDist {
+        if constexpr (LdDemand) return LevelDist(ldp);
+        else return ldr;
+    };
     // Per axis: the doubled centre p2 = 2 p (odd), the step sign st, the cell c at the current
     // level (size vs); the next plane is k = c + (st > 0 ? vs : 0), and dd = |p2 - 2 k| (twice the
     // distance to it) is kept exactly.  |w_a| is kept in FP32 (exact when widened to FP64).
@@ -187,8 +194,8 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
     int capp = 127;
     float tb = INFINITY;  // a level_dist value (FP32, exact in FP64)
     if (graded == 2) {
-        capp = path_cap(ld, g.n_levels, t);
-        tb = ld.at(capp + 1, g.n_levels);
+        capp = path_cap(LD(), g.n_levels, t);
+        tb = LD().at(capp + 1, g.n_levels);
     }
     long long blk = block_of<D>(g, c0);
     int cap0 = maxl;
@@ -211,9 +218,9 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
                     an = (double)af[a];
                 }
             }
-            cg = graded_cap(ld, g.n_levels, dn, an);
+            cg = graded_cap(LD(), g.n_levels, dn, an);
         } else {
-            cg = path_cap(ld, g.n_levels, 0.0);
+            cg = path_cap(LD(), g.n_levels, 0.0);
         }
         cap0 = cg < maxl ? cg : maxl;
     }
@@ -287,8 +294,8 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             // the cap rises at t = tb and binds here, so the level rises: re-locate from x(t),
             // which lies in the current cell
             t = te;
-            capp = path_cap(ld, g.n_levels, t);
-            tb = ld.at(capp + 1, g.n_levels);
+            capp = path_cap(LD(), g.n_levels, t);
+            tb = LD().at(capp + 1, g.n_levels);
             const int nl = lraw < capp ? lraw : capp;
             ++cnt.lvlchg;
             const int nvs = 1 << nl;
@@ -322,14 +329,14 @@ __device__ __forceinline__ int hdda(const Geo& g, const uint64_t* sts, int mode,
             int nl;
             if (graded == 2) {
                 // the path cap at the crossing (exact), and the new block's level under it
-                capp = graded_cap(ld, g.n_levels, d2s0, aws);
-                tb = ld.at(capp + 1, g.n_levels);
+                capp = graded_cap(LD(), g.n_levels, d2s0, aws);
+                tb = LD().at(capp + 1, g.n_levels);
                 lraw = block_level(sts, blk, mode, maxl);
                 nl = lraw < capp ? lraw : capp;
             } else {
                 int capb = maxl;
                 if (graded) {
-                    int cg = graded_cap(ld, g.n_levels, d2s0, aws);
+                    int cg = graded_cap(LD(), g.n_levels, d2s0, aws);
                     capb = cg < maxl ? cg : maxl;
                 }
                 nl = block_level(sts, blk, mode, capb);
@@ -487,7 +494,13 @@ __device__ __forceinline__ long long block_slot(const Geo& g, const int32_t* slo
     return v;
 }
 
-// Copies the block-state words, and on small grids the slot table, to LDS.
+// LDS copy of the launch's level_dist table, after the state words and (on small grids) the slot table.
+__device__ __forceinline__ float* lds_level_dist(const TraceLaunch& t, uint64_t* sts)
+{
+    return (float*)((int32_t*)(sts + t.g.n_state_words) + (t.slot_lds ? t.g.nblocks : 0));
+}
+
+// Copies the block-state words, on small grids the slot table, and the level_dist table to LDS.
 __device__ __forceinline__ void stage_blocks(const TraceLaunch& t, uint64_t* sts)
 {
     for (int i = threadIdx.x; i < t.g.n_state_words; i += blockDim.x) sts[i] = t.states[i];
@@ -495,6 +508,7 @@ __device__ __forceinline__ void stage_blocks(const TraceLaunch& t, uint64_t* sts
         int32_t* ls = (int32_t*)(sts + t.g.n_state_words);
         for (long long i = threadIdx.x; i < t.g.nblocks; i += blockDim.x) ls[i] = t.slot[i];
     }
+    if (threadIdx.x < kMaxLevels) lds_level_dist(t, sts)[threadIdx.x] = t.level_dist[threadIdx.x];
     __syncthreads();
 }
 
@@ -686,14 +700,21 @@ struct AccJ {
     __device__ __forceinline__ bool add(const float* e, const float* x, const int*, int, long long, double t0,
                                         double t1, float dsf)
     {
-        const SegK k((float)(t1 - t0) * dsf);
+        add_dt(e, x, (float)(t1 - t0) * dsf);
+        return false;
+    }
+    // A traversed segment always has dt > 0 (t1 > t0, and the difference of two crossing times is
+    // far above FP32's smallest subnormal), so the zero-length segment a pipelined visitor starts
+    // with leaves "first" set: psi is taken at the first real segment.
+    __device__ __forceinline__ void add_dt(const float* e, const float* x, float dt)
+    {
+        const SegK k(dt);
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
             const float tr = rte_step(I[l], Tr[l], e[l], x[l], k);
             if (first) psi[l] = 1.0f - tr;
         }
-        first = 0;
-        return false;
+        if (dt > 0.f) first = 0;
     }
 };
 
@@ -710,9 +731,10 @@ template <int D, typename T, class Acc = AccPlain>
 struct VisStatic {
     using AccT = Acc;
     static constexpr int kMinWaves = (!Acc::kTrunc && !Acc::kJ) ? 4 : 1;
-    // the same one-segment software pipeline as the velocity-interpolation visitor (plain and interval
-    // accumulators): a cell's record is loaded at its visit and applied at the next one or in finish()
-    static constexpr bool kPipe = !Acc::kTrunc && !Acc::kJ;
+    // the same one-segment software pipeline as the velocity-interpolation visitor (every accumulator but
+    // the truncated ones; the angle-integrated one in 2D only, where its registers allow it): a cell's
+    // record is loaded at its visit and applied at the next one or in finish()
+    static constexpr bool kPipe = !Acc::kTrunc && (!Acc::kJ || D == 2);
     const Geo* g;
     const int32_t* slot;
     const T* vals;
@@ -841,13 +863,14 @@ template <int D, typename T = float, class Acc = AccPlain>
 struct VisVelinterp {
     using AccT = Acc;
     static constexpr int kMinWaves = (D == 2 && !Acc::kTrunc && !Acc::kJ) ? 4 : 1;
-    // Plain and interval accumulators take a one-segment software pipeline: a segment's node records
+    // All accumulators but the truncated ones (and the angle-integrated one in 3D, whose registers would
+    // drop a wave per SIMD) take a one-segment software pipeline: a segment's node records
     // are loaded when it is visited and applied at the next visit (or in finish()), so their latency
     // overlaps the traversal step in between, and the next cell's node coordinate is read before the
     // pending update, which overlaps that read.  Segments are applied in order with the same
     // arithmetic; the pipeline starts with a zero-length, zero-valued segment, which leaves I and T
     // unchanged bit for bit (tau = 0 takes the series branch: h = 0, exp(-0) = 1).
-    static constexpr bool kPipe = !Acc::kTrunc && !Acc::kJ;
+    static constexpr bool kPipe = !Acc::kTrunc && (!Acc::kJ || D == 2);
     const TraceLaunch* tl;
     const float4* vgrid;
     const T* vnodes;
@@ -1088,8 +1111,9 @@ __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* 
     Vis vis;
     vis.init(&t, wf);
     constexpr bool kIv = Vis::AccT::kIv;
-    int rc = hdda<D, kIv>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt,
-                          t.t_lo, t.t_hi);
+    extern __shared__ uint64_t lds_words[];
+    int rc = hdda<D, kIv, true>(t.g, sts, t.mode, t.max_level, t.graded, lds_level_dist(t, lds_words), pv, wf,
+                                t.step_cap, vis, cnt, t.t_lo, t.t_hi);
     finish_visit(vis, 0);
     int capped = rc == 1;
     const int nl = t.lb.nl;
@@ -1199,8 +1223,19 @@ k_trace(TraceLaunch t)
 // the wave) and accumulates J = sum_d w_d I_d and psi = sum_d w_d (1 - exp(-tau_1,d))
 // in registers; one partial per chunk is written (the caller's chunks are summed
 // in a fixed order afterwards).
+// Waves per SIMD the angle-integrated kernel is held to: 3 for the software-pipelined visitors (their
+// pending records would otherwise push it to 2), else the compiler's choice.
+template <class V, class = void>
+struct MinWavesJ {
+    static constexpr int v = 1;
+};
+template <class V>
+struct MinWavesJ<V, std::void_t<decltype(V::kPipe)>> {
+    static constexpr int v = V::kPipe ? 3 : 1;
+};
+
 template <int D, class Vis>
-__global__ void __launch_bounds__(256) k_trace_j(TraceLaunch t)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWavesJ<Vis>::v))) k_trace_j(TraceLaunch t)
 {
     extern __shared__ uint64_t sts[];
     stage_blocks(t, sts);
@@ -1255,7 +1290,8 @@ __global__ void __launch_bounds__(256) k_trace_j(TraceLaunch t)
         Vis vis;
         vis.init(&t, wf);
         Counters cnt = {0, 0, 0};
-        const int rc = hdda<D>(t.g, sts, t.mode, t.max_level, t.graded, t.level_dist, pv, wf, t.step_cap, vis, cnt);
+        const int rc = hdda<D, false, true>(t.g, sts, t.mode, t.max_level, t.graded, lds_level_dist(t, sts), pv, wf,
+                                            t.step_cap, vis, cnt);
         finish_visit(vis, 0);
         if (rc == 1) {
             atomicAdd(&t.err[0], 1ull);
@@ -1301,7 +1337,7 @@ static hipError_t launch_one(const TraceLaunch& t0, hipStream_t s)
 {
     TraceLaunch t = t0;
     long long tiles = (t.n_probes + 63) / 64;
-    size_t shm = sizeof(uint64_t) * (size_t)t.g.n_state_words;
+    size_t shm = sizeof(uint64_t) * (size_t)t.g.n_state_words + sizeof(float) * kMaxLevels;
     // small grids: the slot table joins the state words in LDS (at most 32 KiB more per workgroup)
     t.slot_lds = t.g.nblocks <= kSlotLdsMax ? 1 : 0;
     if (t.slot_lds) shm += sizeof(int32_t) * (size_t)t.g.nblocks;
