@@ -960,6 +960,19 @@ struct VisVelinterp {
     }
 };
 
+// Whether a visitor is software-pipelined.  The pipelined ones traverse with the level_dist table read
+// from LDS where it is needed (nothing in their traversal may wait on vector-memory loads, and holding
+// the table in registers spilled scalar registers); the others keep it in scalar registers, read once
+// from the launch's arguments, which costs the VALU-bound Core-and-Voigt march fewer instructions.
+template <class V, class = void>
+struct Pipelined {
+    static constexpr bool v = false;
+};
+template <class V>
+struct Pipelined<V, std::void_t<decltype(V::kPipe)>> {
+    static constexpr bool v = V::kPipe;
+};
+
 // Ends a traversal: visitors with a pending (software-pipelined) segment apply it.
 template <class V>
 __device__ __forceinline__ auto finish_visit(V& v, int) -> decltype(v.finish(), void())
@@ -1112,8 +1125,10 @@ __device__ __forceinline__ void trace_ray(const TraceLaunch& t, const uint64_t* 
     vis.init(&t, wf);
     constexpr bool kIv = Vis::AccT::kIv;
     extern __shared__ uint64_t lds_words[];
-    int rc = hdda<D, kIv, true>(t.g, sts, t.mode, t.max_level, t.graded, lds_level_dist(t, lds_words), pv, wf,
-                                t.step_cap, vis, cnt, t.t_lo, t.t_hi);
+    constexpr bool kLdsLd = Pipelined<Vis>::v;
+    int rc = hdda<D, kIv, kLdsLd>(t.g, sts, t.mode, t.max_level, t.graded,
+                                  kLdsLd ? lds_level_dist(t, lds_words) : t.level_dist, pv, wf, t.step_cap, vis, cnt,
+                                  t.t_lo, t.t_hi);
     finish_visit(vis, 0);
     int capped = rc == 1;
     const int nl = t.lb.nl;
@@ -1225,13 +1240,9 @@ k_trace(TraceLaunch t)
 // in a fixed order afterwards).
 // Waves per SIMD the angle-integrated kernel is held to: 3 for the software-pipelined visitors (their
 // pending records would otherwise push it to 2), else the compiler's choice.
-template <class V, class = void>
-struct MinWavesJ {
-    static constexpr int v = 1;
-};
 template <class V>
-struct MinWavesJ<V, std::void_t<decltype(V::kPipe)>> {
-    static constexpr int v = V::kPipe ? 3 : 1;
+struct MinWavesJ {
+    static constexpr int v = Pipelined<V>::v ? 3 : 1;
 };
 
 template <int D, class Vis>
@@ -1290,8 +1301,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWav
         Vis vis;
         vis.init(&t, wf);
         Counters cnt = {0, 0, 0};
-        const int rc = hdda<D, false, true>(t.g, sts, t.mode, t.max_level, t.graded, lds_level_dist(t, sts), pv, wf,
-                                            t.step_cap, vis, cnt);
+        constexpr bool kLdsLd = Pipelined<Vis>::v;
+        const int rc = hdda<D, false, kLdsLd>(t.g, sts, t.mode, t.max_level, t.graded,
+                                              kLdsLd ? lds_level_dist(t, sts) : t.level_dist, pv, wf, t.step_cap, vis,
+                                              cnt);
         finish_visit(vis, 0);
         if (rc == 1) {
             atomicAdd(&t.err[0], 1ull);
