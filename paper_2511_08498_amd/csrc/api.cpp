@@ -124,7 +124,10 @@ static rt_status check_desc(const rt_scene_desc* d, const rt_scene_inputs* inp)
 // LDS a trace workgroup stages: the packed block states, and the slot table on grids of <= kSlotLdsMax blocks.
 static long long trace_lds_bytes(const Geo& g)
 {
-    return 8ll * g.n_state_words + (g.nblocks <= kSlotLdsMax ? 4ll * g.nblocks : 0ll) + 4ll * kMaxLevels;
+    // state words, the slot table on small grids, the level_dist table, and the angle-integrated
+    // kernel's J and psi sums (2 x kLam floats per lane of a 256-lane workgroup)
+    return 8ll * g.n_state_words + (g.nblocks <= kSlotLdsMax ? 4ll * g.nblocks : 0ll) + 4ll * kMaxLevels +
+           2ll * kLam * 256 * 4;
 }
 
 static void make_geo(const rt_scene_desc* d, Geo& g)
@@ -430,6 +433,7 @@ static LamBatch make_batch(const rt_scene* sc, int lam_begin, int lam_end)
         for (int l = 0; l < kLam; ++l) {
             lb.dl[l][k] = (float)(lb.lam[l] - lb.lam0[k]);
             lb.rr[l][k] = (float)(lb.lam[l] / lb.lam0[k]);
+            lb.sr[l][k] = (float)(0.56418958354775628 * lb.lam0[k] / lb.lam[l]);
         }
     }
     return lb;

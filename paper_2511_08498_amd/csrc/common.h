@@ -48,6 +48,7 @@ struct LamBatch {
     // FP32 per-batch constants of the line evaluation (read as kernel arguments):
     float dl[kLam][kMaxLines];  // lam - lam0
     float rr[kLam][kMaxLines];  // lam / lam0
+    float sr[kLam][kMaxLines];  // lam0 / (sqrt(pi) lam): the Voigt profile's normalisation and wavelength scaling
     float k0[kMaxLines];        // lam0 / c
 };
 

@@ -678,6 +678,9 @@ struct AccTrunc {
     }
 };
 
+// Lanes of an angle-integrated workgroup: its J and psi accumulators live in LDS, lane-major.
+constexpr int kJStride = 256;
+
 // Angle integration: the plain march, plus 1 - exp(-tau) of the first segment
 // (the probe's own cell up to its boundary), whose weighted sum over directions
 // is the diagonal of the approximate operator.
@@ -685,15 +688,16 @@ struct AccJ {
     static constexpr bool kTrunc = false;
     static constexpr bool kJ = true;
     static constexpr bool kIv = false;
-    float I[kLam], Tr[kLam], psi[kLam];
+    float I[kLam], Tr[kLam];
     int first;
+    float* pacc;  // the lane's psi accumulators in LDS (wavelength l at pacc[l * kJStride])
+    float wdir;   // the direction's quadrature weight
     __device__ void init(const TraceLaunch*)
     {
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
             I[l] = 0.f;
             Tr[l] = 1.f;
-            psi[l] = 0.f;
         }
         first = 1;
     }
@@ -703,16 +707,17 @@ struct AccJ {
         add_dt(e, x, (float)(t1 - t0) * dsf);
         return false;
     }
-    // A traversed segment always has dt > 0 (t1 > t0, and the difference of two crossing times is
-    // far above FP32's smallest subnormal), so the zero-length segment a pipelined visitor starts
-    // with leaves "first" set: psi is taken at the first real segment.
+    // The first segment's 1 - exp(-tau) enters the weighted psi sum at once (psi += w (1 - exp(-tau_1))).
+    // A traversed segment always has dt > 0 (t1 > t0, and the difference of two crossing times is far
+    // above FP32's smallest subnormal), so the zero-length segment a pipelined visitor starts with leaves
+    // "first" set (it adds w x 0, which leaves the sum unchanged).
     __device__ __forceinline__ void add_dt(const float* e, const float* x, float dt)
     {
         const SegK k(dt);
 #pragma unroll
         for (int l = 0; l < kLam; ++l) {
             const float tr = rte_step(I[l], Tr[l], e[l], x[l], k);
-            if (first) psi[l] = 1.0f - tr;
+            if (first) pacc[l * kJStride] = fmaf(wdir, 1.0f - tr, pacc[l * kJStride]);
         }
         if (dt > 0.f) first = 0;
     }
@@ -1051,7 +1056,7 @@ struct VisCav {
                         phi = __expf(-x * x);
                     } else {
                         float r2 = tl->lb.rr[l][k];
-                        phi = voigt_h(ls[k][2] * r2 * r2, x) * ls[k][3] * (0.56418958354775628f / r2);
+                        phi = voigt_h(ls[k][2] * r2 * r2, x) * ls[k][3] * tl->lb.sr[l][k];
                     }
                     ee = fmaf(ls[k][0], phi, ee);
                     xx = fmaf(ls[k][1], phi, xx);
@@ -1238,11 +1243,12 @@ k_trace(TraceLaunch t)
 // the wave) and accumulates J = sum_d w_d I_d and psi = sum_d w_d (1 - exp(-tau_1,d))
 // in registers; one partial per chunk is written (the caller's chunks are summed
 // in a fixed order afterwards).
-// Waves per SIMD the angle-integrated kernel is held to: 3 for the software-pipelined visitors (their
-// pending records would otherwise push it to 2), else the compiler's choice.
+// Waves per SIMD the angle-integrated kernel is held to: 4 for the software-pipelined visitors (with
+// its J and psi sums in LDS their march fits the plain march's registers; a few per-direction values
+// spill outside the segment loop), else the compiler's choice.
 template <class V>
 struct MinWavesJ {
-    static constexpr int v = Pipelined<V>::v ? 3 : 1;
+    static constexpr int v = Pipelined<V>::v ? 4 : 1;
 };
 
 template <int D, class Vis>
@@ -1290,16 +1296,23 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWav
             if (D > 2) pv[2] = bcz * t.g.B + (local >> (2 * t.g.log2B));
         }
     }
-    float J[kLam], P[kLam];
+    // J and psi sums of the lane, in LDS (lane-major: column threadIdx.x), which keeps the march's
+    // registers at the plain march's count
+    __shared__ float jsum[kLam * kJStride], psum[kLam * kJStride];
+    float* const jl = jsum + threadIdx.x;
+    float* const pl = psum + threadIdx.x;
 #pragma unroll
-    for (int l = 0; l < kLam; ++l) J[l] = P[l] = 0.f;
+    for (int l = 0; l < kLam; ++l) jl[l * kJStride] = pl[l * kJStride] = 0.f;
     for (long long dir = d0; dir < d1; ++dir) {
         if (!live) continue;
         float wf[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int a = 0; a < D; ++a) wf[a] = t.dirs[dir * D + a];
+        const float w = t.weights[dir];
         Vis vis;
         vis.init(&t, wf);
+        vis.acc.pacc = pl;
+        vis.acc.wdir = w;
         Counters cnt = {0, 0, 0};
         constexpr bool kLdsLd = Pipelined<Vis>::v;
         const int rc = hdda<D, false, kLdsLd>(t.g, sts, t.mode, t.max_level, t.graded,
@@ -1310,12 +1323,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWav
             atomicAdd(&t.err[0], 1ull);
             atomicMin(&t.err[1], (unsigned long long)(dir * t.n_probes + probe));
         }
-        const float w = t.weights[dir];
 #pragma unroll
-        for (int l = 0; l < kLam; ++l) {
-            J[l] = fmaf(w, fmaf(vis.acc.Tr[l], t.I0, vis.acc.I[l]), J[l]);
-            P[l] = fmaf(w, vis.acc.psi[l], P[l]);
-        }
+        for (int l = 0; l < kLam; ++l) jl[l * kJStride] = fmaf(w, fmaf(vis.acc.Tr[l], t.I0, vis.acc.I[l]), jl[l * kJStride]);
     }
     if (!live) return;
     const int nl = t.lb.nl;
@@ -1323,8 +1332,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MinWav
     for (int l = 0; l < kLam; ++l) {
         if (l >= nl) continue;
         const long long o = (chunk * nl + l) * t.n_probes + probe;
-        t.part_J[o] = J[l];
-        if (t.part_psi) t.part_psi[o] = P[l];
+        t.part_J[o] = jl[l * kJStride];
+        if (t.part_psi) t.part_psi[o] = pl[l * kJStride];
     }
 }
 
