@@ -138,11 +138,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg2", "cfg3", "cfg4", "cfg5", "matrix", "prefilter"],
+    ap.add_argument("--workload", default="cfg2",
+                    choices=["cfg2", "cfg3", "cfg4", "cfg5", "matrix", "prefilter", "nrc_forward"],
                     help="cfg2: 2D velocity interpolation (default, the headline line); cfg3: 3D Core and Voigt "
                          "per storage dtype; cfg4: 48-scene batched vs sequential; cfg5: radiance cache on cfg3; "
                          "matrix: the paper's method matrix on a prominence-like 2D scene; prefilter: box-filtered "
-                         "vs prefiltered merged cells (Sect. 5.1) on cfg2's scene with the lines at rest")
+                         "vs prefiltered merged cells (Sect. 5.1) on cfg2's scene with the lines at rest; "
+                         "nrc_forward: the cache network's fused forward kernel on 2^22 dense rows")
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=None, help="velocity nodes per orthant (default: cfg2 headline 41, "
                                                            "else 21)")
@@ -206,6 +208,8 @@ def main():
         return bench_matrix(args)
     if args.workload == "prefilter":
         return bench_prefilter(args)
+    if args.workload == "nrc_forward":
+        return bench_nrc_forward(args)
     return bench_cfg2(args)
 
 
@@ -1183,14 +1187,65 @@ def bench_cfg5(args):
         "cpu_baseline": {**cpu, "value": cpu_seglam / cpu_s / 1e9, "unit": "Gsegments/s", "cores": nthreads,
                          "kind": "oracle", "sample": "%d pairs x %d wavelengths, FP64 dense Classic, %.1f s" % (
                              kk_np.size, nb * 8, cpu_s)}}
-    cnt = measured_counters("counters_nrc_mfma_cfg5", sources=NRC_SOURCES)
+    # the network kernel's roofline on dense rows (`--workload nrc_forward`): in the compose pass above most
+    # rows fall back and are copied, so its dispatch times the copies, not the MLP
+    cnt = measured_counters("counters_nrc_forward_dense", sources=NRC_SOURCES)
     if cnt is not None:
-        f = cnt["k_nrc_forward"]
         out_line["roofline_nrc_forward"] = {
-            "bound": "mfma", "achieved": f["achieved_tflops"], "peak": f["peak_tflops_bf16_dense"], "unit": "TFLOP/s",
-            "frac": f["mfma_frac_of_peak"], "mfma_busy_frac": f["mfma_busy_frac"], "valu_issue_frac": f["valu_issue_frac"],
-            "counters": "profiles/counters_nrc_mfma_cfg5.json"}
+            "bound": "mfma", "achieved": cnt["achieved_tflops"], "peak": 2500.0, "unit": "TFLOP/s",
+            "frac": cnt["mfma_frac_of_peak"], "mfma_busy_frac": cnt["mfma_busy_frac"],
+            "valu_issue_frac": cnt["valu_issue_frac"], "rows": "2^22 dense rows (bench.py --workload nrc_forward)",
+            "counters": "profiles/counters_nrc_forward_dense.json"}
     print(json.dumps(out_line), flush=True)
+
+
+# ----------------------------------------------------------------------------- cache network forward
+NRC_FLOP_PER_ROW = 2 * (256 * 64 + 3 * 64 * 64 + 64)
+
+
+def bench_nrc_forward(args):
+    """The cache network's fused forward kernel alone (rt_nrc_predict) on 2^22 dense training-form rows:
+    every 16-row tile holds queries, so the MLP's MFMA rate is measured without the compose pass's
+    fallback copies.  Seeded uniform features in the ranges the packed rows take (positions, directions,
+    wavelength offset and level statistics in [-1, 1]); the network is the library's seeded initialisation."""
+    import numpy as np
+    import torch
+    import paper_2511_08498_amd as rt
+    rt.lib()
+    dev = torch.device("cuda")
+    n = 1 << 22
+    g = torch.Generator(device="cpu").manual_seed(7)
+    raw = (torch.rand((n, 12), generator=g) * 2.0 - 1.0).to(dev)
+    raw[:, 11] = 1.0
+    nn = rt.Nrc(max_batch=2 ** 14, freq_max=128.0, seed=5)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        nn.predict(raw)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        y = nn.predict(raw)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    t = float(np.mean(ms)) / 1e3
+    assert torch.isfinite(y).all().item()
+    tflops = n * NRC_FLOP_PER_ROW / t / 1e12
+    line = {"workload": "nrc_forward",
+            "config": {"workload": "cache network 256-4x64 SiLU-1, BF16 MFMA, fused Fourier encoding (frequencies "
+                                   "up to 128), 4194304 dense rows per launch"},
+            "ms_per_launch": float(np.mean(ms)), "launches": args.steps, "rows_per_s": n / t,
+            "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": tflops / 2500.0, "flop_per_row": NRC_FLOP_PER_ROW}}
+    cnt = measured_counters("counters_nrc_forward_dense", sources=NRC_SOURCES)
+    if cnt is not None:
+        line["roofline"].update({"mfma_busy_frac": cnt["mfma_busy_frac"], "valu_issue_frac": cnt["valu_issue_frac"],
+                                 "counters": "profiles/counters_nrc_forward_dense.json"})
+    log("nrc forward: %.3f ms per launch, %.3g rows/s, %.1f TFLOP/s (%.1f %% of the BF16 dense peak)" % (
+        t * 1e3, n / t, tflops, 100 * tflops / 2500.0))
+    print(json.dumps(line), flush=True)
 
 
 # ----------------------------------------------------------------------------- method matrix

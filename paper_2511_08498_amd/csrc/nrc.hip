@@ -188,13 +188,23 @@ __device__ __forceinline__ bool row_queried(const NrcFwd& a, long long row)
 
 // Eight waves per workgroup share one LDS copy of the hidden weights (72 KiB with the per-wave
 // activation tiles), so two workgroups fit a CU: four waves per SIMD.
+//
+// Every product is taken transposed, D^T = W X^T (the weights as the A operand, the activations as
+// B), so a lane's accumulators hold one row (lane % 16) and four consecutive hidden units per
+// 16-unit tile: the activations go to LDS as 8-byte runs, the pre-activations and BF16 activations
+// of training rows as 16- and 8-byte stores, and the output layer reduces over four lanes only.
 constexpr int kFwdWaves = 8;
+// activation tile row stride in LDS: 64 units + 8 of padding (144 B), so the rows of a 16-lane group
+// start on different banks (a 128-B stride puts all 16 on the same ones)
+constexpr int kHP = kHid + 8;
 
 __global__ void __launch_bounds__(64 * kFwdWaves) k_nrc_forward(NrcFwd a)
 {
     __shared__ __attribute__((aligned(16))) __bf16 sW1[kHid * kFeat];
     __shared__ __attribute__((aligned(16))) __bf16 sW[3][kHid * kHid];
-    __shared__ __attribute__((aligned(16))) __bf16 sH[kFwdWaves][16 * kHid];
+    __shared__ __attribute__((aligned(16))) __bf16 sH[kFwdWaves][16 * kHP];
+    __shared__ __attribute__((aligned(16))) float sB[4][kHid];  // hidden biases
+    __shared__ __attribute__((aligned(16))) float sW5[kHid];    // output weights
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     {
         const uint4* src = (const uint4*)(a.wb + kOffW1);
@@ -205,19 +215,12 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_nrc_forward(NrcFwd a)
             uint4* d2 = (uint4*)sW[L];
             for (int i = tid; i < kHid * kHid / 8; i += blockDim.x) d2[i] = s2[i];
         }
+        const int boff[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
+        for (int i = tid; i < 4 * kHid; i += blockDim.x) sB[i / kHid][i % kHid] = a.wf[boff[i / kHid] + i % kHid];
+        for (int i = tid; i < kHid; i += blockDim.x) sW5[i] = a.wf[kOffW5 + i];
     }
     __syncthreads();
     const int r16 = lane & 15, g = lane >> 4;
-    // per-lane bias / output weights for the 4 column tiles
-    float bias[4][4], w5[4];
-    for (int nt = 0; nt < 4; ++nt) {
-        int c = 16 * nt + r16;
-        bias[0][nt] = a.wf[kOffB1 + c];
-        bias[1][nt] = a.wf[kOffB2 + c];
-        bias[2][nt] = a.wf[kOffB3 + c];
-        bias[3][nt] = a.wf[kOffB4 + c];
-        w5[nt] = a.wf[kOffW5 + c];
-    }
     const float b5 = a.wf[kOffB5];
     // the lane's four encoding frequencies f_j = fmax^(j / 15), j = 4 g + p
     float fr[4];
@@ -243,7 +246,7 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_nrc_forward(NrcFwd a)
         }
         for (int sub = 0; sub < n_sub; ++sub) {
             const long long tile = tile0 + sub;
-            const long long row_a = tile * 16 + r16;  // the row this lane feeds as an A operand
+            const long long row_a = tile * 16 + r16;  // this lane's row (its activations and outputs)
             float r[11], w, tgt;
             bool valid;
             row_raw(a, row_a, r, w, tgt, valid);
@@ -252,34 +255,41 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_nrc_forward(NrcFwd a)
                 if (g == 0 && valid) a.I_out[row_a] = a.I_near[row_a];
                 continue;
             }
-            // ---- layer 1: 256 -> 64
+            // ---- layer 1: 256 -> 64; D^T element (unit 16 nt + 4 g + j, row r16)
             f32x4 acc[4];
             for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
             for (int ks = 0; ks < kFeat / 32; ++ks) {
                 const int k0 = 32 * ks + 8 * g;
-                const bf16x8 av = encode8(r, ks, g, fr, valid);
-                if (a.mode == 0 && a.x_out && valid) *(bf16x8*)(a.x_out + row_a * kFeat + k0) = av;
+                const bf16x8 xv = encode8(r, ks, g, fr, valid);
+                if (a.mode == 0 && a.x_out && valid) *(bf16x8*)(a.x_out + row_a * kFeat + k0) = xv;
                 for (int nt = 0; nt < 4; ++nt) {
-                    bf16x8 bv = *(const bf16x8*)(sW1 + (16 * nt + r16) * kFeat + k0);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nt], 0, 0, 0);
+                    bf16x8 wv8 = *(const bf16x8*)(sW1 + (16 * nt + r16) * kFeat + k0);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv8, xv, acc[nt], 0, 0, 0);
                 }
             }
             // ---- hidden layers
+            const bool store_row = a.mode == 0 && row_a < a.rows;
             for (int L = 0; L < 4; ++L) {
-                // bias + SiLU; D element (row 4 g + j, col 16 nt + r16)
-                for (int nt = 0; nt < 4; ++nt)
+                // bias + SiLU on units u0 .. u0 + 3 of row r16
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int u0 = 16 * nt + 4 * g;
+                    const float4 bv = *(const float4*)&sB[L][u0];
+                    const float zb[4] = {bv.x, bv.y, bv.z, bv.w};
+                    float z[4];
+                    __bf16 hb[4];
                     for (int j = 0; j < 4; ++j) {
-                        float z = acc[nt][j] + bias[L][nt];
-                        float h = silu(z);
-                        const int row = 4 * g + j, col = 16 * nt + r16;
-                        sH[wv][row * kHid + col] = (__bf16)h;
-                        const long long grow = tile * 16 + row;
-                        if (a.mode == 0 && grow < a.rows) {
-                            if (a.z_out) a.z_out[((long long)L * a.rows + grow) * kHid + col] = z;
-                            if (a.h_out) a.h_out[((long long)L * a.rows + grow) * kHid + col] = (__bf16)h;
-                        }
+                        z[j] = acc[nt][j] + zb[j];
+                        const float h = silu(z[j]);
+                        hb[j] = (__bf16)h;
                         acc[nt][j] = h;
                     }
+                    *(uint2*)&sH[wv][r16 * kHP + u0] = *(const uint2*)hb;
+                    if (store_row) {
+                        const long long o = ((long long)L * a.rows + row_a) * kHid + u0;
+                        if (a.z_out) *(float4*)(a.z_out + o) = make_float4(z[0], z[1], z[2], z[3]);
+                        if (a.h_out) *(uint2*)(a.h_out + o) = *(const uint2*)hb;
+                    }
+                }
                 if (L == 3) break;
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -287,46 +297,38 @@ __global__ void __launch_bounds__(64 * kFwdWaves) k_nrc_forward(NrcFwd a)
                 for (int nt = 0; nt < 4; ++nt) nacc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
                 for (int ks = 0; ks < kHid / 32; ++ks) {
                     const int k0 = 32 * ks + 8 * g;
-                    bf16x8 av = *(const bf16x8*)(&sH[wv][r16 * kHid + k0]);
+                    const bf16x8 hv = *(const bf16x8*)(&sH[wv][r16 * kHP + k0]);
                     for (int nt = 0; nt < 4; ++nt) {
-                        bf16x8 bv = *(const bf16x8*)(sW[L] + (16 * nt + r16) * kHid + k0);
-                        nacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, nacc[nt], 0, 0, 0);
+                        bf16x8 wv8 = *(const bf16x8*)(sW[L] + (16 * nt + r16) * kHid + k0);
+                        nacc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv8, hv, nacc[nt], 0, 0, 0);
                     }
                 }
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 for (int nt = 0; nt < 4; ++nt) acc[nt] = nacc[nt];
             }
-            // ---- output: y[row] = sum_c h4[row][c] w5[c] + b5 (h4 rounded to BF16 as the GEMMs see it)
-            float part[4];
-            for (int j = 0; j < 4; ++j) {
-                float s = 0.f;
-                for (int nt = 0; nt < 4; ++nt) s += (float)(__bf16)acc[nt][j] * w5[nt];
-                part[j] = s;
+            // ---- output: y[row] = sum_u h4[row][u] w5[u] + b5 (h4 rounded to BF16 as the GEMMs see it):
+            // the lane's 16 units, then the four lanes of the row (g = 0..3)
+            float s = 0.f;
+            for (int nt = 0; nt < 4; ++nt) {
+                const float4 w4 = *(const float4*)&sW5[16 * nt + 4 * g];
+                const float ww4[4] = {w4.x, w4.y, w4.z, w4.w};
+                for (int j = 0; j < 4; ++j) s = fmaf((float)(__bf16)acc[nt][j], ww4[j], s);
             }
-            for (int o = 1; o < 16; o <<= 1)
-                for (int j = 0; j < 4; ++j) part[j] += __shfl_xor(part[j], o, 64);
-            // lanes with r16 == j hold row 4 g + j
-            float y = 0.f;
-            for (int j = 0; j < 4; ++j)
-                if (r16 == j) y = part[j] + b5;
-            if (r16 < 4) {
-                const long long grow = tile * 16 + 4 * g + r16;
-                float rr[11], ww, tt;
-                bool v2;
-                row_raw(a, grow, rr, ww, tt, v2);
-                if (v2) {
-                    if (a.yhat) a.yhat[grow] = y;
-                    if (a.mode == 0) {
-                        float e = y - tt;
-                        if (a.dy) a.dy[grow] = ww * 2.0f * e / (float)a.rows;
-                        lsum += ww * e * e;
-                    } else if (ww > 0.f) {
-                        float yc = fminf(fmaxf(y, -8.0f), 8.0f);
-                        a.I_out[grow] = fmaf(a.T_near[grow], __expf(10.0f * yc), a.I_near[grow]);
-                    } else {
-                        a.I_out[grow] = a.I_near[grow];
-                    }
+            s += __shfl_xor(s, 16, 64);
+            s += __shfl_xor(s, 32, 64);
+            const float y = s + b5;
+            if (g == 0 && valid) {
+                if (a.yhat) a.yhat[row_a] = y;
+                if (a.mode == 0) {
+                    float e = y - tgt;
+                    if (a.dy) a.dy[row_a] = w * 2.0f * e / (float)a.rows;
+                    lsum += w * e * e;
+                } else if (w > 0.f) {
+                    float yc = fminf(fmaxf(y, -8.0f), 8.0f);
+                    a.I_out[row_a] = fmaf(a.T_near[row_a], __expf(10.0f * yc), a.I_near[row_a]);
+                } else {
+                    a.I_out[row_a] = a.I_near[row_a];
                 }
             }
             __builtin_amdgcn_wave_barrier();
