@@ -302,3 +302,24 @@ def test_velocity_grid_warning(rt, vscene):
         warnings.simplefilter("error", rt.VelocityGridWarning)
         fine.build(0, 8)
     assert fine.velocity_grid_ratio.max() < 0.31
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_pipelined_velinterp_march_equals_the_unpipelined_one(rt, vscene, storage):
+    """The plain march applies each segment's node records one traversal step after loading them; the
+    truncated march's inference mode with every block falling back runs the same march unpipelined.  Same
+    segments, same order, same arithmetic: the intensities are equal bit for bit (VLM, path-graded cascade caps,
+    and MIP 0)."""
+    import torch
+    sc = vscene
+    scene = rt.Scene.from_dict(sc, emission="velinterp", n_v=41)
+    scene.build(0, 8, iod_threshold=3e-4, tau_thin=0.0, iod_frame="core", storage=storage, velocity_grid_warn=0)
+    dirs = torch.from_numpy(sc["dirs"]).cuda()
+    ld = [v * 16.0 for v in rt.CASCADE_LEVEL_DIST]
+    fb = torch.ones(scene.info["n_blocks"], dtype=torch.uint8, device="cuda")
+    assert (scene.levels() > 0).any()
+    for mode, kw in (("vlm", dict(level_dist=ld, grade="path")), ("level0", {})):
+        full = scene.trace(dirs, mode=mode, **kw)
+        inf = scene.trace_truncated(dirs, 32.0, gen=False, fallback=fb, mode=mode, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(inf["I_near"], full), mode
