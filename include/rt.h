@@ -444,14 +444,24 @@ typedef struct rt_batch_job {
  *                  jobs share it, that storage dtype), both launches on `stream`;
  *   d_claims       optional device uint32 [total tiles], incremented once per
  *                  processed tile (lets tests check that every tile is taken
- *                  exactly once).
+ *                  exactly once);
+ *   tile_shape     which voxels of a brick one 64-probe wave tile takes:
+ *                  RT_TILE_ROWS (0, default): 64 consecutive voxels in x-fastest
+ *                  order (a 16 x 4 strip of a 16^2 brick, an 8 x 8 x 1 slab of an
+ *                  8^3 brick); RT_TILE_CUBES (1): 8 x 8 squares in 2D, 4 x 4 x 4
+ *                  cubes in 3D (bricks smaller than that tile: the whole brick).
+ *                  Outputs keep the probe order of rt_trace, so every tile
+ *                  shape gives the same bits.
  */
+enum { RT_TILE_ROWS = 0, RT_TILE_CUBES = 1 };
 typedef struct rt_batch_params {
     int32_t wg_waves;
     int32_t wgs_per_cu;
     int32_t tiles_per_pop;
     int32_t order;
     unsigned int* d_claims;
+    int32_t tile_shape;
+    int32_t reserved_;
 } rt_batch_params;
 
 typedef struct rt_batch rt_batch;
@@ -485,9 +495,9 @@ void rt_batch_destroy(rt_batch* batch);
 
 /*
  * Autotuner: times every launch shape of a small candidate grid (waves per
- * workgroup x workgroups per CU x tiles per pop) on the given jobs, `reps`
- * runs each after one warm-up, and returns the fastest in *h_best with its
- * mean time in *h_best_ms.  d_ws: a batch workspace for these jobs
+ * workgroup x workgroups per CU x tiles per pop x wave-tile shape) on the
+ * given jobs, `reps` runs each after one warm-up, and returns the fastest in
+ * *h_best with its mean time in *h_best_ms.  d_ws: a batch workspace for these jobs
  * (rt_batch_workspace_bytes), reused by every candidate.  Synchronises
  * `stream`; writes the jobs' outputs.
  */

@@ -98,7 +98,11 @@ class RtNrcDesc(ctypes.Structure):
 
 class RtBatchParams(ctypes.Structure):
     _fields_ = [("wg_waves", ctypes.c_int32), ("wgs_per_cu", ctypes.c_int32), ("tiles_per_pop", ctypes.c_int32),
-                ("order", ctypes.c_int32), ("d_claims", _P)]
+                ("order", ctypes.c_int32), ("d_claims", _P), ("tile_shape", ctypes.c_int32),
+                ("reserved_", ctypes.c_int32)]
+
+
+TILE_SHAPE = {"rows": 0, "cubes": 1}
 
 
 _LIB = None
@@ -629,10 +633,12 @@ def _batch_jobs(jobs):
 class Batch:
     """Many scenes traced in one persistent launch (rt_batch_*)."""
 
-    def __init__(self, jobs, wg_waves=0, wgs_per_cu=0, tiles_per_pop=0, order=0, claims=None, stream=None):
+    def __init__(self, jobs, wg_waves=0, wgs_per_cu=0, tiles_per_pop=0, order=0, claims=None, tile_shape="rows",
+                 stream=None):
         self._arr, self._keep = _batch_jobs(jobs)
         p = RtBatchParams()
         p.wg_waves, p.wgs_per_cu, p.tiles_per_pop, p.order = int(wg_waves), int(wgs_per_cu), int(tiles_per_pop), int(order)
+        p.tile_shape = TILE_SHAPE[tile_shape] if isinstance(tile_shape, str) else int(tile_shape)
         p.d_claims = claims.data_ptr() if claims is not None else None
         self._claims = claims
         self._ws = _batch_workspace(len(jobs))
@@ -677,7 +683,9 @@ def batch_autotune(jobs, reps=3, stream=None):
     _check(lib().rt_batch_autotune(arr, len(jobs), int(reps), ws.data_ptr(), ws.numel(), _stream(stream),
                                    ctypes.byref(best), ctypes.byref(ms)))
     del keep
-    return {"wg_waves": best.wg_waves, "wgs_per_cu": best.wgs_per_cu, "tiles_per_pop": best.tiles_per_pop}, ms.value
+    shape = {v: k for k, v in TILE_SHAPE.items()}[best.tile_shape]
+    return {"wg_waves": best.wg_waves, "wgs_per_cu": best.wgs_per_cu, "tiles_per_pop": best.tiles_per_pop,
+            "tile_shape": shape}, ms.value
 
 
 class Graph:

@@ -945,13 +945,15 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
     size_t need = 0;
     RT_TRY(rt_batch_workspace_bytes(n_jobs, &need));
     RT_TRY(check_ws(d_ws, ws_bytes, need, "rt_batch_create"));
-    rt_batch_params bp = p ? *p : rt_batch_params{0, 0, 0, 0, nullptr};
+    rt_batch_params bp = p ? *p : rt_batch_params{0, 0, 0, 0, nullptr, 0, 0};
     int wg_waves = bp.wg_waves ? bp.wg_waves : 4;
     int wgs_per_cu = bp.wgs_per_cu ? bp.wgs_per_cu : 2;
     int tpp = bp.tiles_per_pop ? bp.tiles_per_pop : 1;
     if (wg_waves != 1 && wg_waves != 2 && wg_waves != 4 && wg_waves != 8) return fail(RT_E_ARG, "wg_waves must be 1, 2, 4 or 8");
     if (wgs_per_cu < 1 || wgs_per_cu > 16) return fail(RT_E_ARG, "wgs_per_cu must be in [1, 16]");
     if (tpp < 1 || tpp > 64) return fail(RT_E_ARG, "tiles_per_pop must be in [1, 64]");
+    if (bp.tile_shape != RT_TILE_ROWS && bp.tile_shape != RT_TILE_CUBES)
+        return fail(RT_E_ARG, "tile_shape must be RT_TILE_ROWS or RT_TILE_CUBES");
     std::vector<BatchJob> bj((size_t)n_jobs);
     std::vector<double> cost((size_t)n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
@@ -985,6 +987,7 @@ rt_status rt_batch_create(const rt_batch_job* jobs, int32_t n_jobs, const rt_bat
         b.graded = t.graded;
         b.step_cap = t.step_cap;
         b.storage = t.storage;
+        b.tile_shape = bp.tile_shape;
         b.I0 = t.I0;
         b.ds0 = t.ds0;
         for (int m = 0; m < kMaxLevels; ++m) b.level_dist[m] = t.level_dist[m];
@@ -1080,43 +1083,45 @@ rt_status rt_batch_autotune(const rt_batch_job* jobs, int32_t n_jobs, int32_t re
     const int waves[] = {2, 4, 8};
     const int per_cu[] = {1, 2, 4};
     const int pops[] = {1, 4};
+    const int shapes[] = {RT_TILE_ROWS, RT_TILE_CUBES};
     hipEvent_t e0, e1;
     RT_HIP(hipEventCreate(&e0));
     RT_HIP(hipEventCreate(&e1));
     float best_t = 3.0e38f;
-    rt_batch_params bestp = {4, 2, 1, 0, nullptr};
+    rt_batch_params bestp = {4, 2, 1, 0, nullptr, RT_TILE_ROWS, 0};
     rt_status st = RT_OK;
     for (int w : waves)
         for (int c : per_cu)
-            for (int q : pops) {
-                rt_batch_params p = {w, c, q, 0, nullptr};
-                rt_batch* bt = nullptr;
-                if ((st = rt_batch_create(jobs, n_jobs, &p, d_ws, ws_bytes, stream, &bt)) != RT_OK) goto done;
-                if ((st = rt_batch_run(bt, stream)) != RT_OK) {
-                    rt_batch_destroy(bt);
-                    goto done;
-                }
-                {
-                    hipError_t e = hipEventRecord(e0, s);
-                    for (int r = 0; r < reps && e == hipSuccess; ++r) {
-                        if (rt_batch_run(bt, stream) != RT_OK) e = hipErrorUnknown;
-                    }
-                    if (e == hipSuccess) e = hipEventRecord(e1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    rt_batch_destroy(bt);
-                    if (e != hipSuccess) {
-                        st = fail(RT_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+            for (int q : pops)
+                for (int sh : shapes) {
+                    rt_batch_params p = {w, c, q, 0, nullptr, sh, 0};
+                    rt_batch* bt = nullptr;
+                    if ((st = rt_batch_create(jobs, n_jobs, &p, d_ws, ws_bytes, stream, &bt)) != RT_OK) goto done;
+                    if ((st = rt_batch_run(bt, stream)) != RT_OK) {
+                        rt_batch_destroy(bt);
                         goto done;
                     }
-                    ms /= (float)reps;
-                    if (ms < best_t) {
-                        best_t = ms;
-                        bestp = p;
+                    {
+                        hipError_t e = hipEventRecord(e0, s);
+                        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+                            if (rt_batch_run(bt, stream) != RT_OK) e = hipErrorUnknown;
+                        }
+                        if (e == hipSuccess) e = hipEventRecord(e1, s);
+                        if (e == hipSuccess) e = hipEventSynchronize(e1);
+                        float ms = 0.f;
+                        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                        rt_batch_destroy(bt);
+                        if (e != hipSuccess) {
+                            st = fail(RT_E_HIP, "autotune timing: %s", hipGetErrorString(e));
+                            goto done;
+                        }
+                        ms /= (float)reps;
+                        if (ms < best_t) {
+                            best_t = ms;
+                            bestp = p;
+                        }
                     }
                 }
-            }
 done:
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -221,6 +221,7 @@ struct BatchJob {
     int graded;
     int step_cap;
     int storage;
+    int tile_shape;     // rt_batch_params.tile_shape
     float I0;
     float ds0;
     float level_dist[kMaxLevels];

@@ -1499,13 +1499,29 @@ hipError_t launch_debug_visited(const TraceLaunch& t, int probe_vox, float wx, f
 template <int D, typename T>
 __device__ __forceinline__ void batched_ray(const BatchJob& J, long long dir, long long probe, unsigned long long* err)
 {
-    long long slot = probe >> (D * J.g.log2B);
-    int local = (int)(probe & (J.g.bvox - 1));
-    int blk = J.active_list[slot];
+    const long long slot = probe >> (D * J.g.log2B);
+    const int local = (int)(probe & (J.g.bvox - 1));
+    // voxel of the brick this lane takes: x-fastest rows, or (RT_TILE_CUBES) tiles of side ts = 8 (2D) or
+    // 4 (3D), x-fastest inside a tile and tiles x-fastest inside the brick
+    int lx, ly, lz;
+    if (J.tile_shape == RT_TILE_CUBES) {
+        const int lts = min(J.g.log2B, D == 2 ? 3 : 2), ts = 1 << lts, ltn = J.g.log2B - lts;
+        const int r = local & ((1 << (D * lts)) - 1), t = local >> (D * lts);
+        lx = ((t & ((1 << ltn) - 1)) << lts) | (r & (ts - 1));
+        ly = (((t >> ltn) & ((1 << ltn) - 1)) << lts) | ((r >> lts) & (ts - 1));
+        lz = D > 2 ? (((t >> (2 * ltn)) << lts) | (r >> (2 * lts))) : 0;
+    } else {
+        lx = local & (J.g.B - 1);
+        ly = (local >> J.g.log2B) & (J.g.B - 1);
+        lz = D > 2 ? local >> (2 * J.g.log2B) : 0;
+    }
+    // the output keeps rt_trace's probe order (x-fastest inside the brick) whatever the tile shape
+    const long long out_probe = (slot << (D * J.g.log2B)) + lx + (ly << J.g.log2B) + (lz << (2 * J.g.log2B));
+    const int blk = J.active_list[slot];
     int pv[3] = {0, 0, 0};
-    pv[0] = (blk % J.g.nb[0]) * J.g.B + (local & (J.g.B - 1));
-    pv[1] = ((blk / J.g.nb[0]) % J.g.nb[1]) * J.g.B + ((local >> J.g.log2B) & (J.g.B - 1));
-    if (D > 2) pv[2] = (blk / (J.g.nb[0] * J.g.nb[1])) * J.g.B + (local >> (2 * J.g.log2B));
+    pv[0] = (blk % J.g.nb[0]) * J.g.B + lx;
+    pv[1] = ((blk / J.g.nb[0]) % J.g.nb[1]) * J.g.B + ly;
+    if (D > 2) pv[2] = (blk / (J.g.nb[0] * J.g.nb[1])) * J.g.B + lz;
     float wf[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int a = 0; a < D; ++a) wf[a] = J.dirs[dir * D + a];
@@ -1517,10 +1533,10 @@ __device__ __forceinline__ void batched_ray(const BatchJob& J, long long dir, lo
     finish_visit(vis, 0);
 #pragma unroll
     for (int l = 0; l < kLam; ++l)
-        if (l < J.nl) J.I[((long long)dir * J.nl + l) * J.n_probes + probe] = fmaf(vis.acc.Tr[l], J.I0, vis.acc.I[l]);
+        if (l < J.nl) J.I[((long long)dir * J.nl + l) * J.n_probes + out_probe] = fmaf(vis.acc.Tr[l], J.I0, vis.acc.I[l]);
     if (capped) {
         atomicAdd(&err[0], 1ull);
-        atomicMin(&err[1], (unsigned long long)(J.tile0 * 64ull + (unsigned long long)(dir * J.tiles * 64 + probe)));
+        atomicMin(&err[1], (unsigned long long)(J.tile0 * 64ull + (unsigned long long)(dir * J.tiles * 64 + out_probe)));
     }
 }
 

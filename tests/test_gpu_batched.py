@@ -95,7 +95,9 @@ def test_batched_path_grading_equals_single_scene_launches(rt, scenes):
 
 @pytest.mark.parametrize("shape", [dict(wg_waves=1, wgs_per_cu=1, tiles_per_pop=1, order=1),
                                    dict(wg_waves=8, wgs_per_cu=4, tiles_per_pop=4, order=0),
-                                   dict(wg_waves=2, wgs_per_cu=16, tiles_per_pop=64, order=0)])
+                                   dict(wg_waves=2, wgs_per_cu=16, tiles_per_pop=64, order=0),
+                                   dict(wg_waves=4, wgs_per_cu=2, tiles_per_pop=1, order=0, tile_shape="cubes"),
+                                   dict(wg_waves=8, wgs_per_cu=4, tiles_per_pop=4, order=1, tile_shape="cubes")])
 def test_launch_shapes_give_identical_bits(rt, scenes, shape):
     import torch
     ref = eager(scenes, rt.CASCADE_LEVEL_DIST)
@@ -153,6 +155,7 @@ def test_autotune_returns_a_valid_shape(rt, scenes):
     outs = [torch.zeros((d.shape[0], 8, s.info["n_probes"]), device="cuda") for _, s, d in scenes]
     best, ms = rt.batch_autotune(jobs_for(scenes, outs), reps=2)
     assert best["wg_waves"] in (2, 4, 8) and best["wgs_per_cu"] in (1, 2, 4) and best["tiles_per_pop"] in (1, 4)
+    assert best["tile_shape"] in ("rows", "cubes")
     assert ms > 0
 
 
