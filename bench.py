@@ -150,7 +150,7 @@ def main():
                                                            "else 21)")
     ap.add_argument("--storage", default="f32", choices=["f32", "bf16", "f16"],
                     help="cfg2: storage of the velocity-node / value records (FP32 accumulation in every case)")
-    ap.add_argument("--iod", type=float, default=None, help="IoD threshold T (default: cfg2 headline 3e-4, matrix 1, "
+    ap.add_argument("--iod", type=float, default=None, help="IoD threshold T (default: cfg2 headline 6e-4, matrix 1, "
                                                              "else 1e-2)")
     ap.add_argument("--avg", default="linear", choices=["log", "linear"], help="stored level values: arithmetic "
                     "(box filter, default) or geometric mean of the children")
@@ -246,12 +246,14 @@ def host_cpu_info():
             "threads": min(usable, CPU_SHARE)}
 
 
-# cfg2 settings.  The headline is the fastest setting whose p99.9 relative error against the FP64 dense
-# Classic march stays below the 5e-3 bar on the measured sample (the accuracy/speed sweep is in the design
-# notes); "as stated" is the configuration's literal reading (IoD threshold 1e-2 with the thin bypass of
-# Sect. 2.2, the rest-frame level test of Sect. 3.1, 21 nodes per quadrant as in Sect. 4.1), which is about
-# ten times faster than the dense march and about fourteen times over the bar.
-CFG2_HEADLINE = {"n_v": 41, "iod": 3e-4, "iod_frame": "core", "tau_thin": 0.0, "grade_scale": 16.0}
+# cfg2 settings.  The headline is the fastest measured setting whose p99.9 relative error against the FP64
+# dense Classic march stays below 4e-3, a 20 % margin under the 5e-3 bar (differently sampled runs move a
+# setting's p99.9 by up to about 5 %; the accuracy/speed sweep is in the design notes); "as stated" is the
+# configuration's literal reading (IoD threshold 1e-2 with the thin bypass of Sect. 2.2, the rest-frame level
+# test of Sect. 3.1, 21 nodes per quadrant as in Sect. 4.1), which is about ten times faster than the dense
+# march and about fourteen times over the bar.
+CFG2_HEADLINE = {"n_v": 41, "iod": 6e-4, "iod_frame": "core", "tau_thin": 0.0, "grade_scale": 16.0}
+HEADLINE_MARGIN_BAR = 4e-3
 CFG2_AS_STATED = {"n_v": 21, "iod": 1e-2, "iod_frame": "rest", "tau_thin": 0.25, "grade_scale": 1.0}
 ACCURACY_BAR = 5e-3
 
@@ -530,16 +532,19 @@ def accuracy_ladder(args, rt, torch, np, sc, scene, hs, dirs, probe_vox, d, ref,
                 ("sparse MIP 0 (no merging)", scene, bk(hs), tk(g, mode="level0")),
                 ("grading x%g" % (g / 2), scene, bk(hs), tk(g / 2)),
                 ("grading x%g" % (g / 4), scene, bk(hs), tk(g / 4)),
-                ("T x3", scene, bk(hs, iod_threshold=3 * hs["iod"]), tk(g)),
-                ("T / 3", scene, bk(hs, iod_threshold=hs["iod"] / 3), tk(g)),
-                ("T / 3, grading x%g" % (g / 2), scene, bk(hs, iod_threshold=hs["iod"] / 3), tk(g / 2)),
+                ("T / 2", scene, bk(hs, iod_threshold=hs["iod"] / 2), tk(g)),
+                ("T / 4", scene, bk(hs, iod_threshold=hs["iod"] / 4), tk(g)),
+                ("T x1.5", scene, bk(hs, iod_threshold=1.5 * hs["iod"]), tk(g)),
+                ("T x1.5, grading x%g" % (g * 0.75), scene, bk(hs, iod_threshold=1.5 * hs["iod"]), tk(g * 0.75)),
+                ("T x2", scene, bk(hs, iod_threshold=2 * hs["iod"]), tk(g)),
+                ("T / 2, grading x%g" % (g / 2), scene, bk(hs, iod_threshold=hs["iod"] / 2), tk(g / 2)),
                 ("T = 1e-2", scene, bk(hs, iod_threshold=1e-2), tk(g)),
                 ("rest-frame level test", scene, bk(hs, iod_frame="rest"), tk(g)),
                 ("thin bypass 0.25", scene, bk(hs, tau_thin=0.25), tk(g)),
                 ("levels <= 1", scene, bk(hs), tk(g, max_level=1)),
                 ("plain VLM (no distance grading)", scene, bk(hs), tk(g, level_dist=None)),
                 ("FP16 node records", scene, bk(hs, storage="f16"), tk(g)),
-                ("FP16 node records, T x3", scene, bk(hs, storage="f16", iod_threshold=3 * hs["iod"]), tk(g))]
+                ("FP16 node records, T x1.5", scene, bk(hs, storage="f16", iod_threshold=1.5 * hs["iod"]), tk(g))]
     res = run_ladder(torch, np, settings, {}, {}, dirs, probe_vox, d, ref, nb_lam)
     for name, scn, b, t in settings:
         res[name]["ms_per_batch"] = time_setting(scn, b, t)
@@ -553,7 +558,7 @@ def accuracy_ladder(args, rt, torch, np, sc, scene, hs, dirs, probe_vox, d, ref,
     scene61 = rt.Scene.from_dict(sc, emission=args.emission, n_v=61)
     more = [("61 nodes per orthant, sparse MIP 0", scene61, bk(hs), tk(g, mode="level0")),
             ("61 nodes per orthant", scene61, bk(hs), tk(g)),
-            ("61 nodes per orthant, T x3", scene61, bk(hs, iod_threshold=3 * hs["iod"]), tk(g))]
+            ("61 nodes per orthant, T x1.5", scene61, bk(hs, iod_threshold=1.5 * hs["iod"]), tk(g))]
     res.update(run_ladder(torch, np, more, {}, {}, dirs, probe_vox, d, ref, nb_lam))
     for name, scn, b, t in more:
         res[name]["ms_per_batch"] = time_setting(scn, b, t)
