@@ -1160,6 +1160,34 @@ def bench_cfg5(args):
     queries = cached(g_nrc, g_cut)
     queries0 = cached(g_nrc0, g_cut0, fallback=None)
     torch.cuda.synchronize()
+    # the accuracy/speed trade of the held-out threshold: fallback maps at looser thresholds, each timed over
+    # one full solve (after one warm-up) and measured on the same sampled pairs
+    sweep = []
+    for thr in (5e-2, 2e-1, 1.0):
+        fbt = [torch.zeros(scene.info["n_blocks"], dtype=torch.uint8, device=dev) for _ in range(nb)]
+        for b in range(nb):
+            cnt = torch.zeros(scene.info["n_blocks"], dtype=torch.int32, device=dev)
+            scene.build(8 * b, 8 * b + 8, iod_threshold=args.iod, avg_mode=args.avg, tau_thin=args.tau_thin,
+                        storage="bf16")
+            tr = scene.trace_truncated(dirs, T_TRUNC, gen=True, probes=hd_probes[b], level_dist=level_dist,
+                                       grade=args.grade)
+            nn.validate(scene, tr, thr, fbt[b], count=cnt)
+            nn.fallback_unverified(scene, cnt, 8 * args.nrc_min_checks, fbt[b])
+            del tr
+        cached(fallback=fbt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cached(fallback=fbt)
+        torch.cuda.synchronize()
+        ms_t = (time.perf_counter() - t0) * 1e3
+        g_t, g_tc = torch.empty_like(g_f32), torch.empty_like(g_f32)
+        q_t = cached(g_t, g_tc, fallback=fbt)
+        sweep.append({"held_out_thresh": thr, "ms_per_solve": ms_t, "speedup_vs_plain_f32": ms_f32 / ms_t,
+                      "fallback_block_frac": float(np.mean([int(f[act].sum().item()) for f in fbt])) / int(act.numel()),
+                      "query_ray_frac": q_t / (n_dir * n_probes * nb), "I": g_t.cpu().numpy()})
+        log("cfg5 threshold %g: %.1f ms per solve (%.2fx plain), %.1f %% of blocks fall back" % (
+            thr, ms_t, ms_f32 / ms_t, 100 * sweep[-1]["fallback_block_frac"]))
+    torch.cuda.synchronize()
     cpu = host_cpu_info()
     nthreads = cpu["threads"]
     ref, cpu_seglam, cpu_s = _oracle_classic(sc, probe_vox, kk_np, d_np, list(range(nb * 8)), nthreads)
@@ -1186,6 +1214,8 @@ def bench_cfg5(args):
                                   "truncated_no_cache": _err(g_cut.cpu().numpy(), ref),
                                   "cache_without_fallback": _err(g_nrc0.cpu().numpy(), ref),
                                   "truncated_no_cache_no_fallback": _err(g_cut0.cpu().numpy(), ref)},
+        "held_out_threshold_sweep": [{**{k: v for k, v in w.items() if k != "I"}, "error_vs_fp64_classic": _err(w["I"], ref)}
+                                     for w in sweep],
         "error_vs_gpu_plain_f32": {"plain_bf16": _err(g_bf16.cpu().numpy(), f32_np),
                                    "cache": _err(g_nrc.cpu().numpy(), f32_np),
                                    "truncated_no_cache": _err(g_cut.cpu().numpy(), f32_np)},
