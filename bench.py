@@ -139,12 +139,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cfg2",
-                    choices=["cfg2", "cfg3", "cfg4", "cfg5", "matrix", "prefilter", "nrc_forward"],
+                    choices=["cfg2", "cfg3", "cfg4", "cfg5", "matrix", "prefilter", "nrc_forward", "nrc_train"],
                     help="cfg2: 2D velocity interpolation (default, the headline line); cfg3: 3D Core and Voigt "
                          "per storage dtype; cfg4: 48-scene batched vs sequential; cfg5: radiance cache on cfg3; "
                          "matrix: the paper's method matrix on a prominence-like 2D scene; prefilter: box-filtered "
                          "vs prefiltered merged cells (Sect. 5.1) on cfg2's scene with the lines at rest; "
-                         "nrc_forward: the cache network's fused forward kernel on 2^22 dense rows")
+                         "nrc_forward: the cache network's fused forward kernel on 2^22 dense rows; nrc_train: its "
+                         "training steps (forward, backward, Adam) at the cache's batch of 2^14 rows")
     ap.add_argument("--emission", default="velinterp", choices=["velinterp", "static", "cav"])
     ap.add_argument("--n-v", type=int, default=None, help="velocity nodes per orthant (default: cfg2 headline 41, "
                                                            "else 21)")
@@ -210,6 +211,8 @@ def main():
         return bench_prefilter(args)
     if args.workload == "nrc_forward":
         return bench_nrc_forward(args)
+    if args.workload == "nrc_train":
+        return bench_nrc_train(args)
     return bench_cfg2(args)
 
 
@@ -1280,6 +1283,62 @@ def bench_nrc_forward(args):
                                  "counters": "profiles/counters_nrc_forward_dense.json"})
     log("nrc forward: %.3f ms per launch, %.3g rows/s, %.1f TFLOP/s (%.1f %% of the BF16 dense peak)" % (
         t * 1e3, n / t, tflops, 100 * tflops / 2500.0))
+    print(json.dumps(line), flush=True)
+
+
+# training step: the forward with saved activations, and on the matrix cores per row the weight gradients of the
+# four hidden layers (2 x (256 x 64 + 3 x 64 x 64)) and the activation gradients below the top three
+# (2 x 3 x 64 x 64); the output layer's gradients are column sums on the vector units
+NRC_TRAIN_FLOP_PER_ROW = NRC_FLOP_PER_ROW + 2 * (256 * 64 + 3 * 64 * 64) + 2 * 3 * 64 * 64
+
+
+def bench_nrc_train(args):
+    """Training steps of the cache network (rt_nrc_train: the fused forward writing its activations, the
+    split-K MFMA backward, Adam) at the cache's batch of 2^14 rows drawn from 2^20 seeded rows: time per step,
+    rows and MFMA-shaped FLOP per second.  Seeded uniform features as in nrc_forward, targets a smooth
+    function of them (the time does not depend on the values)."""
+    import numpy as np
+    import torch
+    import paper_2511_08498_amd as rt
+    rt.lib()
+    dev = torch.device("cuda")
+    n, batch = 1 << 20, 1 << 14
+    g = torch.Generator(device="cpu").manual_seed(11)
+    raw = (torch.rand((n, 12), generator=g) * 2.0 - 1.0)
+    raw[:, 11] = 1.0
+    tgt = (0.3 * torch.sin(3.0 * raw[:, 0]) * torch.cos(2.0 * raw[:, 1]) + 0.1 * raw[:, 6]).to(dev)
+    raw = raw.to(dev)
+    nn = rt.Nrc(max_batch=batch, freq_max=128.0, seed=5)
+    stream = torch.cuda.current_stream()
+    steps = 50
+    nn.train(raw, tgt, steps=max(args.warmup, 1) * steps, batch=batch, lr=1e-3)
+    torch.cuda.synchronize()
+    loss0 = nn.loss()
+    ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        nn.train(raw, tgt, steps=steps, batch=batch, lr=1e-3)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1) / steps)
+    loss1 = nn.loss()
+    assert np.isfinite(loss1)
+    t = float(np.mean(ms)) / 1e3
+    tflops = batch * NRC_TRAIN_FLOP_PER_ROW / t / 1e12
+    line = {"workload": "nrc_train",
+            "config": {"workload": "cache network 256-4x64 SiLU-1 training: BF16 MFMA forward + split-K MFMA "
+                                   "backward + Adam (FP32 master weights), 16384 rows per step from 1048576"},
+            "ms_per_step": float(np.mean(ms)), "steps_timed": args.steps * steps, "rows_per_s": batch / t,
+            "loss_after_warmup": loss0, "loss_end": loss1,
+            "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                         "frac": tflops / 2500.0, "flop_per_row": NRC_TRAIN_FLOP_PER_ROW}}
+    cnt = measured_counters("counters_nrc_train", sources=NRC_SOURCES)
+    if cnt is not None:
+        line["roofline"]["counters"] = "profiles/counters_nrc_train.json"
+        line["roofline"]["per_kernel"] = cnt["per_kernel"]
+    log("nrc train: %.3f ms per step of %d rows, %.3g rows/s, %.2f TFLOP/s (%.2f %% of the BF16 dense peak)" % (
+        t * 1e3, batch, batch / t, tflops, 100 * tflops / 2500.0))
     print(json.dumps(line), flush=True)
 
 

@@ -28,6 +28,7 @@ constexpr int kFeat = 256;
 constexpr int kHid = 64;
 constexpr int kNFreq = 16;
 constexpr int kRaw = 12;  // pos 3, dir 3, lam 1, stats 4, weight 1
+constexpr int kMaxSplits = 64;  // row chunks of the backward's gradient sums
 
 // parameter layout (FP32 master copy and BF16 working copy share it)
 constexpr int kOffW1 = 0;
@@ -354,105 +355,168 @@ hipError_t launch_nrc_forward(const NrcFwd& a, int n_wgs, hipStream_t s)
     return hipGetLastError();
 }
 
-// ----------------------------------------------------------- generic GEMM
-// C_part[z][m][n] = sum over k in split z of A(m,k) B(k,n); A, B read with
-// arbitrary strides (BF16 or FP32, rounded to BF16), FP32 accumulation on the
-// matrix cores.  One wave per 16 x 16 tile.  M, N multiples of 16, K a
-// multiple of 32 x splits.
-template <typename TA, typename TB>
-__global__ void __launch_bounds__(256) k_gemm(const TA* A, long long sam, long long sak, const TB* B, long long sbk,
-                                              long long sbn, float* Cp, int M, int N, long long K, int splits)
+// ----------------------------------------------------------- backward GEMMs
+// Weight-gradient partials of one layer over row chunk z = blockIdx.z (rows [z rpp, (z + 1) rpp)):
+//   part[z pstride + m n_in + n] = sum_r dZ[r][m] In[r][n]        (m < 64, n < n_in)
+// dZ BF16 [rows][64], In BF16 [rows][n_in].  A workgroup takes one 64-column strip of n (blockIdx.x) and its
+// four waves one 16-row tile of m each.  Every 32-row slice of dZ and of the strip of In is read with
+// coalesced 16-byte loads and stored transposed in LDS ([column][row], rows padded to 40), so each MFMA
+// operand is one 16-byte LDS read and the dZ fragment serves the strip's four column tiles.  The strip-0
+// workgroup also writes the bias partial part[z pstride + 64 n_in + m] = sum_r dZ[r][m]; with dy and Ho given
+// (the top layer, n_in = 64; Ho BF16 [rows][64] its output activations) wave 0 writes the output layer's
+// partials part[z pstride + 64 n_in + 64 + c] = sum_r dy[r] Ho[r][c] and part[z pstride + 64 n_in + 128] =
+// sum_r dy[r], from an LDS slice of Ho staged like In's.
+// Each lane's sums run over its fixed share of the rows and the four shares are added in a fixed order.
+__global__ void __launch_bounds__(256) k_gemm_dw(const __bf16* dZ, const __bf16* In, int n_in, const float* dy,
+                                                 const __bf16* Ho, long long rpp, float* part, long long pstride)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tn = blockIdx.x * 4 + wv, tm = blockIdx.y, z = blockIdx.z;
-    if (tn * 16 >= N) return;
-    const int r16 = lane & 15, g = lane >> 4;
-    const long long kz = K / splits, k_begin = kz * z, k_end = k_begin + kz;
-    const long long m = (long long)tm * 16 + r16, n = (long long)tn * 16 + r16;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (long long k0 = k_begin; k0 < k_end; k0 += 32) {
-        bf16x8 av, bv;
+    constexpr int kKS = 32, kPad = kKS + 8;
+    __shared__ __align__(16) __bf16 sA[kHid][kPad];
+    __shared__ __align__(16) __bf16 sB[64][kPad];
+    __shared__ __align__(16) __bf16 sC[kHid][kPad];
+    __shared__ float sy[kKS];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, r16 = lane & 15, g = lane >> 4;
+    const int n0 = blockIdx.x * 64;
+    const long long r_begin = (long long)blockIdx.z * rpp, r_end = r_begin + rpp;
+    const int lk = t >> 3, lc = (t & 7) * 8;  // staging: row lk of the slice, columns lc .. lc + 7
+    f32x4 acc[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f, ysum = 0.f, osum[4] = {0.f, 0.f, 0.f, 0.f};
+    for (long long k0 = r_begin; k0 < r_end; k0 += kKS) {
+        const uint4 va = *(const uint4*)(dZ + (k0 + lk) * kHid + lc);
+        const uint4 vb = *(const uint4*)(In + (k0 + lk) * n_in + n0 + lc);
+        const __bf16* ea = (const __bf16*)&va;
+        const __bf16* eb = (const __bf16*)&vb;
+#pragma unroll
         for (int j = 0; j < 8; ++j) {
-            long long k = k0 + 8 * g + j;
-            av[j] = (__bf16)(float)A[m * sam + k * sak];
-            bv[j] = (__bf16)(float)B[k * sbk + n * sbn];
+            sA[lc + j][lk] = ea[j];
+            sB[lc + j][lk] = eb[j];
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+        if (dy) {
+            if (t < kKS) sy[t] = dy[k0 + t];
+            const uint4 vc = *(const uint4*)(Ho + (k0 + lk) * kHid + lc);
+            const __bf16* ec = (const __bf16*)&vc;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sC[lc + j][lk] = ec[j];
+        }
+        __syncthreads();
+        const bf16x8 av = *(const bf16x8*)&sA[wv * 16 + r16][8 * g];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const bf16x8 bv = *(const bf16x8*)&sB[tt * 16 + r16][8 * g];
+            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tt], 0, 0, 0);
+            if (dy && wv == 0) {
+                const bf16x8 hv = *(const bf16x8*)&sC[tt * 16 + r16][8 * g];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) osum[tt] = fmaf(sy[8 * g + j], (float)hv[j], osum[tt]);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) bsum += (float)av[j];
+        if (dy) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ysum += sy[8 * g + j];
+        }
+        __syncthreads();
     }
-    float* C = Cp + (long long)z * M * N;
-    for (int j = 0; j < 4; ++j) C[((long long)tm * 16 + 4 * g + j) * N + n] = acc[j];
+    float* o = part + (long long)blockIdx.z * pstride;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) o[(long long)(wv * 16 + 4 * g + j) * n_in + n0 + tt * 16 + r16] = acc[tt][j];
+    // the four row shares of a column: lanes r16, r16 + 16, r16 + 32, r16 + 48
+    auto share_sum = [](float v) {
+        v += __shfl_xor(v, 16, 64);
+        return v + __shfl_xor(v, 32, 64);
+    };
+    const float bs = share_sum(bsum);
+    if (blockIdx.x == 0 && g == 0) o[(long long)kHid * n_in + wv * 16 + r16] = bs;
+    if (dy && wv == 0) {
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+            const float os = share_sum(osum[tt]);
+            if (g == 0) o[(long long)kHid * n_in + kHid + tt * 16 + r16] = os;
+        }
+        const float ys = share_sum(ysum);
+        if (blockIdx.x == 0 && lane == 0) o[(long long)kHid * n_in + 2 * kHid] = ys;
+    }
 }
 
-__global__ void k_reduce_splits(const float* Cp, int splits, long long MN, float* C)
+// C[i] = sum over z < parts of part[z * pstride + i], for i < n.  A workgroup takes 16 outputs; its 16
+// thread groups sum every 16th part each, and the 16 group sums are then added in group order, so the
+// result is the same on every run.
+__global__ void __launch_bounds__(256) k_reduce_parts(const float* part, int parts, long long pstride, long long n,
+                                                      float* C)
 {
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= MN) return;
+    __shared__ float red[16][17];
+    const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const long long i = (long long)blockIdx.x * 16 + o;
     float s = 0.f;
-    for (int z = 0; z < splits; ++z) s += Cp[(long long)z * MN + i];
-    C[i] = s;
+    if (i < n)
+        for (int z = g; z < parts; z += 16) s += part[(long long)z * pstride + i];
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        float a = 0.f;
+        for (int k = 0; k < 16; ++k) a += red[k][o];
+        C[i] = a;
+    }
 }
 
-template <typename TA, typename TB>
-hipError_t gemm(const TA* A, long long sam, long long sak, const TB* B, long long sbk, long long sbn, float* C,
-                float* scratch, int M, int N, long long K, int splits, hipStream_t s)
+// Gradient through a hidden layer, written over dZ in place:
+//   dZ[r][c] <- (sum_k dZ[r][k] W[k][c]) silu'(Zp[r][c])
+// (W the layer's BF16 weights [out = k][in = c], Zp the pre-activations of the layer below).  W^T is staged in
+// LDS per workgroup; a wave takes 16 whole rows (all 64 columns), so it has read every input value of its
+// rows before it writes them and no other wave touches them.
+__global__ void __launch_bounds__(256) k_dh_dz(__bf16* dZ, const __bf16* W, const float* Zp, long long rows)
 {
-    dim3 grid((unsigned)((N / 16 + 3) / 4), (unsigned)(M / 16), (unsigned)splits);
-    if (splits == 1) {
-        hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, C, M, N, K, 1);
-        return hipGetLastError();
+    __shared__ __align__(16) __bf16 sW[kHid][kHid + 8];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, r16 = lane & 15, g = lane >> 4;
+    {
+        const int k = t >> 2, c0 = (t & 3) * 16;
+        const uint4 v0 = *(const uint4*)(W + k * kHid + c0);
+        const uint4 v1 = *(const uint4*)(W + k * kHid + c0 + 8);
+        const __bf16* e0 = (const __bf16*)&v0;
+        const __bf16* e1 = (const __bf16*)&v1;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            sW[c0 + j][k] = e0[j];
+            sW[c0 + 8 + j][k] = e1[j];
+        }
     }
-    hipLaunchKernelGGL((k_gemm<TA, TB>), grid, dim3(256), 0, s, A, sam, sak, B, sbk, sbn, scratch, M, N, K, splits);
-    long long MN = (long long)M * N;
-    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, s, scratch, splits, MN, C);
-    return hipGetLastError();
+    __syncthreads();
+    const long long tm = (long long)blockIdx.x * 4 + wv;
+    if (tm * 16 >= rows) return;
+    const long long m = tm * 16 + r16;
+    const bf16x8 a0 = *(const bf16x8*)(dZ + m * kHid + 8 * g);
+    const bf16x8 a1 = *(const bf16x8*)(dZ + m * kHid + 32 + 8 * g);
+    f32x4 acc[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+        const bf16x8 b0 = *(const bf16x8*)&sW[tt * 16 + r16][8 * g];
+        const bf16x8 b1 = *(const bf16x8*)&sW[tt * 16 + r16][32 + 8 * g];
+        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[tt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const long long i = (tm * 16 + 4 * g + j) * kHid + tt * 16 + r16;
+            dZ[i] = (__bf16)(acc[tt][j] * silu_grad(Zp[i]));
+        }
 }
 
 // ----------------------------------------------------------- elementwise
-// dZ[r][c] = dH[r][c] silu'(Z[r][c]); dH either a GEMM result (FP32 [rows][64])
-// or, for the top layer, dy[r] w5[c].
-__global__ void k_dz(const float* dH, const float* dy, const float* w5, const float* Z, __bf16* dZ, long long rows)
+// Top hidden layer: dZ[r][c] = dy[r] w5[c] silu'(Z[r][c]).
+__global__ void k_dz_top(const float* dy, const float* w5, const float* Z, __bf16* dZ, long long rows)
 {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= rows * kHid) return;
     long long r = i / kHid;
     int c = (int)(i - r * kHid);
-    float d = dH ? dH[i] : dy[r] * w5[c];
-    dZ[i] = (__bf16)(d * silu_grad(Z[i]));
-}
-
-// column sums over rows: out[c] = sum_r X[r][c] (X BF16 [rows][ncol]) or, with
-// h given, out[c] = sum_r dy[r] h[r][c] (output-layer weight gradient)
-template <typename T>
-__global__ void k_colsum(const T* X, const float* dy, long long rows, int ncol, float* out)
-{
-    __shared__ float red[256];
-    const int c = blockIdx.x;
-    float s = 0.f;
-    for (long long r = threadIdx.x; r < rows; r += blockDim.x) {
-        float v = (float)X[r * ncol + c];
-        s += dy ? dy[r] * v : v;
-    }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[c] = red[0];
-}
-
-__global__ void k_sum(const float* x, long long n, float* out)
-{
-    __shared__ float red[256];
-    float s = 0.f;
-    for (long long r = threadIdx.x; r < n; r += blockDim.x) s += x[r];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *out = red[0];
+    dZ[i] = (__bf16)(dy[r] * w5[c] * silu_grad(Z[i]));
 }
 
 // Adam with FP32 master weights; refreshes the BF16 copy.
@@ -573,7 +637,6 @@ struct rt_nrc {
     __bf16* H = nullptr;
     float* dy = nullptr;
     __bf16* dZ = nullptr;
-    float* dH = nullptr;
     float* scratch = nullptr;
     float* loss_part = nullptr;
 };
@@ -581,14 +644,14 @@ struct rt_nrc {
 // The cache's workspace in the order it is carved: FP32 master weights, Adam
 // moments, gradients, BF16 weights, then the training activations of a batch
 // of B rows (encoded inputs, pre-activations and activations of the 4 hidden
-// layers, output gradient, layer gradients), the split-K partials of the
-// weight gradients and the per-workgroup loss partials.
+// layers, output gradient, layer gradient), the per-chunk partials of the
+// weight and bias gradients and the per-workgroup loss partials.
 static bool carve_nrc(rt_nrc* nn, size_t B, Carver& c)
 {
     return c.take(&nn->w, kParamsPadded) && c.take(&nn->m, kParamsPadded) && c.take(&nn->v, kParamsPadded) &&
            c.take(&nn->grad, kParamsPadded) && c.take(&nn->wb, kParamsPadded) && c.take(&nn->X, B * kFeat) &&
            c.take(&nn->Z, 4 * B * kHid) && c.take(&nn->H, 4 * B * kHid) && c.take(&nn->dy, B) &&
-           c.take(&nn->dZ, B * kHid) && c.take(&nn->dH, B * kHid) && c.take(&nn->scratch, 64 * (size_t)kHid * kFeat) &&
+           c.take(&nn->dZ, B * kHid) && c.take(&nn->scratch, kMaxSplits * (size_t)(kHid * kFeat + kHid)) &&
            c.take(&nn->loss_part, (size_t)nn->n_wgs);
 }
 
@@ -645,43 +708,41 @@ static hipError_t nrc_forward_rows(rt_nrc* nn, const float* raw, const float* ta
     return launch_nrc_forward(a, nn->n_wgs, s);
 }
 
-// backward of the last training forward (rows in nn->X, Z, H, dy): gradients into nn->grad
+// Backward of the last training forward (rows in nn->X, Z, H, dy): gradients into nn->grad.  The rows are
+// cut into `splits` chunks; per chunk, one kernel per layer sums the weight gradient on the matrix cores and
+// the bias gradient beside it (a layer's weights and bias are adjacent in the parameter layout, and so are
+// the top layer's and the output layer's, whose partials the top layer's kernel adds), and one reduction
+// per layer adds the chunks in a fixed order.  The gradient then passes to the layer below in place.
+static int backward_splits(long long rows)
+{
+    int splits = 1;
+    while (splits < kMaxSplits && (rows / (splits * 2)) % 32 == 0 && rows / (splits * 2) >= 256) splits *= 2;
+    return splits;
+}
+
 static hipError_t nrc_backward(rt_nrc* nn, long long rows, hipStream_t s)
 {
     const long long R = rows;
-    const unsigned eb = (unsigned)((R * kHid + 255) / 256);
-    int splits = 1;
-    while (splits < 64 && (R / (splits * 2)) % 32 == 0 && R / (splits * 2) >= 256) splits *= 2;
-    hipError_t e;
+    const int splits = backward_splits(R);
+    const long long rpp = R / splits;
     const __bf16* Hl[4] = {nn->H, nn->H + R * kHid, nn->H + 2 * R * kHid, nn->H + 3 * R * kHid};
     const float* Zl[4] = {nn->Z, nn->Z + R * kHid, nn->Z + 2 * R * kHid, nn->Z + 3 * R * kHid};
     const int offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
-    const int offB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
-    // output layer
-    hipLaunchKernelGGL((k_colsum<__bf16>), dim3(kHid), dim3(256), 0, s, Hl[3], nn->dy, R, kHid, nn->grad + kOffW5);
-    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, nn->dy, R, nn->grad + kOffB5);
-    // top hidden layer: dZ4 = dy w5 silu'(Z4)
-    hipLaunchKernelGGL(k_dz, dim3(eb), dim3(256), 0, s, (const float*)nullptr, nn->dy, nn->w + kOffW5, Zl[3], nn->dZ, R);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int nin[4] = {kFeat, kHid, kHid, kHid};
+    hipLaunchKernelGGL(k_dz_top, dim3((unsigned)((R * kHid + 255) / 256)), dim3(256), 0, s, nn->dy, nn->w + kOffW5,
+                       Zl[3], nn->dZ, R);
     for (int L = 3; L >= 0; --L) {
-        // dW_L = dZ^T . (H_{L-1} or X); db_L = column sums of dZ
-        if (L > 0) {
-            e = gemm<__bf16, __bf16>(nn->dZ, 1, kHid, Hl[L - 1], kHid, 1, nn->grad + offW[L], nn->scratch, kHid, kHid, R,
-                                     splits, s);
-        } else {
-            e = gemm<__bf16, __bf16>(nn->dZ, 1, kHid, nn->X, kFeat, 1, nn->grad + offW[0], nn->scratch, kHid, kFeat, R,
-                                     splits, s);
-        }
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_colsum<__bf16>), dim3(kHid), dim3(256), 0, s, nn->dZ, (const float*)nullptr, R, kHid,
-                           nn->grad + offB[L]);
-        if (L == 0) break;
-        // dH_{L-1} = dZ_L . W_L ; dZ_{L-1} = dH silu'(Z_{L-1})
-        e = gemm<__bf16, __bf16>(nn->dZ, kHid, 1, nn->wb + offW[L], kHid, 1, nn->dH, nn->scratch, (int)R, kHid, kHid, 1, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_dz, dim3(eb), dim3(256), 0, s, nn->dH, (const float*)nullptr, (const float*)nullptr, Zl[L - 1],
-                           nn->dZ, R);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        // dW_L = dZ_L^T . (H_{L-1} or X) and db_L (+ dW5, db5 on the top layer) per chunk, then summed
+        const long long pstride = (long long)kHid * nin[L] + kHid + (L == 3 ? kHid + 1 : 0);
+        hipLaunchKernelGGL(k_gemm_dw, dim3((unsigned)(nin[L] / 64), 1u, (unsigned)splits), dim3(256), 0, s, nn->dZ,
+                           L > 0 ? Hl[L - 1] : nn->X, nin[L], L == 3 ? (const float*)nn->dy : nullptr,
+                           L == 3 ? Hl[3] : nullptr, rpp, nn->scratch, pstride);
+        hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((pstride + 15) / 16)), dim3(256), 0, s, nn->scratch, splits,
+                           pstride, pstride, nn->grad + offW[L]);
+        // dZ_{L-1} = (dZ_L . W_L) silu'(Z_{L-1})
+        if (L > 0)
+            hipLaunchKernelGGL(k_dh_dz, dim3((unsigned)((R + 63) / 64)), dim3(256), 0, s, nn->dZ, nn->wb + offW[L],
+                               Zl[L - 1], R);
     }
     return hipGetLastError();
 }
