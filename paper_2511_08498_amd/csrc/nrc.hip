@@ -28,7 +28,7 @@ constexpr int kFeat = 256;
 constexpr int kHid = 64;
 constexpr int kNFreq = 16;
 constexpr int kRaw = 12;  // pos 3, dir 3, lam 1, stats 4, weight 1
-constexpr int kMaxSplits = 64;  // row chunks of the backward's gradient sums
+constexpr int kMaxSplits = 256;  // row chunks (workgroups) of the backward's gradient sums
 
 // parameter layout (FP32 master copy and BF16 working copy share it)
 constexpr int kOffW1 = 0;
@@ -355,99 +355,170 @@ hipError_t launch_nrc_forward(const NrcFwd& a, int n_wgs, hipStream_t s)
     return hipGetLastError();
 }
 
-// ----------------------------------------------------------- backward GEMMs
-// Weight-gradient partials of one layer over row chunk z = blockIdx.z (rows [z rpp, (z + 1) rpp)):
-//   part[z pstride + m n_in + n] = sum_r dZ[r][m] In[r][n]        (m < 64, n < n_in)
-// dZ BF16 [rows][64], In BF16 [rows][n_in].  A workgroup takes one 64-column strip of n (blockIdx.x) and its
-// four waves one 16-row tile of m each.  Every 32-row slice of dZ and of the strip of In is read with
-// coalesced 16-byte loads and stored transposed in LDS ([column][row], rows padded to 40), so each MFMA
-// operand is one 16-byte LDS read and the dZ fragment serves the strip's four column tiles.  The strip-0
-// workgroup also writes the bias partial part[z pstride + 64 n_in + m] = sum_r dZ[r][m]; with dy and Ho given
-// (the top layer, n_in = 64; Ho BF16 [rows][64] its output activations) wave 0 writes the output layer's
-// partials part[z pstride + 64 n_in + 64 + c] = sum_r dy[r] Ho[r][c] and part[z pstride + 64 n_in + 128] =
-// sum_r dy[r], from an LDS slice of Ho staged like In's.
-// Each lane's sums run over its fixed share of the rows and the four shares are added in a fixed order.
-__global__ void __launch_bounds__(256) k_gemm_dw(const __bf16* dZ, const __bf16* In, int n_in, const float* dy,
-                                                 const __bf16* Ho, long long rpp, float* part, long long pstride)
+// ----------------------------------------------------------- backward
+// The whole backward of a chunk of rows in one workgroup (4 waves), layer by layer from the top, with the
+// layer gradient dZ kept in LDS (row-major for dH = dZ W, transposed for dW = dZ^T In):
+//   top:  dZ4 = dy w5 silu'(Z4);  db4, dW5 = sum_r dy[r] H4[r][.], db5 = sum_r dy[r]
+//   L = 4..1:  dW_L = dZ_L^T In_L (In_L = H_{L-1}, or the encoded input X for L = 1), on the matrix cores;
+//              dZ_{L-1} = (dZ_L W_L) silu'(Z_{L-1}) on the matrix cores, and its column sums db_{L-1}.
+// A workgroup's rows are 64-row sub-chunks z, z + chunks, z + 2 chunks, ... of the batch; each sum over them
+// goes into the workgroup's own copy of the parameter layout (part + z kParamsPadded), written by its first
+// sub-chunk and added to by the next ones, in order.  MFMA operands are 16-byte LDS reads: In and W are
+// staged transposed with coalesced 16-byte global loads.  Column sums combine a thread's rows first and the
+// four row groups of a column in a fixed order, so every result is the same on every run.
+constexpr int kBwdRows = 64;         // rows of a sub-chunk
+constexpr int kBP = kBwdRows + 8;    // padded row pitch of the transposed tiles (144 B, 16-byte aligned)
+constexpr int kUP = kHid + 8;        // padded row pitch of the row-major tiles
+
+struct NrcBwd {
+    const __bf16* X;   // [rows][256] encoded inputs
+    const __bf16* H;   // 4 x [rows][64] hidden activations
+    const float* Z;    // 4 x [rows][64] pre-activations
+    const float* dy;   // [rows] output gradient
+    const float* w5;   // FP32 output weights
+    const __bf16* wb;  // BF16 weights
+    long long rows;
+    int chunks;
+    float* part;       // [chunks][kParamsPadded]
+};
+
+__global__ void __launch_bounds__(256) k_nrc_backward(NrcBwd a)
 {
-    constexpr int kKS = 32, kPad = kKS + 8;
-    __shared__ __align__(16) __bf16 sA[kHid][kPad];
-    __shared__ __align__(16) __bf16 sB[64][kPad];
-    __shared__ __align__(16) __bf16 sC[kHid][kPad];
-    __shared__ float sy[kKS];
+    __shared__ __align__(16) __bf16 sZ[kBwdRows][kUP];
+    __shared__ __align__(16) __bf16 sZt[kHid][kBP];
+    __shared__ __align__(16) __bf16 sIn[kFeat][kBP];
+    __shared__ __align__(16) __bf16 sWt[kHid][kUP];
+    __shared__ float red[3][256];
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6, r16 = lane & 15, g = lane >> 4;
-    const int n0 = blockIdx.x * 64;
-    const long long r_begin = (long long)blockIdx.z * rpp, r_end = r_begin + rpp;
-    const int lk = t >> 3, lc = (t & 7) * 8;  // staging: row lk of the slice, columns lc .. lc + 7
-    f32x4 acc[4];
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bsum = 0.f, ysum = 0.f, osum[4] = {0.f, 0.f, 0.f, 0.f};
-    for (long long k0 = r_begin; k0 < r_end; k0 += kKS) {
-        const uint4 va = *(const uint4*)(dZ + (k0 + lk) * kHid + lc);
-        const uint4 vb = *(const uint4*)(In + (k0 + lk) * n_in + n0 + lc);
-        const __bf16* ea = (const __bf16*)&va;
-        const __bf16* eb = (const __bf16*)&vb;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            sA[lc + j][lk] = ea[j];
-            sB[lc + j][lk] = eb[j];
-        }
-        if (dy) {
-            if (t < kKS) sy[t] = dy[k0 + t];
-            const uint4 vc = *(const uint4*)(Ho + (k0 + lk) * kHid + lc);
-            const __bf16* ec = (const __bf16*)&vc;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) sC[lc + j][lk] = ec[j];
-        }
-        __syncthreads();
-        const bf16x8 av = *(const bf16x8*)&sA[wv * 16 + r16][8 * g];
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            const bf16x8 bv = *(const bf16x8*)&sB[tt * 16 + r16][8 * g];
-            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[tt], 0, 0, 0);
-            if (dy && wv == 0) {
-                const bf16x8 hv = *(const bf16x8*)&sC[tt * 16 + r16][8 * g];
-#pragma unroll
-                for (int j = 0; j < 8; ++j) osum[tt] = fmaf(sy[8 * g + j], (float)hv[j], osum[tt]);
+    const long long R = a.rows;
+    const long long nsub = R / kBwdRows;
+    float* part = a.part + (long long)blockIdx.x * kParamsPadded;
+    const int offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
+    const int offB[4] = {kOffB1, kOffB2, kOffB3, kOffB4};
+    const int nin[4] = {kFeat, kHid, kHid, kHid};
+    auto four = [&](int k, int c) { return (red[k][c] + red[k][c + 64]) + (red[k][c + 128] + red[k][c + 192]); };
+    for (long long sc = blockIdx.x; sc < nsub; sc += a.chunks) {
+        const bool first = sc == (long long)blockIdx.x;
+        auto put = [&](int i, float v) { part[i] = first ? v : part[i] + v; };
+        const long long r0 = sc * kBwdRows;
+        {
+            const int c = t & 63, ph = t >> 6;
+            const float wc = a.w5[c];
+            const float* Z4 = a.Z + 3 * R * kHid;
+            const __bf16* H4 = a.H + 3 * R * kHid;
+            float sb = 0.f, sw = 0.f, sy = 0.f;
+            for (int rr = ph; rr < kBwdRows; rr += 4) {
+                const long long i = (r0 + rr) * kHid + c;
+                const float y = a.dy[r0 + rr];
+                const __bf16 v = (__bf16)(y * wc * silu_grad(Z4[i]));
+                sZ[rr][c] = v;
+                sZt[c][rr] = v;
+                sb += (float)v;
+                sw += y * (float)H4[i];
+                sy += y;
             }
-        }
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bsum += (float)av[j];
-        if (dy) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) ysum += sy[8 * g + j];
+            red[0][t] = sb;
+            red[1][t] = sw;
+            red[2][t] = sy;
         }
         __syncthreads();
-    }
-    float* o = part + (long long)blockIdx.z * pstride;
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) o[(long long)(wv * 16 + 4 * g + j) * n_in + n0 + tt * 16 + r16] = acc[tt][j];
-    // the four row shares of a column: lanes r16, r16 + 16, r16 + 32, r16 + 48
-    auto share_sum = [](float v) {
-        v += __shfl_xor(v, 16, 64);
-        return v + __shfl_xor(v, 32, 64);
-    };
-    const float bs = share_sum(bsum);
-    if (blockIdx.x == 0 && g == 0) o[(long long)kHid * n_in + wv * 16 + r16] = bs;
-    if (dy && wv == 0) {
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-            const float os = share_sum(osum[tt]);
-            if (g == 0) o[(long long)kHid * n_in + kHid + tt * 16 + r16] = os;
+        if (t < kHid) {
+            put(kOffB4 + t, four(0, t));
+            put(kOffW5 + t, four(1, t));
+            if (t == 0) put(kOffB5, four(2, 0));
         }
-        const float ys = share_sum(ysum);
-        if (blockIdx.x == 0 && lane == 0) o[(long long)kHid * n_in + 2 * kHid] = ys;
+        for (int L = 3; L >= 0; --L) {
+            const int n_in = nin[L];
+            const __bf16* In = L > 0 ? a.H + (long long)(L - 1) * R * kHid : a.X;
+            for (int q = t; q < n_in * kBwdRows / 8; q += 256) {
+                const int rr = q / (n_in / 8), c8 = (q - rr * (n_in / 8)) * 8;
+                const uint4 v = *(const uint4*)(In + (r0 + rr) * n_in + c8);
+                const __bf16* e = (const __bf16*)&v;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) sIn[c8 + j][rr] = e[j];
+            }
+            if (L > 0) {
+                // W_L [out][in] -> sWt[in][out]
+                const int k = t >> 2, c0 = (t & 3) * 16;
+                const __bf16* W = a.wb + offW[L];
+                const uint4 v0 = *(const uint4*)(W + k * kHid + c0);
+                const uint4 v1 = *(const uint4*)(W + k * kHid + c0 + 8);
+                const __bf16* e0 = (const __bf16*)&v0;
+                const __bf16* e1 = (const __bf16*)&v1;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    sWt[c0 + j][k] = e0[j];
+                    sWt[c0 + 8 + j][k] = e1[j];
+                }
+            }
+            __syncthreads();
+            {
+                // dW_L: wave wv takes units 16 wv .. 16 wv + 15, K = the sub-chunk's 64 rows
+                const bf16x8 a0 = *(const bf16x8*)&sZt[wv * 16 + r16][8 * g];
+                const bf16x8 a1 = *(const bf16x8*)&sZt[wv * 16 + r16][32 + 8 * g];
+                for (int nt = 0; nt < n_in / 16; ++nt) {
+                    const bf16x8 b0 = *(const bf16x8*)&sIn[nt * 16 + r16][8 * g];
+                    const bf16x8 b1 = *(const bf16x8*)&sIn[nt * 16 + r16][32 + 8 * g];
+                    f32x4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc, 0, 0, 0);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) put(offW[L] + (wv * 16 + 4 * g + j) * n_in + nt * 16 + r16, acc[j]);
+                }
+            }
+            if (L == 0) break;
+            // dH = dZ_L W_L: wave wv takes rows 16 wv .. 16 wv + 15 and all 64 units
+            f32x4 acc[4];
+            {
+                const bf16x8 a0 = *(const bf16x8*)&sZ[wv * 16 + r16][8 * g];
+                const bf16x8 a1 = *(const bf16x8*)&sZ[wv * 16 + r16][32 + 8 * g];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    const bf16x8 b0 = *(const bf16x8*)&sWt[tt * 16 + r16][8 * g];
+                    const bf16x8 b1 = *(const bf16x8*)&sWt[tt * 16 + r16][32 + 8 * g];
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+                    acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[tt], 0, 0, 0);
+                }
+            }
+            __syncthreads();  // every read of layer L's tiles is done
+            const float* Zp = a.Z + (long long)(L - 1) * R * kHid;
+#pragma unroll
+            for (int tt = 0; tt < 4; ++tt) {
+                float cs = 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int rr = wv * 16 + 4 * g + j, c = tt * 16 + r16;
+                    const __bf16 v = (__bf16)(acc[tt][j] * silu_grad(Zp[(r0 + rr) * kHid + c]));
+                    sZ[rr][c] = v;
+                    sZt[c][rr] = v;
+                    cs += (float)v;
+                }
+                // the wave's 16 rows of column c: lanes r16, r16 + 16, r16 + 32, r16 + 48 hold 4 each
+                cs += __shfl_xor(cs, 16, 64);
+                cs += __shfl_xor(cs, 32, 64);
+                if (g == 0) red[0][wv * 64 + tt * 16 + r16] = cs;
+            }
+            __syncthreads();
+            if (t < kHid) put(offB[L - 1] + t, four(0, t));
+        }
+        __syncthreads();  // the sub-chunk's tiles are free for the next one
     }
 }
 
+// One Adam step with FP32 master weights (bias corrections c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)), which
+// also refreshes the BF16 working copy.
+struct AdamStep {
+    float* w;
+    float* m;
+    float* v;
+    __bf16* wb;
+    float lr, b1, b2, eps, c1, c2;
+};
+
 // C[i] = sum over z < parts of part[z * pstride + i], for i < n.  A workgroup takes 16 outputs; its 16
 // thread groups sum every 16th part each, and the 16 group sums are then added in group order, so the
-// result is the same on every run.
+// result is the same on every run.  With adam.w given, parameter i then takes its Adam step with C[i].
 __global__ void __launch_bounds__(256) k_reduce_parts(const float* part, int parts, long long pstride, long long n,
-                                                      float* C)
+                                                      float* C, AdamStep adam)
 {
     __shared__ float red[16][17];
     const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
@@ -457,82 +528,18 @@ __global__ void __launch_bounds__(256) k_reduce_parts(const float* part, int par
         for (int z = g; z < parts; z += 16) s += part[(long long)z * pstride + i];
     red[g][o] = s;
     __syncthreads();
-    if (g == 0 && i < n) {
-        float a = 0.f;
-        for (int k = 0; k < 16; ++k) a += red[k][o];
-        C[i] = a;
-    }
-}
-
-// Gradient through a hidden layer, written over dZ in place:
-//   dZ[r][c] <- (sum_k dZ[r][k] W[k][c]) silu'(Zp[r][c])
-// (W the layer's BF16 weights [out = k][in = c], Zp the pre-activations of the layer below).  W^T is staged in
-// LDS per workgroup; a wave takes 16 whole rows (all 64 columns), so it has read every input value of its
-// rows before it writes them and no other wave touches them.
-__global__ void __launch_bounds__(256) k_dh_dz(__bf16* dZ, const __bf16* W, const float* Zp, long long rows)
-{
-    __shared__ __align__(16) __bf16 sW[kHid][kHid + 8];
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6, r16 = lane & 15, g = lane >> 4;
-    {
-        const int k = t >> 2, c0 = (t & 3) * 16;
-        const uint4 v0 = *(const uint4*)(W + k * kHid + c0);
-        const uint4 v1 = *(const uint4*)(W + k * kHid + c0 + 8);
-        const __bf16* e0 = (const __bf16*)&v0;
-        const __bf16* e1 = (const __bf16*)&v1;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            sW[c0 + j][k] = e0[j];
-            sW[c0 + 8 + j][k] = e1[j];
-        }
-    }
-    __syncthreads();
-    const long long tm = (long long)blockIdx.x * 4 + wv;
-    if (tm * 16 >= rows) return;
-    const long long m = tm * 16 + r16;
-    const bf16x8 a0 = *(const bf16x8*)(dZ + m * kHid + 8 * g);
-    const bf16x8 a1 = *(const bf16x8*)(dZ + m * kHid + 32 + 8 * g);
-    f32x4 acc[4];
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-        const bf16x8 b0 = *(const bf16x8*)&sW[tt * 16 + r16][8 * g];
-        const bf16x8 b1 = *(const bf16x8*)&sW[tt * 16 + r16][32 + 8 * g];
-        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[tt], 0, 0, 0);
-    }
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const long long i = (tm * 16 + 4 * g + j) * kHid + tt * 16 + r16;
-            dZ[i] = (__bf16)(acc[tt][j] * silu_grad(Zp[i]));
-        }
-}
-
-// ----------------------------------------------------------- elementwise
-// Top hidden layer: dZ[r][c] = dy[r] w5[c] silu'(Z[r][c]).
-__global__ void k_dz_top(const float* dy, const float* w5, const float* Z, __bf16* dZ, long long rows)
-{
-    long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows * kHid) return;
-    long long r = i / kHid;
-    int c = (int)(i - r * kHid);
-    dZ[i] = (__bf16)(dy[r] * w5[c] * silu_grad(Z[i]));
-}
-
-// Adam with FP32 master weights; refreshes the BF16 copy.
-__global__ void k_adam(float* w, float* m, float* v, const float* g, __bf16* wb, int n, float lr, float b1, float b2,
-                       float eps, float c1, float c2)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float gi = g[i];
-    float mi = b1 * m[i] + (1.f - b1) * gi;
-    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
-    w[i] = wi;
-    wb[i] = (__bf16)wi;
+    if (g != 0 || i >= n) return;
+    float gi = 0.f;
+    for (int k = 0; k < 16; ++k) gi += red[k][o];
+    C[i] = gi;
+    if (!adam.w) return;
+    const float mi = adam.b1 * adam.m[i] + (1.f - adam.b1) * gi;
+    const float vi = adam.b2 * adam.v[i] + (1.f - adam.b2) * gi * gi;
+    adam.m[i] = mi;
+    adam.v[i] = vi;
+    const float wi = adam.w[i] - adam.lr * (mi * adam.c1) / (sqrtf(vi * adam.c2) + adam.eps);
+    adam.w[i] = wi;
+    adam.wb[i] = (__bf16)wi;
 }
 
 __global__ void k_to_bf16(const float* w, __bf16* wb, int n)
@@ -636,7 +643,6 @@ struct rt_nrc {
     float* Z = nullptr;
     __bf16* H = nullptr;
     float* dy = nullptr;
-    __bf16* dZ = nullptr;
     float* scratch = nullptr;
     float* loss_part = nullptr;
 };
@@ -644,14 +650,14 @@ struct rt_nrc {
 // The cache's workspace in the order it is carved: FP32 master weights, Adam
 // moments, gradients, BF16 weights, then the training activations of a batch
 // of B rows (encoded inputs, pre-activations and activations of the 4 hidden
-// layers, output gradient, layer gradient), the per-chunk partials of the
-// weight and bias gradients and the per-workgroup loss partials.
+// layers, output gradient), one copy of the parameter layout per row chunk
+// for the gradient partials, and the per-workgroup loss partials.
 static bool carve_nrc(rt_nrc* nn, size_t B, Carver& c)
 {
     return c.take(&nn->w, kParamsPadded) && c.take(&nn->m, kParamsPadded) && c.take(&nn->v, kParamsPadded) &&
            c.take(&nn->grad, kParamsPadded) && c.take(&nn->wb, kParamsPadded) && c.take(&nn->X, B * kFeat) &&
            c.take(&nn->Z, 4 * B * kHid) && c.take(&nn->H, 4 * B * kHid) && c.take(&nn->dy, B) &&
-           c.take(&nn->dZ, B * kHid) && c.take(&nn->scratch, kMaxSplits * (size_t)(kHid * kFeat + kHid)) &&
+           c.take(&nn->scratch, kMaxSplits * (size_t)kParamsPadded) &&
            c.take(&nn->loss_part, (size_t)nn->n_wgs);
 }
 
@@ -708,42 +714,25 @@ static hipError_t nrc_forward_rows(rt_nrc* nn, const float* raw, const float* ta
     return launch_nrc_forward(a, nn->n_wgs, s);
 }
 
-// Backward of the last training forward (rows in nn->X, Z, H, dy): gradients into nn->grad.  The rows are
-// cut into `splits` chunks; per chunk, one kernel per layer sums the weight gradient on the matrix cores and
-// the bias gradient beside it (a layer's weights and bias are adjacent in the parameter layout, and so are
-// the top layer's and the output layer's, whose partials the top layer's kernel adds), and one reduction
-// per layer adds the chunks in a fixed order.  The gradient then passes to the layer below in place.
-static int backward_splits(long long rows)
+// Backward of the last training forward (rows in nn->X, Z, H, dy): gradients into nn->grad, followed by
+// an Adam step when `adam` names the weights.  One workgroup per chunk of rows sums every parameter's
+// gradient over its rows into its own copy of the parameter layout (k_nrc_backward); one reduction over
+// all parameters then adds the chunks in a fixed order.
+static hipError_t nrc_backward(rt_nrc* nn, long long rows, const AdamStep& adam, hipStream_t s)
 {
-    int splits = 1;
-    while (splits < kMaxSplits && (rows / (splits * 2)) % 32 == 0 && rows / (splits * 2) >= 256) splits *= 2;
-    return splits;
-}
-
-static hipError_t nrc_backward(rt_nrc* nn, long long rows, hipStream_t s)
-{
-    const long long R = rows;
-    const int splits = backward_splits(R);
-    const long long rpp = R / splits;
-    const __bf16* Hl[4] = {nn->H, nn->H + R * kHid, nn->H + 2 * R * kHid, nn->H + 3 * R * kHid};
-    const float* Zl[4] = {nn->Z, nn->Z + R * kHid, nn->Z + 2 * R * kHid, nn->Z + 3 * R * kHid};
-    const int offW[4] = {kOffW1, kOffW2, kOffW3, kOffW4};
-    const int nin[4] = {kFeat, kHid, kHid, kHid};
-    hipLaunchKernelGGL(k_dz_top, dim3((unsigned)((R * kHid + 255) / 256)), dim3(256), 0, s, nn->dy, nn->w + kOffW5,
-                       Zl[3], nn->dZ, R);
-    for (int L = 3; L >= 0; --L) {
-        // dW_L = dZ_L^T . (H_{L-1} or X) and db_L (+ dW5, db5 on the top layer) per chunk, then summed
-        const long long pstride = (long long)kHid * nin[L] + kHid + (L == 3 ? kHid + 1 : 0);
-        hipLaunchKernelGGL(k_gemm_dw, dim3((unsigned)(nin[L] / 64), 1u, (unsigned)splits), dim3(256), 0, s, nn->dZ,
-                           L > 0 ? Hl[L - 1] : nn->X, nin[L], L == 3 ? (const float*)nn->dy : nullptr,
-                           L == 3 ? Hl[3] : nullptr, rpp, nn->scratch, pstride);
-        hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((pstride + 15) / 16)), dim3(256), 0, s, nn->scratch, splits,
-                           pstride, pstride, nn->grad + offW[L]);
-        // dZ_{L-1} = (dZ_L . W_L) silu'(Z_{L-1})
-        if (L > 0)
-            hipLaunchKernelGGL(k_dh_dz, dim3((unsigned)((R + 63) / 64)), dim3(256), 0, s, nn->dZ, nn->wb + offW[L],
-                               Zl[L - 1], R);
-    }
+    NrcBwd b;
+    b.X = nn->X;
+    b.H = nn->H;
+    b.Z = nn->Z;
+    b.dy = nn->dy;
+    b.w5 = nn->w + kOffW5;
+    b.wb = nn->wb;
+    b.rows = rows;
+    b.chunks = (int)std::min<long long>(rows / kBwdRows, kMaxSplits);
+    b.part = nn->scratch;
+    hipLaunchKernelGGL(k_nrc_backward, dim3((unsigned)b.chunks), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((kNParams + 15) / 16)), dim3(256), 0, s, nn->scratch, b.chunks,
+                       (long long)kParamsPadded, (long long)kNParams, nn->grad, adam);
     return hipGetLastError();
 }
 
@@ -880,13 +869,11 @@ rt_status rt_nrc_train(rt_nrc* nn, const float* d_raw, const float* d_target, in
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
     for (int it = 0; it < steps; ++it) {
         NRC_HIP(nrc_forward_rows(nn, d_raw, d_target, n, batch, 0, true, nullptr, s));
-        NRC_HIP(nrc_backward(nn, batch, s));
         ++nn->step;
-        float c1 = 1.0f / (1.0f - std::pow(b1, (float)nn->step));
-        float c2 = 1.0f / (1.0f - std::pow(b2, (float)nn->step));
-        hipLaunchKernelGGL(k_adam, dim3((kNParams + 255) / 256), dim3(256), 0, s, nn->w, nn->m, nn->v, nn->grad, nn->wb,
-                           kNParams, lr, b1, b2, eps, c1, c2);
-        NRC_HIP(hipGetLastError());
+        const AdamStep adam = {nn->w, nn->m, nn->v, nn->wb, lr, b1, b2, eps,
+                               1.0f / (1.0f - std::pow(b1, (float)nn->step)),
+                               1.0f / (1.0f - std::pow(b2, (float)nn->step))};
+        NRC_HIP(nrc_backward(nn, batch, adam, s));
     }
     nn->last_rows = batch;
     return RT_OK;
@@ -910,7 +897,7 @@ rt_status rt_nrc_gradients(rt_nrc* nn, const float* d_raw, const float* d_target
     if (n < 256 || n % 256 != 0 || n > nn->max_batch) return set_error(RT_E_ARG, "n must be a multiple of 256 up to max_batch");
     hipStream_t s = (hipStream_t)stream;
     NRC_HIP(nrc_forward_rows(nn, d_raw, d_target, n, n, 1, true, nullptr, s));
-    NRC_HIP(nrc_backward(nn, n, s));
+    NRC_HIP(nrc_backward(nn, n, AdamStep{}, s));
     NRC_HIP(hipMemcpyAsync(d_grad, nn->grad, sizeof(float) * kNParams, hipMemcpyDeviceToDevice, s));
     nn->last_rows = (int)n;
     return RT_OK;

@@ -177,13 +177,17 @@ def test_forward_matches_oracle(rt):
     assert np.linalg.norm(y - y64) / np.linalg.norm(y64) < 2e-2
 
 
-def test_gradients_match_oracle(rt):
-    nn = rt.Nrc(max_batch=8192, freq_max=16.0, seed=3)
+@pytest.mark.parametrize("rows", [512, 16640])
+def test_gradients_match_oracle(rt, rows):
+    """512 rows: eight 64-row chunks, one per workgroup.  16640 rows: 260 chunks on 256 workgroups, so four
+    workgroups add a second chunk to their partial; the gradients are also the same bits on a second call."""
+    nn = rt.Nrc(max_batch=16640, freq_max=16.0, seed=3)
     rng = np.random.default_rng(2)
-    raw = _raw_rows(rng, 512)
+    raw = _raw_rows(rng, rows)
     raw[::7, 11] = 0.0  # ignored rows
-    tgt = (rng.normal(size=512) * 0.3).astype(np.float32)
+    tgt = (rng.normal(size=rows) * 0.3).astype(np.float32)
     g = nn.gradients(raw, tgt).cpu().numpy().astype(np.float64)
+    assert np.array_equal(nn.gradients(raw, tgt).cpu().numpy(), g.astype(np.float32))
     p = _emulated_params(nn.get_weights())
     X = onrc.encode(raw[:, :11].astype(np.float64), 16.0)
     g_ref = onrc.gradients(p, X, tgt.astype(np.float64), raw[:, 11].astype(np.float64), onrc.bf16_round)

@@ -54,11 +54,11 @@ def test_scene_descriptor_validation(rt):
 
 def test_nrc_workspace_bytes(rt):
     B = 16384
-    # weights/Adam/gradient (FP32, padded to 256) + BF16 copy, activations, output and layer gradients,
-    # per-chunk gradient partials (64 chunks of the largest layer's weights + bias), loss partials
+    # weights/Adam/gradient (FP32, padded to 256) + BF16 copy, activations, output gradient,
+    # per-chunk gradient partials (256 chunks of the padded parameter layout), loss partials
     npad = (rt.nrc_num_params() + 255) // 256 * 256
-    expect = (4 * 4 * npad + 2 * npad + 2 * B * 256 + 4 * 4 * B * 64 + 2 * 4 * B * 64 + 4 * B + 2 * B * 64
-              + 4 * 64 * (64 * 256 + 64) + 4 * 512)
+    expect = (4 * 4 * npad + 2 * npad + 2 * B * 256 + 4 * 4 * B * 64 + 2 * 4 * B * 64 + 4 * B + 4 * 256 * npad
+              + 4 * 512)
     assert rt.nrc_workspace_bytes(B) == expect
     for bad in (0, 300, 1 << 20):
         with pytest.raises(rt.RtError):
