@@ -53,13 +53,19 @@ __device__ __forceinline__ float voigt_h(float a, float x)
     float inv = __builtin_amdgcn_rcpf(dr * dr + di * di);
     float Zr = (nr * dr + ni * di) * inv;
     float Zi = (ni * dr - nr * di) * inv;
-    float pr = c[23], pi = 0.0f;
+    // p(Z) = sum_k c_k Z^k has real coefficients: divided by the real quadratic (t - Z)(t - conj Z) =
+    // t^2 - 2 Re Z t + |Z|^2 it leaves a remainder b1 t + b0, so p(Z) = Z b1 + (c_0 - |Z|^2 b2) with the
+    // second-order recurrence b_k = c_k + 2 Re Z b_{k+1} - |Z|^2 b_{k+2} (Horner's scheme for a complex
+    // argument, Knuth, TAOCP vol. 2, 4.6.4): two real FMAs per coefficient instead of a complex multiply-add.
+    const float tz = 2.0f * Zr, m2 = fmaf(Zr, Zr, Zi * Zi);
+    float b2 = 0.0f, b1 = c[23];
 #pragma unroll
-    for (int k = 22; k >= 0; --k) {
-        float tr = fmaf(pr, Zr, fmaf(-pi, Zi, c[k]));
-        pi = fmaf(pr, Zi, pi * Zr);
-        pr = tr;
+    for (int k = 22; k >= 1; --k) {
+        const float b0 = fmaf(tz, b1, fmaf(-m2, b2, c[k]));
+        b2 = b1;
+        b1 = b0;
     }
+    const float pr = fmaf(Zr, b1, fmaf(-m2, b2, c[0])), pi = Zi * b1;
     // 1/(L - i z) and its square
     float ir = dr * inv, ii = -di * inv;
     float i2r = ir * ir - ii * ii, i2i = 2.0f * ir * ii;
