@@ -158,20 +158,24 @@ hipError_t launch_vgrid(const Geo& g, const Inputs& in, const SceneBufs& b, int 
 
 // ------------------------------------------------------ velocity node values
 // One workgroup per (active brick, direction class); one thread per (level
-// cell, node) item.  The
-// thread walks the cell's MIP-0 voxels once, reads each voxel's line
-// parameters once, evaluates eta, chi at the node velocity for all 8 batch
-// wavelengths and accumulates them (ln values in log mode) in registers, then
-// writes the item's record: 64 bytes in FP32, or 32 bytes rounded to nearest
-// even in BF16 / FP16 (packed at half the stride in the same buffer).  Values,
-// not decisions: FP32 sums.
+// cell, node) item.  The workgroup first stages the brick's voxel inputs in
+// LDS ([voxel][eta_bg, chi_bg, then eta*, chi*, a, 1/dlD per line]); each
+// thread then walks its cell's MIP-0 voxels, evaluates eta, chi at the node
+// velocity for all 8 batch wavelengths and accumulates them (ln values in log
+// mode) in registers, and writes the item's record: 64 bytes in FP32, or 32
+// bytes rounded to nearest even in BF16 / FP16 (packed at half the stride in
+// the same buffer).  Values, not decisions: FP32 sums.  (The 41 node items of
+// a cell read the same voxels, so the LDS reads broadcast; read from global
+// memory, every voxel step waited on a dependent load.)
 __device__ __forceinline__ unsigned enc_bits(__hip_bfloat16, float v)
 {
     return __bfloat16_as_ushort(Codec<__hip_bfloat16>::enc(v));
 }
 __device__ __forceinline__ unsigned enc_bits(__half, float v) { return __half_as_ushort(Codec<__half>::enc(v)); }
 
-template <int D, typename T>
+// PROF: the line profile (Gaussian or Voigt) and NL: the lines the loops are unrolled for (2, or kMaxLines),
+// both fixed per launch, so the per-voxel loop has no branch on either.
+template <int D, typename T, int PROF, int NL>
 __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, SceneBufs bufs, LamBatch lb, int n_v,
                                                           float ds0, int avg_mode)
 {
@@ -188,6 +192,24 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
         k0[k] = (float)(lb.lam0[k] / kCkms);
         for (int l = 0; l < kLam; ++l) lam_dl[l][k] = (float)(lb.lam[l] - lb.lam0[k]);
     }
+    extern __shared__ float sv[];
+    const int nper = 2 + 4 * lb.n_lines;
+    for (int i = threadIdx.x; i < g.bvox; i += blockDim.x) {
+        const int ix = i % B, iy = (i / B) % B, iz = D > 2 ? i / (B * B) : 0;
+        const long long v = (long long)(bc0 * B + ix) +
+                            (long long)g.n[0] * ((long long)(bc1 * B + iy) + (long long)g.n[1] * (bc2 * B + iz));
+        float* o = sv + i * nper;
+        o[0] = in.eta_bg[v];
+        o[1] = in.chi_bg[v];
+        for (int k = 0; k < lb.n_lines; ++k) {
+            const long long ok = (long long)k * in.nvox + v;
+            o[2 + 4 * k] = in.eta_star[ok];
+            o[3 + 4 * k] = in.chi_star[ok];
+            o[4 + 4 * k] = in.damp[ok];
+            o[5 + 4 * k] = in.inv_dld[ok];
+        }
+    }
+    __syncthreads();
     for (int item = threadIdx.x; item < total; item += blockDim.x) {
         // items ordered coarse level first so the long ones start early
         int rem = item, m = g.n_levels - 1;
@@ -208,24 +230,25 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
         const int nvx = D > 2 ? size * size * size : size * size;
         for (int q = 0; q < nvx; ++q) {
             int qx = q & (size - 1), qy = (q >> m) & (size - 1), qz = D > 2 ? q >> (2 * m) : 0;
-            long long v = (long long)(bc0 * B + cx * size + qx) +
-                          (long long)g.n[0] * ((long long)(bc1 * B + cy * size + qy) +
-                                               (long long)g.n[1] * (bc2 * B + cz * size + qz));
-            float eb = in.eta_bg[v], cb = in.chi_bg[v];
-            float es[kMaxLines], cs[kMaxLines], a0[kMaxLines], idl[kMaxLines];
-            for (int k = 0; k < lb.n_lines; ++k) {
-                long long o = (long long)k * in.nvox + v;
-                es[k] = in.eta_star[o];
-                cs[k] = in.chi_star[o];
-                a0[k] = in.damp[o];
-                idl[k] = in.inv_dld[o];
+            const float* pv = sv + ((cx * size + qx) + B * ((cy * size + qy) + B * (cz * size + qz))) * nper;
+            float eb = pv[0], cb = pv[1];
+            float es[NL], cs[NL], a0[NL], idl[NL];
+#pragma unroll
+            for (int k = 0; k < NL; ++k) {
+                const bool on = k < lb.n_lines;
+                es[k] = on ? pv[2 + 4 * k] : 0.f;
+                cs[k] = on ? pv[3 + 4 * k] : 0.f;
+                a0[k] = on ? pv[4 + 4 * k] : 0.f;
+                idl[k] = on ? pv[5 + 4 * k] : 0.f;
             }
 #pragma unroll
             for (int l = 0; l < kLam; ++l) {
                 float ee = eb, cc = cb;
-                for (int k = 0; k < lb.n_lines; ++k) {
+#pragma unroll
+                for (int k = 0; k < NL; ++k) {
+                    if (k >= lb.n_lines) break;
                     float x = fmaf(k0[k], uk, lam_dl[l][k]) * idl[k];
-                    float phi = line_shape(lb.profile, x, a0[k], lb.lam[l], lb.lam0[k], idl[k]);
+                    float phi = line_shape(PROF, x, a0[k], lb.lam[l], lb.lam0[k], idl[k]);
                     ee = fmaf(es[k], phi, ee);
                     cc = fmaf(cs[k], phi, cc);
                 }
@@ -269,18 +292,35 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
     }
 }
 
+template <int D, int PROF, int NL>
+static void launch_nodes_typed(dim3 grid, size_t shm, const Geo& g, const Inputs& in, const SceneBufs& b,
+                               const LamBatch& lb, int n_v, float ds0, int avg_mode, int storage, hipStream_t s)
+{
+    if (storage == RT_F32)
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, float, PROF, NL>), grid, dim3(256), shm, s, g, in, b, lb, n_v, ds0,
+                           avg_mode);
+    else if (storage == RT_BF16)
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, __hip_bfloat16, PROF, NL>), grid, dim3(256), shm, s, g, in, b, lb,
+                           n_v, ds0, avg_mode);
+    else
+        hipLaunchKernelGGL((k_velinterp_nodes2<D, __half, PROF, NL>), grid, dim3(256), shm, s, g, in, b, lb, n_v, ds0,
+                           avg_mode);
+}
+
 template <int D>
 static void launch_nodes_dim(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active, const LamBatch& lb,
                              int n_v, int n_vclass, float ds0, int avg_mode, int storage, hipStream_t s)
 {
     const dim3 grid(n_active, n_vclass);
-    if (storage == RT_F32)
-        hipLaunchKernelGGL((k_velinterp_nodes2<D, float>), grid, dim3(256), 0, s, g, in, b, lb, n_v, ds0, avg_mode);
-    else if (storage == RT_BF16)
-        hipLaunchKernelGGL((k_velinterp_nodes2<D, __hip_bfloat16>), grid, dim3(256), 0, s, g, in, b, lb, n_v, ds0,
-                           avg_mode);
-    else
-        hipLaunchKernelGGL((k_velinterp_nodes2<D, __half>), grid, dim3(256), 0, s, g, in, b, lb, n_v, ds0, avg_mode);
+    const size_t shm = sizeof(float) * (size_t)g.bvox * (size_t)(2 + 4 * lb.n_lines);  // <= 512 x 18 floats
+    const bool two = lb.n_lines <= 2;
+    if (lb.profile == RT_PROFILE_GAUSS) {
+        if (two) launch_nodes_typed<D, RT_PROFILE_GAUSS, 2>(grid, shm, g, in, b, lb, n_v, ds0, avg_mode, storage, s);
+        else launch_nodes_typed<D, RT_PROFILE_GAUSS, kMaxLines>(grid, shm, g, in, b, lb, n_v, ds0, avg_mode, storage, s);
+    } else {
+        if (two) launch_nodes_typed<D, RT_PROFILE_VOIGT, 2>(grid, shm, g, in, b, lb, n_v, ds0, avg_mode, storage, s);
+        else launch_nodes_typed<D, RT_PROFILE_VOIGT, kMaxLines>(grid, shm, g, in, b, lb, n_v, ds0, avg_mode, storage, s);
+    }
 }
 
 hipError_t launch_velinterp_nodes(const Geo& g, const Inputs& in, const SceneBufs& b, int n_active,
