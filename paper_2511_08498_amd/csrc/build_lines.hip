@@ -218,7 +218,9 @@ __global__ void __launch_bounds__(256) k_velinterp_nodes2(Geo g, Inputs in, Scen
             if (rem < nc * n_v) break;
             rem -= nc * n_v;
         }
-        const int cell = rem / n_v, kn = rem - cell * n_v;
+        // inside a level, cells fastest: the lanes of a wave write adjacent records of one node plane
+        const int ncm = g.lvl_off[m + 1] - g.lvl_off[m];
+        const int kn = rem / ncm, cell = rem - kn * ncm;
         const int side = B >> m, size = 1 << m;
         const int cx = cell % side, cy = (cell / side) % side, cz = D > 2 ? cell / (side * side) : 0;
         const long long rec = q_cls * ncell_all + (long long)slot * g.cells + g.lvl_off[m] + cell;
